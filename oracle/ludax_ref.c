@@ -1,0 +1,696 @@
+/*
+ * ludax_ref.c -- plain CPU oracle of the batched board-game step and the
+ * uniform-random playout (Ludax, arXiv 2506.22609).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU
+ * baseline of the benchmark, never by the GPU library.  It is deliberately
+ * slow: one env at a time, scalar loops over cells, full-board scans for
+ * every end rule.  No bitboards, no precomputed tables.
+ *
+ * What each part follows:
+ *   init          Sec. 3.1 (start rules); Reversi start squares, App. C.
+ *   legal         Sec. 3.2 (play mechanic defines a fixed-size legal mask);
+ *                 Sec. 3.4 (Connect Four as cell placement above a piece or
+ *                 the floor); App. C rule texts; force_pass in the App. B
+ *                 grammar.
+ *   step          Sec. 3.2 (mechanic, then effects such as Reversi's flip),
+ *                 Sec. 3.3 (end rules checked in order, wins before draws).
+ *   win rules     App. C: lines of 3 / 4 in Tic-Tac-Toe / Connect Four,
+ *                 exactly five in Gomoku, Hex edge-to-edge connection,
+ *                 Reversi disc count after both players pass.
+ *   playout       Sec. 6 (uniform-random action policy, full games).
+ *   Philox        Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
+ *                 Easy as 1, 2, 3", SC'11: Philox4x32 with 10 rounds.
+ */
+#include "ludax_ref.h"
+
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAX_CELLS 361
+#define MAX_ACTIONS (MAX_CELLS + 1)
+
+typedef struct {
+    int kind, H, W, cells, A, max_plies;
+} game_t;
+
+typedef struct {
+    int8_t board[MAX_CELLS];
+    int to_move, status, winner, passes, ply, last_action;
+} env_t;
+
+static volatile int g_checks = 0;
+static int64_t g_check_failures = 0;
+static pthread_mutex_t g_check_mu = PTHREAD_MUTEX_INITIALIZER;
+
+void ludax_ref_set_checks(int on) { g_checks = on; }
+int64_t ludax_ref_check_failures(void) { return g_check_failures; }
+
+static void check_failed(void)
+{
+    pthread_mutex_lock(&g_check_mu);
+    g_check_failures++;
+    pthread_mutex_unlock(&g_check_mu);
+}
+
+/* ------------------------------------------------------------------ */
+/* game descriptions                                                   */
+/* ------------------------------------------------------------------ */
+
+static int natural_bound(int kind, int cells)
+{
+    switch (kind) {
+    case LUDAX_REF_REVERSI:
+        /* 60 placements, at most 59 single passes between them, and the
+         * final two passes. */
+        return (cells - 4) + (cells - 4 - 1) + 2;
+    default:
+        return cells; /* one stone per ply, never removed */
+    }
+}
+
+static int resolve(const ludax_ref_desc *d, game_t *g)
+{
+    if (!d) return LUDAX_REF_E_INVALID;
+    int k = d->kind, H = d->rows, W = d->cols;
+    if (H <= 0 || W <= 0 || d->max_plies < 0 || d->max_plies > 32767) return LUDAX_REF_E_INVALID;
+    int ok = 0;
+    switch (k) {
+    case LUDAX_REF_TICTACTOE:    ok = (H == 3 && W == 3); break;
+    case LUDAX_REF_CONNECT_FOUR: ok = (H == 6 && W == 7); break;
+    case LUDAX_REF_HEX:          ok = (H == W && H >= 1 && H <= 19); break;
+    case LUDAX_REF_REVERSI:      ok = (H == 8 && W == 8); break;
+    case LUDAX_REF_GOMOKU:       ok = (H == W && H >= 5 && H <= 19); break;
+    default: return LUDAX_REF_E_UNSUPPORTED;
+    }
+    if (!ok) return LUDAX_REF_E_UNSUPPORTED;
+    g->kind = k;
+    g->H = H;
+    g->W = W;
+    g->cells = H * W;
+    g->A = g->cells + (k == LUDAX_REF_REVERSI ? 1 : 0);
+    g->max_plies = d->max_plies ? d->max_plies : natural_bound(k, g->cells);
+    return LUDAX_REF_OK;
+}
+
+int ludax_ref_info(const ludax_ref_desc *d, int32_t *cells, int32_t *num_actions,
+                   int32_t *max_plies)
+{
+    game_t g;
+    int rc = resolve(d, &g);
+    if (rc) return rc;
+    if (cells) *cells = g.cells;
+    if (num_actions) *num_actions = g.A;
+    if (max_plies) *max_plies = g.max_plies;
+    return LUDAX_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* state access                                                        */
+/* ------------------------------------------------------------------ */
+
+static int state_ok(const ludax_ref_state *s)
+{
+    return s && s->board && s->to_move && s->status && s->winner && s->passes && s->ply &&
+           s->last_action;
+}
+
+static void load_env(const game_t *g, const ludax_ref_state *s, int64_t i, env_t *e)
+{
+    memcpy(e->board, s->board + i * g->cells, (size_t)g->cells);
+    e->to_move = s->to_move[i];
+    e->status = s->status[i];
+    e->winner = s->winner[i];
+    e->passes = s->passes[i];
+    e->ply = s->ply[i];
+    e->last_action = s->last_action[i];
+}
+
+static void store_env(const game_t *g, ludax_ref_state *s, int64_t i, const env_t *e)
+{
+    memcpy(s->board + i * g->cells, e->board, (size_t)g->cells);
+    s->to_move[i] = (int8_t)e->to_move;
+    s->status[i] = (int8_t)e->status;
+    s->winner[i] = (int8_t)e->winner;
+    s->passes[i] = (int8_t)e->passes;
+    s->ply[i] = (int16_t)e->ply;
+    s->last_action[i] = (int16_t)e->last_action;
+}
+
+static int on_board(const game_t *g, int r, int c) { return r >= 0 && r < g->H && c >= 0 && c < g->W; }
+
+static int at(const game_t *g, const env_t *e, int r, int c) { return e->board[r * g->W + c]; }
+
+/* ------------------------------------------------------------------ */
+/* init                                                                */
+/* ------------------------------------------------------------------ */
+
+static void init_env(const game_t *g, env_t *e)
+{
+    memset(e->board, 0, sizeof e->board);
+    if (g->kind == LUDAX_REF_REVERSI) {
+        /* App. C: white on D4 and E5, black on D5 and E4.  Letters name
+         * columns left to right, digits name rows top to bottom.  Player 1
+         * is black and moves first. */
+        const int D = 3, E = 4, row4 = 3, row5 = 4;
+        e->board[row4 * 8 + D] = 2; /* D4 white */
+        e->board[row5 * 8 + E] = 2; /* E5 white */
+        e->board[row5 * 8 + D] = 1; /* D5 black */
+        e->board[row4 * 8 + E] = 1; /* E4 black */
+    }
+    e->to_move = 1;
+    e->status = LUDAX_REF_RUNNING;
+    e->winner = -1;
+    e->passes = 0;
+    e->ply = 0;
+    e->last_action = -1;
+}
+
+int ludax_ref_init(const ludax_ref_desc *d, ludax_ref_state *s, int64_t n)
+{
+    game_t g;
+    int rc = resolve(d, &g);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && !state_ok(s))) return LUDAX_REF_E_INVALID;
+    env_t e;
+    for (int64_t i = 0; i < n; i++) {
+        init_env(&g, &e);
+        store_env(&g, s, i, &e);
+    }
+    return LUDAX_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* legal actions                                                       */
+/* ------------------------------------------------------------------ */
+
+static const int DIR8[8][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
+
+/* Number of opponent stones that a stone of `me` placed at (r, c) would
+ * sandwich along direction (dr, dc): walk over the opponent's stones; the
+ * first cell that is not the opponent's must be on the board and ours. */
+static int flank_len(const game_t *g, const env_t *e, int r, int c, int dr, int dc, int me)
+{
+    int opp = 3 - me, k = 0;
+    int rr = r + dr, cc = c + dc;
+    while (on_board(g, rr, cc) && at(g, e, rr, cc) == opp) {
+        k++;
+        rr += dr;
+        cc += dc;
+    }
+    if (k > 0 && on_board(g, rr, cc) && at(g, e, rr, cc) == me) return k;
+    return 0;
+}
+
+static int reversi_placement_legal(const game_t *g, const env_t *e, int r, int c, int me)
+{
+    if (at(g, e, r, c) != 0) return 0;
+    for (int d = 0; d < 8; d++)
+        if (flank_len(g, e, r, c, DIR8[d][0], DIR8[d][1], me)) return 1;
+    return 0;
+}
+
+static void legal(const game_t *g, const env_t *e, uint8_t *m)
+{
+    memset(m, 0, (size_t)g->A);
+    if (e->status != LUDAX_REF_RUNNING) return;
+    int me = e->to_move;
+    switch (g->kind) {
+    case LUDAX_REF_TICTACTOE:
+    case LUDAX_REF_HEX:
+    case LUDAX_REF_GOMOKU:
+        for (int i = 0; i < g->cells; i++) m[i] = (e->board[i] == 0);
+        break;
+    case LUDAX_REF_CONNECT_FOUR:
+        /* an empty cell resting on the floor (bottom row) or on a piece */
+        for (int r = 0; r < g->H; r++)
+            for (int c = 0; c < g->W; c++)
+                m[r * g->W + c] = at(g, e, r, c) == 0 && (r == g->H - 1 || at(g, e, r + 1, c) != 0);
+        break;
+    case LUDAX_REF_REVERSI: {
+        int any = 0;
+        for (int r = 0; r < g->H; r++)
+            for (int c = 0; c < g->W; c++) {
+                int ok = reversi_placement_legal(g, e, r, c, me);
+                m[r * g->W + c] = (uint8_t)ok;
+                any |= ok;
+            }
+        m[g->cells] = (uint8_t)!any; /* forced pass, and only then */
+        break;
+    }
+    }
+}
+
+int ludax_ref_legal_mask(const ludax_ref_desc *d, const ludax_ref_state *s, uint8_t *mask,
+                         int64_t n)
+{
+    game_t g;
+    int rc = resolve(d, &g);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!state_ok(s) || !mask))) return LUDAX_REF_E_INVALID;
+    env_t e;
+    for (int64_t i = 0; i < n; i++) {
+        load_env(&g, s, i, &e);
+        legal(&g, &e, mask + i * g.A);
+    }
+    return LUDAX_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* end rules                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Does `who` own a maximal straight run whose length satisfies the rule
+ * (length >= len, or exactly len)?  Full-board scan over the four line
+ * orientations; a run is visited from its first cell only. */
+static int has_line(const game_t *g, const env_t *e, int who, int len, int exact)
+{
+    static const int DIR4[4][2] = {{0, 1}, {1, 0}, {1, 1}, {1, -1}};
+    for (int r = 0; r < g->H; r++)
+        for (int c = 0; c < g->W; c++) {
+            if (at(g, e, r, c) != who) continue;
+            for (int d = 0; d < 4; d++) {
+                int dr = DIR4[d][0], dc = DIR4[d][1];
+                int pr = r - dr, pc = c - dc;
+                if (on_board(g, pr, pc) && at(g, e, pr, pc) == who) continue; /* not a run start */
+                int L = 0, rr = r, cc = c;
+                while (on_board(g, rr, cc) && at(g, e, rr, cc) == who) {
+                    L++;
+                    rr += dr;
+                    cc += dc;
+                }
+                if (exact ? (L == len) : (L >= len)) return 1;
+            }
+        }
+    return 0;
+}
+
+/* Hex (App. C): a parallelogram of hexagons.  Neighbours of (r, c) are
+ * (r-1,c) (r-1,c+1) (r,c-1) (r,c+1) (r+1,c-1) (r+1,c).  Player 1 joins the
+ * top row to the bottom row, player 2 the left column to the right column.
+ * Breadth-first search from every stone of `who` on its first side. */
+static int hex_connected(const game_t *g, const env_t *e, int who)
+{
+    static const int NB[6][2] = {{-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}};
+    int N = g->H;
+    uint8_t seen[MAX_CELLS];
+    int queue[MAX_CELLS], qh = 0, qt = 0;
+    memset(seen, 0, sizeof seen);
+    for (int k = 0; k < N; k++) {
+        int r = (who == 1) ? 0 : k, c = (who == 1) ? k : 0;
+        int i = r * N + c;
+        if (e->board[i] == who && !seen[i]) {
+            seen[i] = 1;
+            queue[qt++] = i;
+        }
+    }
+    while (qh < qt) {
+        int i = queue[qh++];
+        int r = i / N, c = i % N;
+        if ((who == 1 && r == N - 1) || (who == 2 && c == N - 1)) return 1;
+        for (int d = 0; d < 6; d++) {
+            int rr = r + NB[d][0], cc = c + NB[d][1];
+            if (!on_board(g, rr, cc)) continue;
+            int j = rr * N + cc;
+            if (e->board[j] == who && !seen[j]) {
+                seen[j] = 1;
+                queue[qt++] = j;
+            }
+        }
+    }
+    return 0;
+}
+
+static int board_full(const game_t *g, const env_t *e)
+{
+    for (int i = 0; i < g->cells; i++)
+        if (e->board[i] == 0) return 0;
+    return 1;
+}
+
+/* The mover's end rules, in the order the game lists them (Sec. 3.3).
+ * Returns -1 if the game goes on, else the winner (0 = draw). */
+static int end_rules(const game_t *g, const env_t *e, int me)
+{
+    switch (g->kind) {
+    case LUDAX_REF_TICTACTOE:
+        if (has_line(g, e, me, 3, 0)) return me;
+        if (board_full(g, e)) return 0;
+        return -1;
+    case LUDAX_REF_CONNECT_FOUR:
+        if (has_line(g, e, me, 4, 0)) return me;
+        if (board_full(g, e)) return 0;
+        return -1;
+    case LUDAX_REF_GOMOKU:
+        if (has_line(g, e, me, 5, 1)) return me;
+        if (board_full(g, e)) return 0;
+        return -1;
+    case LUDAX_REF_HEX:
+        if (hex_connected(g, e, me)) return me;
+        return -1;
+    case LUDAX_REF_REVERSI:
+        if (e->passes >= 2) {
+            int n1 = 0, n2 = 0;
+            for (int i = 0; i < g->cells; i++) {
+                n1 += e->board[i] == 1;
+                n2 += e->board[i] == 2;
+            }
+            return n1 > n2 ? 1 : (n2 > n1 ? 2 : 0);
+        }
+        return -1;
+    }
+    return -1;
+}
+
+/* Consistency: the opponent of the mover can never hold a win after the
+ * mover's ply (no captures in the line and connection games). */
+static void check_opponent(const game_t *g, const env_t *e, int me)
+{
+    int opp = 3 - me;
+    int bad = 0;
+    switch (g->kind) {
+    case LUDAX_REF_TICTACTOE: bad = has_line(g, e, opp, 3, 0); break;
+    case LUDAX_REF_CONNECT_FOUR: bad = has_line(g, e, opp, 4, 0); break;
+    case LUDAX_REF_GOMOKU: bad = has_line(g, e, opp, 5, 1); break;
+    case LUDAX_REF_HEX: bad = hex_connected(g, e, opp); break;
+    default: break;
+    }
+    if (bad) check_failed();
+}
+
+int ludax_ref_holds_win(const ludax_ref_desc *d, const int8_t *board, int who)
+{
+    game_t g;
+    if (resolve(d, &g) || !board || (who != 1 && who != 2)) return -1;
+    env_t e;
+    memcpy(e.board, board, (size_t)g.cells);
+    switch (g.kind) {
+    case LUDAX_REF_TICTACTOE: return has_line(&g, &e, who, 3, 0);
+    case LUDAX_REF_CONNECT_FOUR: return has_line(&g, &e, who, 4, 0);
+    case LUDAX_REF_GOMOKU: return has_line(&g, &e, who, 5, 1);
+    case LUDAX_REF_HEX: return hex_connected(&g, &e, who);
+    default: return -1;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* step                                                                */
+/* ------------------------------------------------------------------ */
+
+static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_t *term)
+{
+    rew[0] = rew[1] = 0;
+    if (e->status != LUDAX_REF_RUNNING) { /* stepping an ended env: no-op */
+        *term = 1;
+        return;
+    }
+    uint8_t m[MAX_ACTIONS];
+    legal(g, e, m);
+    if (a < 0 || a >= g->A || !m[a]) { /* illegal: flag it, change nothing else */
+        e->status = LUDAX_REF_ILLEGAL;
+        *term = 1;
+        return;
+    }
+    int me = e->to_move;
+    if (g->kind == LUDAX_REF_REVERSI && a == g->cells) {
+        e->passes += 1;
+    } else {
+        int r = a / g->W, c = a % g->W;
+        if (g->kind == LUDAX_REF_REVERSI) {
+            /* find every sandwiched line first, then flip them all */
+            int len[8];
+            for (int d = 0; d < 8; d++) len[d] = flank_len(g, e, r, c, DIR8[d][0], DIR8[d][1], me);
+            for (int d = 0; d < 8; d++)
+                for (int k = 1; k <= len[d]; k++)
+                    e->board[(r + k * DIR8[d][0]) * g->W + (c + k * DIR8[d][1])] = (int8_t)me;
+            e->passes = 0;
+        }
+        e->board[a] = (int8_t)me;
+    }
+    e->ply += 1;
+    e->last_action = a;
+
+    int w = end_rules(g, e, me);
+    if (g_checks) check_opponent(g, e, me);
+    if (w >= 0) {
+        e->status = LUDAX_REF_TERMINAL;
+        e->winner = w;
+        if (w == 1) { rew[0] = 1; rew[1] = -1; }
+        if (w == 2) { rew[0] = -1; rew[1] = 1; }
+    } else {
+        e->to_move = 3 - me;
+        if (e->ply >= g->max_plies) {
+            e->status = LUDAX_REF_TRUNCATED;
+            e->winner = -1;
+        }
+    }
+    *term = (uint8_t)(e->status != LUDAX_REF_RUNNING);
+}
+
+int ludax_ref_step(const ludax_ref_desc *d, ludax_ref_state *s, const int32_t *action,
+                   int8_t *reward, uint8_t *terminal, uint8_t *next_mask, int64_t n)
+{
+    game_t g;
+    int rc = resolve(d, &g);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!state_ok(s) || !action || !reward || !terminal)))
+        return LUDAX_REF_E_INVALID;
+    env_t e;
+    for (int64_t i = 0; i < n; i++) {
+        load_env(&g, s, i, &e);
+        step_env(&g, &e, action[i], reward + 2 * i, terminal + i);
+        store_env(&g, s, i, &e);
+        if (next_mask) legal(&g, &e, next_mask + i * g.A);
+    }
+    return LUDAX_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 and the playout                                       */
+/* ------------------------------------------------------------------ */
+
+void ludax_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    /* Salmon et al. SC'11: each round multiplies counter words 0 and 2 by
+     * the two Philox multipliers, and the new counter is
+     * (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0));
+     * between rounds the key is bumped by the two Weyl constants. */
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+uint32_t ludax_ref_draw(uint64_t seed, int64_t game_id, int32_t ply)
+{
+    /* counter = (ply / 4, low and high words of the game id, 0),
+     * key = (low and high words of the seed); word ply % 4 of the block. */
+    uint64_t gid = (uint64_t)game_id;
+    uint32_t ctr[4] = {(uint32_t)ply >> 2, (uint32_t)gid, (uint32_t)(gid >> 32), 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    ludax_ref_philox4x32_10(ctr, key, out);
+    return out[(uint32_t)ply & 3u];
+}
+
+typedef struct {
+    int64_t steps, w1, w2, draws;
+} tally_t;
+
+static void playout_env(const game_t *g, env_t *e, uint64_t seed, int64_t gid, int8_t rew[2],
+                        uint8_t *term, tally_t *t)
+{
+    rew[0] = rew[1] = 0;
+    uint8_t m[MAX_ACTIONS];
+    while (e->status == LUDAX_REF_RUNNING) {
+        legal(g, e, m);
+        int nlegal = 0;
+        for (int a = 0; a < g->A; a++) nlegal += m[a];
+        if (nlegal == 0) { /* only on a hand-made, unreachable state */
+            e->status = LUDAX_REF_ILLEGAL;
+            break;
+        }
+        /* uniform choice among the legal actions: multiply-shift of one
+         * 32-bit Philox word, then the k-th legal action in index order */
+        uint32_t w = ludax_ref_draw(seed, gid, e->ply);
+        int k = (int)(((uint64_t)w * (uint64_t)nlegal) >> 32);
+        int a = -1;
+        for (int i = 0; i < g->A; i++)
+            if (m[i]) {
+                if (k == 0) {
+                    a = i;
+                    break;
+                }
+                k--;
+            }
+        uint8_t tt;
+        step_env(g, e, a, rew, &tt);
+        t->steps++;
+    }
+    *term = 1;
+    if (e->status == LUDAX_REF_TERMINAL) {
+        if (e->winner == 1) t->w1++;
+        else if (e->winner == 2) t->w2++;
+        else if (e->winner == 0) t->draws++;
+    }
+}
+
+typedef struct {
+    const game_t *g;
+    ludax_ref_state *s;
+    uint64_t seed;
+    int64_t base;
+    const int64_t *gid;
+    int8_t *reward;
+    uint8_t *terminal;
+    int64_t lo, hi;
+    tally_t t;
+} job_t;
+
+static void *playout_range(void *arg)
+{
+    job_t *j = (job_t *)arg;
+    env_t e;
+    memset(&j->t, 0, sizeof j->t);
+    for (int64_t i = j->lo; i < j->hi; i++) {
+        load_env(j->g, j->s, i, &e);
+        int was_running = e.status == LUDAX_REF_RUNNING;
+        int64_t gid = j->gid ? j->gid[i] : j->base + i;
+        tally_t t = {0, 0, 0, 0};
+        playout_env(j->g, &e, j->seed, gid, j->reward + 2 * i, j->terminal + i, &t);
+        /* outcomes are counted only for games that ended inside this call */
+        if (!was_running) t.w1 = t.w2 = t.draws = 0;
+        j->t.steps += t.steps;
+        j->t.w1 += t.w1;
+        j->t.w2 += t.w2;
+        j->t.draws += t.draws;
+        store_env(j->g, j->s, i, &e);
+    }
+    return NULL;
+}
+
+int ludax_ref_playout(const ludax_ref_desc *d, ludax_ref_state *s, uint64_t seed,
+                      int64_t game_id_base, const int64_t *game_id, int8_t *reward,
+                      uint8_t *terminal, int64_t *stats, int64_t n, int threads)
+{
+    game_t g;
+    int rc = resolve(d, &g);
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!state_ok(s) || !reward || !terminal))) return LUDAX_REF_E_INVALID;
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if (threads > n) threads = (int)(n > 0 ? n : 1);
+    job_t jobs[256];
+    pthread_t tid[256];
+    for (int k = 0; k < threads; k++) {
+        jobs[k].g = &g;
+        jobs[k].s = s;
+        jobs[k].seed = seed;
+        jobs[k].base = game_id_base;
+        jobs[k].gid = game_id;
+        jobs[k].reward = reward;
+        jobs[k].terminal = terminal;
+        jobs[k].lo = n * k / threads;
+        jobs[k].hi = n * (k + 1) / threads;
+    }
+    if (threads == 1) {
+        playout_range(&jobs[0]);
+    } else {
+        for (int k = 0; k < threads; k++) pthread_create(&tid[k], NULL, playout_range, &jobs[k]);
+        for (int k = 0; k < threads; k++) pthread_join(tid[k], NULL);
+    }
+    if (stats)
+        for (int k = 0; k < threads; k++) {
+            stats[0] += jobs[k].t.steps;
+            stats[1] += jobs[k].t.w1;
+            stats[2] += jobs[k].t.w2;
+            stats[3] += jobs[k].t.draws;
+        }
+    return LUDAX_REF_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* enumeration helpers                                                 */
+/* ------------------------------------------------------------------ */
+
+static int64_t perft_rec(const game_t *g, const env_t *e, int depth)
+{
+    if (depth == 0) return 1;
+    if (e->status != LUDAX_REF_RUNNING) return 0;
+    uint8_t m[MAX_ACTIONS];
+    legal(g, e, m);
+    int64_t total = 0;
+    for (int a = 0; a < g->A; a++) {
+        if (!m[a]) continue;
+        env_t c = *e;
+        int8_t rew[2];
+        uint8_t t;
+        step_env(g, &c, a, rew, &t);
+        total += perft_rec(g, &c, depth - 1);
+    }
+    return total;
+}
+
+int64_t ludax_ref_perft(const ludax_ref_desc *d, const ludax_ref_state *s, int depth)
+{
+    game_t g;
+    if (resolve(d, &g) || !state_ok(s) || depth < 0) return -1;
+    env_t e;
+    load_env(&g, s, 0, &e);
+    return perft_rec(&g, &e, depth);
+}
+
+static int64_t games_rec(const game_t *g, const env_t *e, int64_t *tab, int max_len,
+                         int64_t *trunc)
+{
+    if (e->status != LUDAX_REF_RUNNING) {
+        if (e->status == LUDAX_REF_TERMINAL && e->ply <= max_len && e->winner >= 0)
+            tab[e->ply * 3 + e->winner]++;
+        else if (trunc)
+            (*trunc)++;
+        return 1;
+    }
+    uint8_t m[MAX_ACTIONS];
+    legal(g, e, m);
+    int64_t total = 0;
+    for (int a = 0; a < g->A; a++) {
+        if (!m[a]) continue;
+        env_t c = *e;
+        int8_t rew[2];
+        uint8_t t;
+        step_env(g, &c, a, rew, &t);
+        total += games_rec(g, &c, tab, max_len, trunc);
+    }
+    return total;
+}
+
+int64_t ludax_ref_count_games(const ludax_ref_desc *d, const ludax_ref_state *s,
+                              int64_t *by_len_winner, int max_len, int64_t *truncated)
+{
+    game_t g;
+    if (resolve(d, &g) || !state_ok(s) || !by_len_winner || max_len < 0) return -1;
+    env_t e;
+    load_env(&g, s, 0, &e);
+    return games_rec(&g, &e, by_len_winner, max_len, truncated);
+}
