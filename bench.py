@@ -1,0 +1,162 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched random-playout hot path on one MI355X.
+
+Workload: single-game batches of 65536 environments each, Connect Four 6x7
+and Hex 11x11 (int8 boards), uniform-random playouts from the start
+position to the end of every game.  One benchmark step = for each batch:
+ludax_init (start positions) + ludax_playout (legal mask, Philox draw,
+k-th legal action, apply, end rules, repeated until every game has ended,
+plus the step/outcome counters).  Every step uses fresh game ids, so no
+two steps play the same games.
+
+Prints one JSON line: env-steps/s over the timed steps (all plies applied
+by all environments / wall time between two device synchronisations), the
+roofline figures of the dominant kernel (the Hex playout kernel, timed
+with events on its own stream) and the CPU oracle's rate on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Integer VALU work per env-step of the playout kernels (lane operations),
+# from the static instruction count of one pass of the playout loop body
+# along the path every ply takes; see the roofline section of the design
+# notes for the derivation.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 164, "hex11x11_n65536": 186}
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T lane-ops/s
+
+
+def _cpu_baseline(batches, budget_s: float):
+    """The oracle as it stands, on the host's cores, over whole batches of
+    the same workload until about budget_s seconds have elapsed."""
+    from oracle import ref
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 64))
+    steps, t0, reps = 0, time.perf_counter(), 0
+    while True:
+        for b in batches:
+            g = ref.Game(b.kind, b.rows, b.cols)
+            s = ref.init(g, b.n)
+            _, _, st = ref.playout(g, s, 1, b.n * (1000 + reps), threads=cores)
+            steps += int(st[0])
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 50:
+            break
+    return {"value": steps / el, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} x ({' + '.join(b.name for b in batches)}), full batches, "
+                      f"{steps} env-steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall-time budget of the CPU oracle baseline (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the playouts are independent per game; "
+              f"--gpus {args.gpus} is not supported by this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    batches = W.BENCH_BATCHES
+    dominant = W.HEX11_65536.name
+    games = [ludax.Game(b.kind, b.rows, b.cols) for b in batches]
+    states = [ludax.State(g, b.n) for g, b in zip(games, batches)]
+    rewards = [torch.empty((b.n, 2), dtype=torch.int8, device="cuda") for b in batches]
+    terms = [torch.empty(b.n, dtype=torch.uint8, device="cuda") for b in batches]
+    stats = [torch.zeros(4, dtype=torch.int64, device="cuda") for _ in batches]
+    stream = torch.cuda.current_stream()
+    ev = {b.name: [] for b in batches}
+
+    def one_step(k: int, record: bool):
+        for b, g, s, r, t, st in zip(batches, games, states, rewards, terms, stats):
+            ludax.init(g, s, stream=stream)
+            if record:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            ludax.playout(g, s, args.seed, W.game_id_base(k, b), reward=r, terminal=t, stats=st,
+                          stream=stream)
+            if record:
+                e1.record(stream)
+                ev[b.name].append((e0, e1))
+
+    for k in range(args.warmup):
+        one_step(k, False)
+    torch.cuda.synchronize()
+    for st in stats:
+        st.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        one_step(k, True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    per = {}
+    total_steps = 0
+    for b, st in zip(batches, stats):
+        v = st.cpu().tolist()
+        kern_ms = sum(a.elapsed_time(c) for a, c in ev[b.name]) / args.steps
+        per[b.name] = {"env_steps": v[0], "p1_wins": v[1], "p2_wins": v[2], "draws": v[3],
+                       "playout_kernel_ms": kern_ms,
+                       "env_steps_per_s_kernel": v[0] / args.steps / (kern_ms / 1e3)}
+        total_steps += v[0]
+    value = total_steps / elapsed
+
+    d = per[dominant]
+    steps_per_launch = d["env_steps"] / args.steps
+    ops = VALU_OPS_PER_STEP[dominant] * steps_per_launch
+    achieved = ops / (d["playout_kernel_ms"] / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                "kernel": f"k_playout<Hex<11>> ({dominant})",
+                "ops_per_env_step": VALU_OPS_PER_STEP[dominant],
+                "env_steps_per_launch": steps_per_launch}
+
+    out = {
+        "metric": "env-steps/s (plain random playouts, single-game batches)",
+        "value": value,
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8",
+        "data": "synthetic (start positions + Philox4x32-10 seeded uniform-random play)",
+        "config": {"workload": " + ".join(b.name for b in batches),
+                   "envs_per_batch": batches[0].n, "seed": args.seed, "per_game": per},
+        "roofline": roofline,
+    }
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = _cpu_baseline(batches, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

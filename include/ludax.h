@@ -1,0 +1,176 @@
+/*
+ * ludax.h -- C ABI of the MI355X batched board-game engine.
+ *
+ * The library runs the data-parallel hot path of Ludax (Todd et al.,
+ * "Ludax: A GPU-Accelerated Description Language for Board Games",
+ * arXiv 2506.22609) as hand-written HIP kernels for gfx950: the start
+ * position, the legal-action mask, the transition (placement, Connect Four's
+ * gravity placement, Reversi's flanking flips and forced pass), the ordered
+ * end rules (n-in-a-row, exactly five, Hex edge-to-edge connection, disc
+ * count) and the uniform-random playout loop built on them, for many
+ * environments at once.
+ *
+ * Games and sizes (App. C rule texts):
+ *   LUDAX_TICTACTOE    3x3, a line of three wins, full board draws
+ *   LUDAX_CONNECT_FOUR 6x7, placement on the floor or on a piece (Sec. 3.4),
+ *                      a line of four or more wins, full board draws
+ *   LUDAX_HEX          NxN, 1 <= N <= 19, parallelogram of hexagons, player 1
+ *                      joins the top and bottom rows, player 2 the left and
+ *                      right columns; no draws, no swap rule
+ *   LUDAX_REVERSI      8x8, standard four-disc start, placements must flank,
+ *                      all flanked lines flip, forced pass, the game ends when
+ *                      both players pass in a row, most discs wins
+ *   LUDAX_GOMOKU       NxN, 5 <= N <= 19, a line of exactly five wins, full
+ *                      board draws
+ * Anything else is LUDAX_E_UNSUPPORTED.
+ *
+ * Board and action conventions:
+ *   cell (r, c) has index r*cols + c, r = 0 the top row, c = 0 the left
+ *   column; a cell holds 0 (empty), 1 (player 1) or 2 (player 2).
+ *   The action space is the set of cells (Sec. 3.4: its size depends only
+ *   on the board and the play mechanic), plus one PASS action at index
+ *   rows*cols for Reversi.  Player 1 moves first; movers alternate; a pass
+ *   is a ply.  Reversi: player 1 is black; discs start on D5, E4 (player 1)
+ *   and D4, E5 (player 2) with letters naming columns left to right and
+ *   digits rows top to bottom.
+ *
+ * Memory and streams: every buffer is caller-owned DEVICE memory; the
+ * library never allocates, frees or synchronises inside ludax_init,
+ * ludax_legal_mask, ludax_step or ludax_playout.  Work is enqueued on the
+ * given stream and runs asynchronously; results are valid once the stream
+ * has reached that point.  A game handle is immutable after creation and
+ * may be used from several streams and threads at once.
+ *
+ * Errors: every call returns LUDAX_OK or a negative code.  Argument errors
+ * are found on the host before anything is enqueued.  n = 0 is a no-op that
+ * succeeds whatever the buffer pointers are (the game handle must be
+ * valid).  Per-environment conditions (an illegal action, stepping an ended
+ * environment) are found on the device and reported as data in the state,
+ * never as return codes.
+ */
+#ifndef LUDAX_H
+#define LUDAX_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* game kinds */
+#define LUDAX_TICTACTOE    1
+#define LUDAX_CONNECT_FOUR 2
+#define LUDAX_HEX          3
+#define LUDAX_REVERSI      4
+#define LUDAX_GOMOKU       5
+
+/* per-environment status values (ludax_state.status) */
+#define LUDAX_RUNNING   0 /* the game goes on */
+#define LUDAX_TERMINAL  1 /* an end rule fired; winner is 0 (draw), 1 or 2 */
+#define LUDAX_TRUNCATED 2 /* max_plies reached without an end rule; winner -1 */
+#define LUDAX_ILLEGAL   3 /* an action outside the legal mask was applied */
+
+/* return codes */
+#define LUDAX_OK             0
+#define LUDAX_E_INVALID     -1 /* NULL required pointer, n < 0, misaligned board, bad desc */
+#define LUDAX_E_UNSUPPORTED -2 /* unknown kind or unsupported board size */
+#define LUDAX_E_DEVICE      -3 /* a HIP launch failed; see ludax_last_device_error() */
+
+typedef struct ludax_game ludax_game; /* opaque, immutable after create */
+
+/* Static description of a game (Sec. 4: every shape is fixed when the
+ * game is built). */
+typedef struct {
+    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_GOMOKU */
+    int32_t rows;
+    int32_t cols;
+    int32_t max_plies; /* 0 = the natural bound: cells (Reversi: 121); at most 32767 */
+} ludax_game_desc;
+
+/* Structure-of-arrays batch state for n environments (Sec. 4, dynamic
+ * state attributes: only the fields these games need).  All pointers are
+ * device memory owned by the caller.  board must be 16-byte aligned.
+ * States are expected to be reachable from ludax_init by steps and
+ * playouts; on hand-edited boards results are defined only as "no memory
+ * access outside the buffers" (see ludax_playout for the one safeguard). */
+typedef struct {
+    int8_t  *board;       /* [n][rows*cols], 0 empty, 1, 2 */
+    int8_t  *to_move;     /* [n] player to move, 1 or 2 */
+    int8_t  *status;      /* [n] LUDAX_RUNNING ... LUDAX_ILLEGAL */
+    int8_t  *winner;      /* [n] -1 none, 0 draw, 1, 2 */
+    int8_t  *passes;      /* [n] consecutive passes (Reversi; 0 otherwise) */
+    int16_t *ply;         /* [n] plies applied since the start */
+    int16_t *last_action; /* [n] last applied action, -1 before the first */
+    void    *aux;         /* reserved; may be NULL (no game needs it: aux_bytes = 0) */
+} ludax_state;
+
+/* Build a game handle.  Host only, no device work.  *out is set on
+ * success; release it with ludax_game_destroy. */
+int ludax_game_create(const ludax_game_desc *desc, ludax_game **out);
+int ludax_game_destroy(ludax_game *game);
+
+/* Shapes of a game: cells = rows*cols, num_actions = A, aux_bytes per env
+ * (always 0 here), max_plies after resolving 0 to the natural bound.  Any
+ * output pointer may be NULL. */
+int ludax_game_info(const ludax_game *game, int32_t *cells, int32_t *num_actions,
+                    int32_t *aux_bytes, int32_t *max_plies);
+
+/* Start position (Sec. 3.1 start rules) for all n environments: empty
+ * board (Reversi: the four start discs), to_move 1, RUNNING, winner -1,
+ * passes 0, ply 0, last_action -1. */
+int ludax_init(const ludax_game *game, ludax_state *state, int64_t n, hipStream_t stream);
+
+/* Legal-action mask (Sec. 3.2: each play mechanic defines one of fixed
+ * size).  mask: [n][A] uint8, 1 = legal.  An environment that is not
+ * RUNNING has an all-zero row; a RUNNING one always has at least one legal
+ * action (Reversi: PASS is legal exactly when no placement is). */
+int ludax_legal_mask(const ludax_game *game, const ludax_state *state, uint8_t *mask, int64_t n,
+                     hipStream_t stream);
+
+/* One transition per environment (Sec. 3.2 mechanic then effects, Sec. 3.3
+ * end rules checked in order, wins before draws):
+ *   - env not RUNNING: no change; reward 0/0; terminal 1.
+ *   - action outside [0, A) or not legal: status = ILLEGAL, nothing else
+ *     changes; reward 0/0; terminal 1.
+ *   - else the action is applied, ply += 1, last_action = action, and the
+ *     mover's end rules are checked.  A win gives reward +1 to the winner
+ *     and -1 to the loser, a draw 0/0; to_move stays the mover.  Otherwise
+ *     to_move passes to the other player and, if ply reaches max_plies,
+ *     status = TRUNCATED (reward 0/0).
+ * action: [n] int32; reward: [n][2] int8 (player 1, player 2); terminal:
+ * [n] uint8 = (status != RUNNING) after the step; next_mask: [n][A] uint8
+ * legal mask of the new state, or NULL. */
+int ludax_step(const ludax_game *game, ludax_state *state, const int32_t *action, int8_t *reward,
+               uint8_t *terminal, uint8_t *next_mask, int64_t n, hipStream_t stream);
+
+/* Uniform-random playout of every RUNNING environment to its end (Sec. 6:
+ * a uniformly random legal action each ply).  At each ply with legal mask
+ * m and n_legal = popcount(m):
+ *   w = word (ply mod 4) of Philox4x32-10(counter = (ply / 4, low and high
+ *       32 bits of the game id, 0), key = (low and high 32 bits of seed)),
+ *   k = (w * n_legal) >> 32 (64-bit product),
+ *   action = the k-th (from 0) legal action in increasing index order,
+ * then the ply is applied as in ludax_step.  The game id of env i is
+ * game_id[i], or game_id_base + i if game_id is NULL; so a game's moves
+ * depend only on (seed, game id, ply), not on its slot or the batch.
+ * reward [n][2]: the rewards of the ply that ended the game inside this
+ * call (0/0 for envs that were not RUNNING at the call).  terminal [n]: 1.
+ * stats [4] int64 or NULL is ADDED to (the caller zeroes it):
+ *   {plies applied, player-1 wins, player-2 wins, draws} over games that
+ *   ended inside this call.  A RUNNING env with no legal action (only
+ *   possible on a hand-edited board) is set ILLEGAL and stops. */
+int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed,
+                  int64_t game_id_base, const int64_t *game_id, int8_t *reward,
+                  uint8_t *terminal, int64_t *stats, int64_t n, hipStream_t stream);
+
+/* Text of a return code; never NULL. */
+const char *ludax_strerror(int code);
+
+/* Text of the last HIP error seen by a call on this thread ("" if none). */
+const char *ludax_last_device_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LUDAX_H */

@@ -1,0 +1,308 @@
+// bitboard.hpp -- device primitives for env-per-lane board games on gfx950.
+//
+// A board of up to 19x19 cells is a multiword bitboard of 32-bit words held
+// in VGPRs (one environment per lane).  Shifts by compile-time amounts become
+// v_alignbit_b32 funnel shifts; masks are compile-time immediates expanded
+// word by word with static_for, so no table is read from memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+
+namespace lx {
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// Word `word` of the mask whose bit b (0 <= b < nbits) is set iff pred(b).
+template <class P>
+constexpr uint32_t mask_word(P pred, int nbits, int word)
+{
+    uint32_t m = 0;
+    for (int j = 0; j < 32; ++j) {
+        const int b = 32 * word + j;
+        if (b < nbits && pred(b)) m |= 1u << j;
+    }
+    return m;
+}
+
+template <int NW>
+struct BB {
+    uint32_t w[NW];
+};
+
+template <int NW>
+__device__ __forceinline__ BB<NW> bb_zero()
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = 0u;
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ BB<NW> operator|(const BB<NW> &a, const BB<NW> &b)
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = a.w[i] | b.w[i];
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ BB<NW> operator&(const BB<NW> &a, const BB<NW> &b)
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = a.w[i] & b.w[i];
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ BB<NW> andnot(const BB<NW> &a, const BB<NW> &b) // a & ~b
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = a.w[i] & ~b.w[i];
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ BB<NW> operator~(const BB<NW> &a)
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = ~a.w[i];
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ bool any(const BB<NW> &a)
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) o |= a.w[i];
+    return o != 0u;
+}
+
+template <int NW>
+__device__ __forceinline__ bool same(const BB<NW> &a, const BB<NW> &b)
+{
+    uint32_t o = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) o |= a.w[i] ^ b.w[i];
+    return o == 0u;
+}
+
+template <int NW>
+__device__ __forceinline__ int popcount(const BB<NW> &a)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) c += __popc(a.w[i]);
+    return c;
+}
+
+// a & M, a & ~M and M itself, where M = {b < NBITS : P{}(b)} for a
+// default-constructible constexpr predicate type P.
+template <class P, int NBITS, int NW>
+__device__ __forceinline__ BB<NW> and_mask(const BB<NW> &a)
+{
+    BB<NW> r;
+    static_for<NW>([&](auto I) {
+        constexpr int i = I;
+        constexpr uint32_t m = mask_word(P{}, NBITS, i);
+        r.w[i] = a.w[i] & m;
+    });
+    return r;
+}
+
+template <class P, int NBITS, int NW>
+__device__ __forceinline__ BB<NW> andnot_mask(const BB<NW> &a)
+{
+    BB<NW> r;
+    static_for<NW>([&](auto I) {
+        constexpr int i = I;
+        constexpr uint32_t m = mask_word(P{}, NBITS, i);
+        r.w[i] = a.w[i] & ~m;
+    });
+    return r;
+}
+
+template <class P, int NBITS, int NW>
+__device__ __forceinline__ BB<NW> const_mask()
+{
+    BB<NW> r;
+    static_for<NW>([&](auto I) {
+        constexpr int i = I;
+        r.w[i] = mask_word(P{}, NBITS, i);
+    });
+    return r;
+}
+
+struct AllBits {
+    constexpr bool operator()(int) const { return true; }
+};
+
+// Logical shift towards higher bit indices by a compile-time amount.
+template <int S, int NW>
+__device__ __forceinline__ BB<NW> shl(const BB<NW> &x)
+{
+    static_assert(S > 0, "shift amount");
+    constexpr int q = S / 32, s = S % 32;
+    BB<NW> r;
+    static_for<NW>([&](auto I) {
+        constexpr int i = I;
+        constexpr int j = i - q;
+        uint32_t hi = 0u, lo = 0u;
+        if constexpr (j >= 0) hi = x.w[j >= 0 ? j : 0];
+        if constexpr (j - 1 >= 0) lo = x.w[j - 1 >= 0 ? j - 1 : 0];
+        if constexpr (s == 0) r.w[i] = hi;
+        else r.w[i] = __builtin_amdgcn_alignbit(hi, lo, 32 - s);
+    });
+    return r;
+}
+
+// Logical shift towards lower bit indices by a compile-time amount.
+template <int S, int NW>
+__device__ __forceinline__ BB<NW> shr(const BB<NW> &x)
+{
+    static_assert(S > 0, "shift amount");
+    constexpr int q = S / 32, s = S % 32;
+    BB<NW> r;
+    static_for<NW>([&](auto I) {
+        constexpr int i = I;
+        constexpr int j = i + q;
+        uint32_t hi = 0u, lo = 0u;
+        if constexpr (j < NW) lo = x.w[j < NW ? j : 0];
+        if constexpr (j + 1 < NW) hi = x.w[j + 1 < NW ? j + 1 : 0];
+        if constexpr (s == 0) r.w[i] = lo;
+        else r.w[i] = __builtin_amdgcn_alignbit(hi, lo, s);
+    });
+    return r;
+}
+
+// Shift by a signed compile-time amount (positive = towards higher bits).
+template <int S, int NW>
+__device__ __forceinline__ BB<NW> shift(const BB<NW> &x)
+{
+    if constexpr (S > 0) return shl<S>(x);
+    else return shr<-S>(x);
+}
+
+// Bitboard with only bit b set (b in range).
+template <int NW>
+__device__ __forceinline__ BB<NW> onehot(int b)
+{
+    BB<NW> r;
+    const uint32_t bit = 1u << (b & 31);
+    const int q = b >> 5;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = (q == i) ? bit : 0u;
+    return r;
+}
+
+template <int NW>
+__device__ __forceinline__ uint32_t test_bit(const BB<NW> &x, int b)
+{
+    const int q = b >> 5;
+    uint32_t w = x.w[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) w = (q == i) ? x.w[i] : w;
+    return (w >> (b & 31)) & 1u;
+}
+
+// Position of the k-th (from 0) set bit of a 32-bit word; k < popcount(w).
+__device__ __forceinline__ int select_in_word(uint32_t w, int k)
+{
+    int pos = 0;
+    int c = __popc(w & 0xFFFFu);
+    if (k >= c) { k -= c; w >>= 16; pos += 16; }
+    c = __popc(w & 0xFFu);
+    if (k >= c) { k -= c; w >>= 8; pos += 8; }
+    c = __popc(w & 0xFu);
+    if (k >= c) { k -= c; w >>= 4; pos += 4; }
+    c = __popc(w & 0x3u);
+    if (k >= c) { k -= c; w >>= 2; pos += 2; }
+    c = (int)(w & 1u);
+    if (k >= c) pos += 1;
+    return pos;
+}
+
+// Index of the k-th (from 0) set bit in increasing bit order; k < popcount(m).
+template <int NW>
+__device__ __forceinline__ int select_bit(const BB<NW> &m, int k)
+{
+    uint32_t wsel = m.w[0];
+    int base = 0;
+    bool found = false;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int c = __popc(m.w[i]);
+        const bool here = !found && k < c;
+        wsel = here ? m.w[i] : wsel;
+        base = here ? 32 * i : base;
+        k = (!found && !here) ? k - c : k;
+        found = found || here;
+    }
+    return base + select_in_word(wsel, k);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4x32 Philox S-box.  Each round multiplies counter words 0 and 2 by the two
+// Philox multipliers; the high halves are xored with the other two words and
+// the round key, the low halves move into place; the key advances by the two
+// Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct Philox4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2,
+                                                 uint32_t c3, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    Philox4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+// Pack four 0/1/2 cell bytes (one dword, little endian) into 4-bit fields:
+// player-1 flags and player-2 flags, cell j at bit j.
+__device__ __forceinline__ uint32_t pack4_p1(uint32_t v) { return ((v & 0x01010101u) * 0x00204081u) >> 21 & 0xFu; }
+__device__ __forceinline__ uint32_t pack4_p2(uint32_t v) { return (((v >> 1) & 0x01010101u) * 0x00204081u) >> 21 & 0xFu; }
+// Inverse: 4-bit fields of both players -> four cell bytes.
+__device__ __forceinline__ uint32_t unpack4(uint32_t b1, uint32_t b2)
+{
+    return ((b1 * 0x00204081u) & 0x01010101u) | (((b2 * 0x00204081u) & 0x01010101u) << 1);
+}
+
+} // namespace lx

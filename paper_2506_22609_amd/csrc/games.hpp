@@ -1,0 +1,441 @@
+// games.hpp -- the five rule sets as env-per-lane bitboard state machines.
+//
+// Every game keeps the two players' stones as bitboards in registers, in an
+// internal bit layout chosen so that line and neighbour tests are shifts:
+//   Tic-Tac-Toe   bit = cell (9 bits)
+//   Connect Four  row stride 8 (a zero guard column stops horizontal and
+//                 diagonal shifts from wrapping), 48 bits
+//   Reversi       bit = cell (64 bits); column masks stop wrapping
+//   Hex N         bit = cell (N*N bits); column masks stop wrapping
+//   Gomoku N      row stride N+1 (zero guard column), N*(N+1) bits
+// Every internal layout is increasing in the cell index, so "the k-th legal
+// cell in index order" is the k-th set bit of the internal legal mask.
+//
+// Interface of a game type G (used by the kernels):
+//   KIND, H, W, CELLS, A, NWC (words of a cell-indexed bitboard), NWI (words
+//   of the internal layout), HAS_PASS
+//   from_canon / to_canon: cell-indexed <-> internal layout
+//   load(c1, c2) / store(c1, c2): whole state from / to cell-indexed boards
+//   placements(me): internal mask of legal placements for player `me`
+//   action_of(bit) / bit_of(action)
+//   place(bit, me): apply a legal placement, return the end-rule outcome:
+//                   -1 the game goes on, 0 draw, 1 or 2 the winner
+//   pass(passes): Reversi's forced pass
+#pragma once
+
+#include "bitboard.hpp"
+
+namespace lx {
+
+// ---------------------------------------------------------------------------
+// generic cell-layout helpers
+// ---------------------------------------------------------------------------
+
+// Read LEN <= 32 bits starting at compile-time bit position POS.
+template <int POS, int LEN, int NW>
+__device__ __forceinline__ uint32_t get_field(const BB<NW> &x)
+{
+    constexpr int q = POS / 32, s = POS % 32;
+    constexpr uint32_t m = LEN == 32 ? 0xFFFFFFFFu : ((1u << LEN) - 1u);
+    uint32_t v = x.w[q] >> s;
+    if constexpr (s + LEN > 32 && q + 1 < NW) v |= x.w[q + 1 < NW ? q + 1 : 0] << (32 - s);
+    return v & m;
+}
+
+// OR a LEN-bit value into compile-time bit position POS.
+template <int POS, int LEN, int NW>
+__device__ __forceinline__ void or_field(BB<NW> &x, uint32_t v)
+{
+    constexpr int q = POS / 32, s = POS % 32;
+    x.w[q] |= v << s;
+    if constexpr (s + LEN > 32 && q + 1 < NW) x.w[q + 1 < NW ? q + 1 : 0] |= v >> (32 - s);
+}
+
+// Re-stride rows: cell (r, c) at bit r*FROM + c -> bit r*TO + c, c < W.
+template <int H, int W, int FROM, int TO, int NWF, int NWT>
+__device__ __forceinline__ BB<NWT> restride(const BB<NWF> &x)
+{
+    BB<NWT> r = bb_zero<NWT>();
+    static_for<H>([&](auto R) {
+        constexpr int row = R;
+        or_field<row * TO, W>(r, get_field<row * FROM, W>(x));
+    });
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Tic-Tac-Toe (App. C): a line of three wins, then a full board draws.
+// ---------------------------------------------------------------------------
+struct TicTacToe {
+    static constexpr int KIND = 1, H = 3, W = 3, CELLS = 9, A = 9, NWC = 1, NWI = 1;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<1>;
+    M p1, p2;
+
+    __device__ static M from_canon(const BB<NWC> &c) { return c; }
+    __device__ static BB<NWC> to_canon(const M &m) { return m; }
+    __device__ static int action_of(int b) { return b; }
+    __device__ static int bit_of(int a) { return a; }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = c1; p2 = c2; }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = p1; c2 = p2; }
+    __device__ void prepare() {}
+
+    __device__ M placements(int) const
+    {
+        M m;
+        m.w[0] = ~(p1.w[0] | p2.w[0]) & 0x1FFu;
+        return m;
+    }
+
+    __device__ static bool three(uint32_t x)
+    {
+        // rows, columns, diagonals of the 3x3 board
+        constexpr uint32_t L[8] = {0x007u, 0x038u, 0x1C0u, 0x049u, 0x092u, 0x124u, 0x111u, 0x054u};
+        bool w = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w = w || ((x & L[i]) == L[i]);
+        return w;
+    }
+
+    __device__ int place(int b, int me)
+    {
+        const uint32_t bit = 1u << b;
+        uint32_t own = (me == 1 ? p1.w[0] : p2.w[0]) | bit;
+        if (me == 1) p1.w[0] = own;
+        else p2.w[0] = own;
+        if (three(own)) return me;
+        if ((p1.w[0] | p2.w[0]) == 0x1FFu) return 0;
+        return -1;
+    }
+    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int pass(int &) { return -1; }
+};
+
+// ---------------------------------------------------------------------------
+// Connect Four 6x7 (App. C; Sec. 3.4): a placement must rest on the floor
+// or on a piece; four or more in a line wins; then a full board draws.
+// Internal bit of (r, c) = 8r + c; column 7 is an always-empty guard.
+// ---------------------------------------------------------------------------
+struct ConnectFour {
+    static constexpr int KIND = 2, H = 6, W = 7, CELLS = 42, A = 42, NWC = 2, NWI = 2;
+    static constexpr int S = 8, NBITS = H * S;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<NWI>;
+    M p1, p2;
+
+    struct Valid {
+        constexpr bool operator()(int b) const { return (b % S) < W; }
+    };
+    struct Floor {
+        constexpr bool operator()(int b) const { return b / S == H - 1 && (b % S) < W; }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c) { return restride<H, W, W, S, NWC, NWI>(c); }
+    __device__ static BB<NWC> to_canon(const M &m) { return restride<H, W, S, W, NWI, NWC>(m); }
+    __device__ static int action_of(int b) { return (b >> 3) * W + (b & 7); }
+    __device__ static int bit_of(int a) { return (a / W) * S + (a % W); }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = from_canon(c1); p2 = from_canon(c2); }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = to_canon(p1); c2 = to_canon(p2); }
+    __device__ void prepare() {}
+
+    __device__ M placements(int) const
+    {
+        const M occ = p1 | p2;
+        // empty cells whose lower neighbour (bit + 8) is occupied, or on the floor
+        const M support = shr<S>(occ) | const_mask<Floor, NBITS, NWI>();
+        return and_mask<Valid, NBITS, NWI>(andnot(support, occ));
+    }
+
+    template <int D>
+    __device__ static bool four_along(const M &x)
+    {
+        const M a = x & shr<D>(x);
+        return any(a & shr<2 * D>(a));
+    }
+
+    __device__ int place(int b, int me)
+    {
+        M own = (me == 1 ? p1 : p2) | onehot<NWI>(b);
+        if (me == 1) p1 = own;
+        else p2 = own;
+        if (four_along<1>(own) || four_along<S>(own) || four_along<S - 1>(own) || four_along<S + 1>(own))
+            return me;
+        const M occ = p1 | p2;
+        if (same(occ, const_mask<Valid, NBITS, NWI>())) return 0;
+        return -1;
+    }
+    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int pass(int &) { return -1; }
+};
+
+// ---------------------------------------------------------------------------
+// Hex NxN (App. C): parallelogram board; (r, c) touches (r-1, c), (r-1, c+1),
+// (r, c-1), (r, c+1), (r+1, c-1), (r+1, c).  Player 1 joins row 0 to row
+// N-1, player 2 column 0 to column N-1.  No draws (every full board has a
+// winner), so the only end rule is the mover's connection.
+//
+// Connection test (Sec. 4 keeps an incremental component structure; here
+// the incremental structure is one bitboard per player): reach[p] holds
+// player p's stones connected to p's first side.  A new stone that is on the
+// first side or touches reach[p] floods through p's stones not yet in
+// reach[p]; the mover wins when reach[p] meets the far side.  Every stone
+// enters reach[p] at most once per game.  The single-step kernel has no
+// carried reach sets and floods the new stone's group instead.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Hex {
+    static constexpr int KIND = 3, H = N, W = N, CELLS = N * N, A = N * N;
+    static constexpr int NWC = (CELLS + 31) / 32, NWI = NWC, NBITS = CELLS;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<NWI>;
+    M p1, p2, r1, r2;
+
+    struct Col0 {
+        constexpr bool operator()(int b) const { return b % N == 0; }
+    };
+    struct ColL {
+        constexpr bool operator()(int b) const { return b % N == N - 1; }
+    };
+    struct Row0 {
+        constexpr bool operator()(int b) const { return b < N; }
+    };
+    struct RowL {
+        constexpr bool operator()(int b) const { return b >= N * (N - 1); }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c) { return c; }
+    __device__ static BB<NWC> to_canon(const M &m) { return m; }
+    __device__ static int action_of(int b) { return b; }
+    __device__ static int bit_of(int a) { return a; }
+
+    // x plus its six neighbours, clipped to the board
+    __device__ static M dilate(const M &x)
+    {
+        if constexpr (N == 1) {
+            return x;
+        } else {
+            // neighbours in column c+1, (r, c+1) and (r-1, c+1): a wrap lands in column 0
+            const M up_right = andnot_mask<Col0, NBITS, NWI>(shl<1>(x) | shr<N - 1>(x));
+            // neighbours in column c-1, (r, c-1) and (r+1, c-1): a wrap lands in column N-1
+            const M left_down = andnot_mask<ColL, NBITS, NWI>(shr<1>(x) | shl<N - 1>(x));
+            const M vert = shl<N>(x) | shr<N>(x);
+            return and_mask<AllBits, NBITS, NWI>(x | up_right | left_down | vert);
+        }
+    }
+
+    // grow `seed` inside `allowed` to its connected closure
+    __device__ static M flood(M seed, const M &allowed)
+    {
+        for (;;) {
+            const M next = dilate(seed) & allowed;
+            if (same(next, seed)) return seed;
+            seed = next;
+        }
+    }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = c1; p2 = c2; }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = p1; c2 = p2; }
+    __device__ void prepare()
+    {
+        r1 = flood(and_mask<Row0, NBITS, NWI>(p1), p1);
+        r2 = flood(and_mask<Col0, NBITS, NWI>(p2), p2);
+    }
+
+    __device__ M placements(int) const { return and_mask<AllBits, NBITS, NWI>(~(p1 | p2)); }
+
+    // playout version: carried reach sets
+    __device__ int place(int b, int me)
+    {
+        const M s = onehot<NWI>(b);
+        M own = (me == 1 ? p1 : p2) | s;
+        M reach = me == 1 ? r1 : r2;
+        const bool first_side = me == 1 ? (b < N) : (b % N == 0);
+        const bool touches = first_side || any(dilate(s) & reach);
+        bool won = false;
+        if (touches) {
+            reach = reach | flood(s, andnot(own, reach));
+            won = me == 1 ? any(and_mask<RowL, NBITS, NWI>(reach)) : any(and_mask<ColL, NBITS, NWI>(reach));
+        }
+        if (me == 1) { p1 = own; r1 = reach; }
+        else { p2 = own; r2 = reach; }
+        return won ? me : -1;
+    }
+
+    // single-step version: flood the new stone's group
+    __device__ int place_step(int b, int me)
+    {
+        const M s = onehot<NWI>(b);
+        const M own = (me == 1 ? p1 : p2) | s;
+        if (me == 1) p1 = own;
+        else p2 = own;
+        const M g = flood(s, own);
+        const bool won = me == 1 ? (any(and_mask<Row0, NBITS, NWI>(g)) && any(and_mask<RowL, NBITS, NWI>(g)))
+                                 : (any(and_mask<Col0, NBITS, NWI>(g)) && any(and_mask<ColL, NBITS, NWI>(g)));
+        return won ? me : -1;
+    }
+    __device__ int pass(int &) { return -1; }
+};
+
+// ---------------------------------------------------------------------------
+// Reversi 8x8 (App. C): a placement must sandwich at least one line of the
+// opponent's discs between the new disc and one of the mover's; every such
+// line flips.  With no placement the mover must pass (PASS = action 64).
+// Two passes in a row end the game; most discs wins, equal counts draw.
+// ---------------------------------------------------------------------------
+struct Reversi {
+    static constexpr int KIND = 4, H = 8, W = 8, CELLS = 64, A = 65, NWC = 2, NWI = 2, NBITS = 64;
+    static constexpr bool HAS_PASS = true;
+    using M = BB<2>;
+    M p1, p2;
+
+    struct Col0 {
+        constexpr bool operator()(int b) const { return b % 8 == 0; }
+    };
+    struct Col7 {
+        constexpr bool operator()(int b) const { return b % 8 == 7; }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c) { return c; }
+    __device__ static BB<NWC> to_canon(const M &m) { return m; }
+    __device__ static int action_of(int b) { return b; }
+    __device__ static int bit_of(int a) { return a; }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = c1; p2 = c2; }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = p1; c2 = p2; }
+    __device__ void prepare() {}
+
+    // one step in direction D (0..7): E, W, S, N, SE, SW, NE, NW
+    template <int D>
+    __device__ static M step(const M &x)
+    {
+        if constexpr (D == 0) return andnot_mask<Col0, 64, 2>(shl<1>(x));
+        else if constexpr (D == 1) return andnot_mask<Col7, 64, 2>(shr<1>(x));
+        else if constexpr (D == 2) return shl<8>(x);
+        else if constexpr (D == 3) return shr<8>(x);
+        else if constexpr (D == 4) return andnot_mask<Col0, 64, 2>(shl<9>(x));
+        else if constexpr (D == 5) return andnot_mask<Col7, 64, 2>(shl<7>(x));
+        else if constexpr (D == 6) return andnot_mask<Col0, 64, 2>(shr<7>(x));
+        else return andnot_mask<Col7, 64, 2>(shr<9>(x));
+    }
+
+    // cells from which a disc of `own` flanks a run of `opp` along D
+    template <int D>
+    __device__ static M moves_along(const M &own, const M &opp, const M &empty)
+    {
+        M x = step<D>(own) & opp;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) x = x | (step<D>(x) & opp);
+        return step<D>(x) & empty;
+    }
+
+    __device__ M placements(int me) const
+    {
+        const M own = me == 1 ? p1 : p2;
+        const M opp = me == 1 ? p2 : p1;
+        const M empty = ~(p1 | p2);
+        // walking from the mover's discs over a run of the opponent's along
+        // D lands on exactly the empty cells that flank along -D; all eight
+        // directions together give every legal placement
+        M m = bb_zero<2>();
+        static_for<8>([&](auto Dc) {
+            constexpr int D = Dc;
+            m = m | moves_along<D>(own, opp, empty);
+        });
+        return m;
+    }
+
+    // opponent discs flipped along D by a disc placed at s
+    template <int D>
+    __device__ static M flips_along(const M &s, const M &own, const M &opp)
+    {
+        M run = step<D>(s) & opp;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) run = run | (step<D>(run) & opp);
+        return any(step<D>(run) & own) ? run : bb_zero<2>();
+    }
+
+    __device__ int place(int b, int me)
+    {
+        const M s = onehot<2>(b);
+        M own = me == 1 ? p1 : p2;
+        M opp = me == 1 ? p2 : p1;
+        M f = bb_zero<2>();
+        static_for<8>([&](auto Dc) {
+            constexpr int D = Dc;
+            f = f | flips_along<D>(s, own, opp);
+        });
+        own = own | f | s;
+        opp = andnot(opp, f);
+        if (me == 1) { p1 = own; p2 = opp; }
+        else { p2 = own; p1 = opp; }
+        return -1;
+    }
+
+    __device__ int place_step(int b, int me) { return place(b, me); }
+
+    __device__ int pass(int &passes)
+    {
+        passes += 1;
+        if (passes < 2) return -1;
+        const int n1 = popcount(p1), n2 = popcount(p2);
+        return n1 > n2 ? 1 : (n2 > n1 ? 2 : 0);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Gomoku NxN (App. C): a maximal line of exactly five wins (six or more does
+// not count), then a full board draws.  Internal bit of (r, c) = r(N+1) + c;
+// column N is an always-empty guard.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Gomoku {
+    static constexpr int KIND = 5, H = N, W = N, CELLS = N * N, A = N * N;
+    static constexpr int S = N + 1, NBITS = N * S;
+    static constexpr int NWC = (CELLS + 31) / 32, NWI = (NBITS + 31) / 32;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<NWI>;
+    M p1, p2;
+
+    struct Valid {
+        constexpr bool operator()(int b) const { return (b % S) < N; }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c) { return restride<N, N, N, S, NWC, NWI>(c); }
+    __device__ static BB<NWC> to_canon(const M &m) { return restride<N, N, S, N, NWI, NWC>(m); }
+    __device__ static int action_of(int b) { return (b / S) * N + (b % S); }
+    __device__ static int bit_of(int a) { return (a / N) * S + (a % N); }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = from_canon(c1); p2 = from_canon(c2); }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = to_canon(p1); c2 = to_canon(p2); }
+    __device__ void prepare() {}
+
+    __device__ M placements(int) const { return and_mask<Valid, NBITS, NWI>(~(p1 | p2)); }
+
+    // starts of maximal runs of exactly five along step D
+    template <int D>
+    __device__ static bool five_along(const M &x)
+    {
+        const M a1 = x & shr<D>(x);         // i, i+D
+        const M a2 = a1 & shr<2 * D>(a1);   // i .. i+3D
+        const M a3 = a2 & shr<4 * D>(x);    // i .. i+4D
+        const M e = andnot(andnot(a3, shl<D>(x)), shr<5 * D>(x));
+        return any(e);
+    }
+
+    __device__ int place(int b, int me)
+    {
+        M own = (me == 1 ? p1 : p2) | onehot<NWI>(b);
+        if (me == 1) p1 = own;
+        else p2 = own;
+        if (five_along<1>(own) || five_along<S>(own) || five_along<S - 1>(own) || five_along<S + 1>(own))
+            return me;
+        if (popcount(p1 | p2) == CELLS) return 0;
+        return -1;
+    }
+    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int pass(int &) { return -1; }
+};
+
+} // namespace lx

@@ -1,0 +1,247 @@
+"""Python binding of the GPU library (``include/ludax.h``).
+
+Argument marshalling only: shapes, dtypes, devices and contiguity are
+checked here, raw device pointers and the current HIP stream are handed to
+the C ABI, and every step of the computation runs in the library's HIP
+kernels.  PyTorch provides device memory and streams.  If the library has
+not been built this module raises on first use; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU = 1, 2, 3, 4, 5
+RUNNING, TERMINAL, TRUNCATED, ILLEGAL = 0, 1, 2, 3
+OK, E_INVALID, E_UNSUPPORTED, E_DEVICE = 0, -1, -2, -3
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so")
+
+# every symbol the public header declares
+EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
+           "ludax_legal_mask", "ludax_step", "ludax_playout", "ludax_strerror",
+           "ludax_last_device_error")
+
+_lock = threading.Lock()
+_lib = None
+
+
+class LudaxError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = f"{where}: {_load().ludax_strerror(code).decode()} ({code})"
+        if code == E_DEVICE:
+            msg += ": " + _load().ludax_last_device_error().decode()
+        super().__init__(msg)
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("max_plies", ctypes.c_int32)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("board", ctypes.c_void_p), ("to_move", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("winner", ctypes.c_void_p),
+                ("passes", ctypes.c_void_p), ("ply", ctypes.c_void_p),
+                ("last_action", ctypes.c_void_p), ("aux", ctypes.c_void_p)]
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    f"{LIB_PATH} is missing: build the HIP library first "
+                    "(python -c 'import __graft_entry__; __graft_entry__.build()')")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+            P = ctypes.POINTER
+            L.ludax_game_create.argtypes = [P(_Desc), P(vp)]
+            L.ludax_game_destroy.argtypes = [vp]
+            L.ludax_game_info.argtypes = [vp, P(i32), P(i32), P(i32), P(i32)]
+            L.ludax_init.argtypes = [vp, P(_State), i64, vp]
+            L.ludax_legal_mask.argtypes = [vp, P(_State), vp, i64, vp]
+            L.ludax_step.argtypes = [vp, P(_State), vp, vp, vp, vp, i64, vp]
+            L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
+                                        vp]
+            L.ludax_strerror.argtypes = [ctypes.c_int]
+            L.ludax_strerror.restype = ctypes.c_char_p
+            L.ludax_last_device_error.argtypes = []
+            L.ludax_last_device_error.restype = ctypes.c_char_p
+            for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
+                         "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_playout"):
+                getattr(L, name).restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def lib():
+    """The loaded ctypes library (raises if it was not built)."""
+    return _load()
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise LudaxError(code, where)
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, shape, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Game:
+    """An immutable game handle (kind, board size, ply bound)."""
+
+    def __init__(self, kind: int, rows: int, cols: int, max_plies: int = 0):
+        L = _load()
+        h = ctypes.c_void_p()
+        _check(L.ludax_game_create(ctypes.byref(_Desc(kind, rows, cols, max_plies)),
+                                   ctypes.byref(h)), "ludax_game_create")
+        self._h = h
+        self.kind, self.rows, self.cols = kind, rows, cols
+        c, a, x, m = (ctypes.c_int32() for _ in range(4))
+        _check(L.ludax_game_info(h, ctypes.byref(c), ctypes.byref(a), ctypes.byref(x),
+                                 ctypes.byref(m)), "ludax_game_info")
+        self.cells, self.num_actions, self.aux_bytes, self.max_plies = c.value, a.value, x.value, m.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ludax_game_destroy(h)
+            self._h = None
+
+
+class State:
+    """Device structure-of-arrays state of n environments."""
+
+    FIELDS = ("board", "to_move", "status", "winner", "passes", "ply", "last_action")
+
+    def __init__(self, game: Game, n: int, device="cuda"):
+        self.n, self.cells = n, game.cells
+        self.board = torch.empty((n, game.cells), dtype=torch.int8, device=device)
+        self.to_move = torch.empty(n, dtype=torch.int8, device=device)
+        self.status = torch.empty(n, dtype=torch.int8, device=device)
+        self.winner = torch.empty(n, dtype=torch.int8, device=device)
+        self.passes = torch.empty(n, dtype=torch.int8, device=device)
+        self.ply = torch.empty(n, dtype=torch.int16, device=device)
+        self.last_action = torch.empty(n, dtype=torch.int16, device=device)
+
+    def _c(self) -> _State:
+        for f in self.FIELDS:
+            t = getattr(self, f)
+            if not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError(f"state.{f} must be a contiguous device tensor")
+        if self.board.data_ptr() % 16:
+            raise ValueError("state.board must be 16-byte aligned")
+        return _State(*[_ptr(getattr(self, f)) for f in self.FIELDS], None)
+
+    @classmethod
+    def from_tensors(cls, game: Game, **fields) -> "State":
+        s = cls.__new__(cls)
+        s.cells = game.cells
+        s.n = fields["board"].shape[0]
+        dt = {"board": torch.int8, "to_move": torch.int8, "status": torch.int8,
+              "winner": torch.int8, "passes": torch.int8, "ply": torch.int16,
+              "last_action": torch.int16}
+        for f in cls.FIELDS:
+            t = fields[f]
+            shape = (s.n, game.cells) if f == "board" else (s.n,)
+            _need(t, dt[f], shape, f)
+            setattr(s, f, t)
+        return s
+
+    def clone(self) -> "State":
+        s = State.__new__(State)
+        s.n, s.cells = self.n, self.cells
+        for f in self.FIELDS:
+            setattr(s, f, getattr(self, f).clone())
+        return s
+
+    def cpu(self) -> dict:
+        return {f: getattr(self, f).cpu().numpy() for f in self.FIELDS}
+
+
+def init(game: Game, state: State, stream=None):
+    _check(_load().ludax_init(game.handle, ctypes.byref(state._c()), state.n, _stream(stream)),
+           "ludax_init")
+
+
+def legal_mask(game: Game, state: State, out: torch.Tensor | None = None, stream=None):
+    if out is None:
+        out = torch.empty((state.n, game.num_actions), dtype=torch.uint8, device=state.board.device)
+    _need(out, torch.uint8, (state.n, game.num_actions), "mask")
+    _check(_load().ludax_legal_mask(game.handle, ctypes.byref(state._c()), _ptr(out), state.n,
+                                    _stream(stream)), "ludax_legal_mask")
+    return out
+
+
+def step(game: Game, state: State, action: torch.Tensor, want_mask: bool = True, reward=None,
+         terminal=None, next_mask=None, stream=None):
+    dev = state.board.device
+    _need(action, torch.int32, (state.n,), "action")
+    if reward is None:
+        reward = torch.empty((state.n, 2), dtype=torch.int8, device=dev)
+    if terminal is None:
+        terminal = torch.empty(state.n, dtype=torch.uint8, device=dev)
+    if want_mask and next_mask is None:
+        next_mask = torch.empty((state.n, game.num_actions), dtype=torch.uint8, device=dev)
+    _need(reward, torch.int8, (state.n, 2), "reward")
+    _need(terminal, torch.uint8, (state.n,), "terminal")
+    if next_mask is not None:
+        _need(next_mask, torch.uint8, (state.n, game.num_actions), "next_mask")
+    _check(_load().ludax_step(game.handle, ctypes.byref(state._c()), _ptr(action), _ptr(reward),
+                              _ptr(terminal), _ptr(next_mask), state.n, _stream(stream)),
+           "ludax_step")
+    return reward, terminal, next_mask
+
+
+def playout(game: Game, state: State, seed: int, game_id_base: int = 0, game_id=None, reward=None,
+            terminal=None, stats=True, stream=None):
+    """stats: True (a fresh zeroed int64[4] is returned), a caller tensor
+    (added to), or None (no counters)."""
+    dev = state.board.device
+    if reward is None:
+        reward = torch.empty((state.n, 2), dtype=torch.int8, device=dev)
+    if terminal is None:
+        terminal = torch.empty(state.n, dtype=torch.uint8, device=dev)
+    if stats is True:
+        stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    _need(reward, torch.int8, (state.n, 2), "reward")
+    _need(terminal, torch.uint8, (state.n,), "terminal")
+    if stats is not None:
+        _need(stats, torch.int64, (4,), "stats")
+    if game_id is not None:
+        _need(game_id, torch.int64, (state.n,), "game_id")
+    _check(_load().ludax_playout(game.handle, ctypes.byref(state._c()),
+                                 ctypes.c_uint64(seed & (2**64 - 1)), game_id_base, _ptr(game_id),
+                                 _ptr(reward), _ptr(terminal), _ptr(stats), state.n,
+                                 _stream(stream)), "ludax_playout")
+    return reward, terminal, stats

@@ -1,0 +1,39 @@
+"""Seeded synthetic workloads: which games, batch sizes, seeds and game-id
+ranges the tests and the benchmark run.  Holds no rule or sampling
+arithmetic; both the GPU library and the CPU oracle take these as inputs.
+
+The paper benchmarks its own rule sets under a uniformly random policy
+(Sec. 6); no dataset is involved, so every input is a start position plus
+(seed, game id) pairs.
+"""
+from dataclasses import dataclass
+
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU = 1, 2, 3, 4, 5
+
+SEEDS = (1, 2, 3)
+
+
+@dataclass(frozen=True)
+class Batch:
+    name: str
+    kind: int
+    rows: int
+    cols: int
+    n: int
+
+
+# 1024 Tic-Tac-Toe playouts (the small case the oracle finishes at once)
+TTT_1024 = Batch("tictactoe3x3_n1024", TICTACTOE, 3, 3, 1024)
+# single-game batches of 65536 envs: Connect Four 6x7 and Hex 11x11
+C4_65536 = Batch("connect4_6x7_n65536", CONNECT_FOUR, 6, 7, 65536)
+HEX11_65536 = Batch("hex11x11_n65536", HEX, 11, 11, 65536)
+# the other rule sets at the same batch size (mixed-batch members)
+REVERSI_65536 = Batch("reversi8x8_n65536", REVERSI, 8, 8, 65536)
+GOMOKU15_65536 = Batch("gomoku15x15_n65536", GOMOKU, 15, 15, 65536)
+
+BENCH_BATCHES = (C4_65536, HEX11_65536)
+
+
+def game_id_base(step: int, batch: Batch) -> int:
+    """Distinct game ids per benchmark step: step * n."""
+    return step * batch.n

@@ -1,0 +1,117 @@
+"""The C-ABI library without a GPU: it loads, exports every symbol the
+public header declares, and rejects bad arguments on the host before any
+device work (so no GPU is touched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ludax.h")
+
+ludax = pytest.importorskip("paper_2506_22609_amd.ludax")
+
+
+def _lib():
+    try:
+        return ludax.lib()
+    except RuntimeError as e:
+        pytest.skip(str(e))
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(ludax_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared() == sorted(ludax.EXPORTS)
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+def _create(kind, rows, cols, max_plies=0):
+    L = _lib()
+    h = ctypes.c_void_p()
+    rc = L.ludax_game_create(ctypes.byref(ludax._Desc(kind, rows, cols, max_plies)), ctypes.byref(h))
+    return rc, h
+
+
+def test_game_create_and_info():
+    L = _lib()
+    cases = {(1, 3, 3): (9, 9, 9), (2, 6, 7): (42, 42, 42), (3, 11, 11): (121, 121, 121),
+             (4, 8, 8): (64, 65, 121), (5, 15, 15): (225, 225, 225), (3, 1, 1): (1, 1, 1),
+             (3, 19, 19): (361, 361, 361), (5, 5, 5): (25, 25, 25)}
+    for (k, r, c), exp in cases.items():
+        rc, h = _create(k, r, c)
+        assert rc == 0
+        cells, A, aux, mp = (ctypes.c_int32() for _ in range(4))
+        assert L.ludax_game_info(h, ctypes.byref(cells), ctypes.byref(A), ctypes.byref(aux),
+                                 ctypes.byref(mp)) == 0
+        assert (cells.value, A.value, mp.value) == exp and aux.value == 0
+        assert L.ludax_game_destroy(h) == 0
+    rc, h = _create(2, 6, 7, 10)
+    mp = ctypes.c_int32()
+    L.ludax_game_info(h, None, None, None, ctypes.byref(mp))
+    assert mp.value == 10
+    L.ludax_game_destroy(h)
+
+
+def test_unsupported_and_invalid_descs():
+    for k, r, c in [(2, 7, 6), (1, 4, 4), (3, 20, 20), (3, 5, 6), (5, 4, 4), (5, 20, 20), (4, 6, 6),
+                    (9, 3, 3), (0, 3, 3)]:
+        assert _create(k, r, c)[0] == ludax.E_UNSUPPORTED, (k, r, c)
+    for k, r, c, m in [(1, 0, 3, 0), (1, 3, -1, 0), (1, 3, 3, -1), (1, 3, 3, 40000)]:
+        assert _create(k, r, c, m)[0] == ludax.E_INVALID
+    L = _lib()
+    assert L.ludax_game_create(None, None) == ludax.E_INVALID
+    assert L.ludax_game_destroy(None) == ludax.E_INVALID
+    assert L.ludax_game_info(None, None, None, None, None) == ludax.E_INVALID
+
+
+def test_host_argument_checks_need_no_gpu():
+    L = _lib()
+    rc, h = _create(3, 11, 11)
+    assert rc == 0
+    st = ludax._State(*([16] * 7), None)  # aligned, non-null fake pointers (never dereferenced)
+    null_board = ludax._State(None, *([16] * 6), None)
+    odd_board = ludax._State(17, *([16] * 6), None)
+    s = ctypes.c_void_p(0)
+    # n < 0, NULL or misaligned required pointers, NULL handle
+    assert L.ludax_init(h, ctypes.byref(st), -1, s) == ludax.E_INVALID
+    assert L.ludax_init(None, ctypes.byref(st), 1, s) == ludax.E_INVALID
+    assert L.ludax_init(h, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_init(h, ctypes.byref(null_board), 1, s) == ludax.E_INVALID
+    assert L.ludax_init(h, ctypes.byref(odd_board), 1, s) == ludax.E_INVALID
+    assert L.ludax_legal_mask(h, ctypes.byref(st), None, 1, s) == ludax.E_INVALID
+    assert L.ludax_legal_mask(h, ctypes.byref(st), 17, 1, s) == ludax.E_INVALID
+    assert L.ludax_step(h, ctypes.byref(st), None, 16, 16, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_step(h, ctypes.byref(st), 16, None, 16, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_step(h, ctypes.byref(st), 16, 16, None, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_step(h, ctypes.byref(st), 16, 16, 16, 17, 1, s) == ludax.E_INVALID
+    assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, None, 16, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, None, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, 16, None, 2**31, s) == ludax.E_INVALID
+    # n = 0 is a no-op that launches nothing, whatever the buffers are
+    assert L.ludax_init(h, ctypes.byref(st), 0, s) == 0
+    assert L.ludax_init(h, None, 0, s) == 0
+    assert L.ludax_legal_mask(h, ctypes.byref(st), 16, 0, s) == 0
+    assert L.ludax_legal_mask(h, ctypes.byref(null_board), None, 0, s) == 0
+    assert L.ludax_step(h, ctypes.byref(st), 16, 16, 16, None, 0, s) == 0
+    assert L.ludax_step(h, None, None, None, None, None, 0, s) == 0
+    assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, 16, None, 0, s) == 0
+    assert L.ludax_playout(h, None, 1, 0, None, None, None, None, 0, s) == 0
+    assert L.ludax_init(None, None, 0, s) == ludax.E_INVALID
+    L.ludax_game_destroy(h)
+
+
+def test_strerror():
+    L = _lib()
+    for code in (0, -1, -2, -3, 5):
+        assert isinstance(L.ludax_strerror(code), bytes) and L.ludax_strerror(code)
+    assert L.ludax_last_device_error() == b""

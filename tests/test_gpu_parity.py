@@ -1,0 +1,190 @@
+"""GPU parity: every call of the C ABI (through the Python binding) against
+the CPU oracle, byte for byte, on the same seeded inputs.
+
+Sizes span several 64-env workgroups plus a ragged tail; states come from
+the start position and from reachable mid-game positions (some already
+ended); actions include illegal and out-of-range ones.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from tests.gpu_util import assert_same_state, from_device, pair, random_states, to_device
+
+pytestmark = pytest.mark.gpu
+
+ludax = pytest.importorskip("paper_2506_22609_amd.ludax")
+
+GAMES = [
+    (ref.TICTACTOE, 3, 3),
+    (ref.CONNECT_FOUR, 6, 7),
+    (ref.HEX, 11, 11),
+    (ref.REVERSI, 8, 8),
+    (ref.GOMOKU, 15, 15),
+    (ref.HEX, 19, 19),
+    (ref.GOMOKU, 19, 19),
+]
+IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 517])
+def test_init(g, n):
+    og, dg = pair(*g)
+    d = ludax.State(dg, n)
+    ludax.init(dg, d)
+    assert_same_state(ref.init(og, n), from_device(d), f"init n={n}")
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_legal_mask(g):
+    og, dg = pair(*g)
+    rng = np.random.default_rng(100 + g[0] * 31 + g[1])
+    n = 333
+    s = random_states(og, n, og.cells if g[0] != ref.REVERSI else 70, rng)
+    d = to_device(dg, s)
+    got = ludax.legal_mask(dg, d).cpu().numpy()
+    exp = ref.legal_mask(og, s)
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_step_sequences(g):
+    """Drive both sides with the same per-ply actions: mostly legal, some
+    illegal or out of range; compare everything after every ply."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(7 + g[0] * 13 + g[1])
+    n = 200
+    s = ref.init(og, n)
+    d = ludax.State(dg, n)
+    ludax.init(dg, d)
+    plies = min(og.cells + 6, 140)
+    for p in range(plies):
+        m = ref.legal_mask(og, s)
+        a = np.zeros(n, np.int32)
+        for i in range(n):
+            r = rng.random()
+            idx = np.flatnonzero(m[i])
+            if r < 0.01:
+                a[i] = -1 - int(rng.integers(0, 5))
+            elif r < 0.02:
+                a[i] = og.num_actions + int(rng.integers(0, 5))
+            elif r < 0.04 or idx.size == 0:
+                a[i] = int(rng.integers(0, og.num_actions))
+            else:
+                a[i] = idx[rng.integers(0, idx.size)]
+        rew, term, nm = ref.step(og, s, a)
+        grew, gterm, gnm = ludax.step(dg, d, torch.from_numpy(a).cuda())
+        assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
+        assert np.array_equal(term, gterm.cpu().numpy()), f"terminal at ply {p}"
+        assert np.array_equal(nm, gnm.cpu().numpy()), f"next mask at ply {p}"
+        assert_same_state(s, from_device(d), f"ply {p}")
+        if (s.status != ref.RUNNING).all():
+            break
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_step_without_mask(g):
+    og, dg = pair(*g)
+    rng = np.random.default_rng(3)
+    n = 130
+    s = random_states(og, n, 10, rng)
+    d = to_device(dg, s)
+    m = ref.legal_mask(og, s)
+    a = np.array([np.flatnonzero(r)[0] if r.any() else 0 for r in m], np.int32)
+    rew, term, _ = ref.step(og, s, a, want_mask=False)
+    grew, gterm, _ = ludax.step(dg, d, torch.from_numpy(a).cuda(), want_mask=False)
+    assert np.array_equal(rew, grew.cpu().numpy()) and np.array_equal(term, gterm.cpu().numpy())
+    assert_same_state(s, from_device(d))
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_playout_from_start(g, seed):
+    og, dg = pair(*g)
+    n = 1000 if og.cells <= 121 else 300
+    s = ref.init(og, n)
+    rew, term, stats = ref.playout(og, s, seed, 5000, threads=8)
+    d = ludax.State(dg, n)
+    ludax.init(dg, d)
+    grew, gterm, gstats = ludax.playout(dg, d, seed, 5000)
+    assert_same_state(s, from_device(d), "playout")
+    assert np.array_equal(rew, grew.cpu().numpy())
+    assert np.array_equal(term, gterm.cpu().numpy())
+    assert np.array_equal(stats, gstats.cpu().numpy())
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_playout_from_midgame_with_ids(g):
+    """Mid-game states (some ended, some ILLEGAL) and explicit game ids."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(11)
+    n = 257
+    s = random_states(og, n, min(og.cells, 40), rng)
+    s.status[::17] = ref.ILLEGAL
+    gid = rng.integers(-(2**62), 2**62, size=n, dtype=np.int64)
+    d = to_device(dg, s)
+    rew, term, stats = ref.playout(og, s, 0xDEADBEEFCAFEF00D, 0, game_id=gid)
+    grew, gterm, gstats = ludax.playout(dg, d, 0xDEADBEEFCAFEF00D, 0,
+                                        game_id=torch.from_numpy(gid).cuda())
+    assert_same_state(s, from_device(d), "playout")
+    assert np.array_equal(rew, grew.cpu().numpy())
+    assert np.array_equal(term, gterm.cpu().numpy())
+    assert np.array_equal(stats, gstats.cpu().numpy())
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_truncation(g):
+    og, dg = pair(g[0], g[1], g[2], 7)
+    n = 190
+    s = ref.init(og, n)
+    rew, term, stats = ref.playout(og, s, 9, 0)
+    d = ludax.State(dg, n)
+    ludax.init(dg, d)
+    grew, gterm, gstats = ludax.playout(dg, d, 9, 0)
+    assert_same_state(s, from_device(d))
+    assert np.array_equal(stats, gstats.cpu().numpy())
+
+
+@pytest.mark.parametrize("kind,sizes", [(ref.HEX, range(1, 20)), (ref.GOMOKU, range(5, 20))],
+                         ids=["hex", "gomoku"])
+def test_every_board_size(kind, sizes):
+    for N in sizes:
+        og, dg = pair(kind, N, N)
+        n = 130
+        s = ref.init(og, n)
+        rew, term, stats = ref.playout(og, s, N, 0, threads=8)
+        d = ludax.State(dg, n)
+        ludax.init(dg, d)
+        grew, gterm, gstats = ludax.playout(dg, d, N, 0)
+        assert_same_state(s, from_device(d), f"N={N}")
+        assert np.array_equal(stats, gstats.cpu().numpy()), f"N={N}"
+        # step parity on a few plies from mid-game
+        rng = np.random.default_rng(N)
+        s = random_states(og, 70, min(N * N, 30), rng)
+        d = to_device(dg, s)
+        for _ in range(3):
+            m = ref.legal_mask(og, s)
+            a = np.array([np.flatnonzero(r)[rng.integers(0, r.sum())] if r.any() else 0 for r in m],
+                         np.int32)
+            rew, term, nm = ref.step(og, s, a)
+            grew, gterm, gnm = ludax.step(dg, d, torch.from_numpy(a).cuda())
+            assert np.array_equal(nm, gnm.cpu().numpy()) and np.array_equal(rew, grew.cpu().numpy())
+            assert_same_state(s, from_device(d), f"step N={N}")
+
+
+def test_zero_envs():
+    og, dg = pair(ref.HEX, 11, 11)
+    d = ludax.State(dg, 0)
+    ludax.init(dg, d)
+    ludax.legal_mask(dg, d)
+    ludax.step(dg, d, torch.zeros(0, dtype=torch.int32, device="cuda"))
+    _, _, st = ludax.playout(dg, d, 1, 0)
+    assert st.cpu().numpy().tolist() == [0, 0, 0, 0]
