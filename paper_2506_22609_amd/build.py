@@ -26,6 +26,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the SLP vectorizer has nothing to gain on this integer code and
+    # crashes on some of the larger Gomoku step kernels
+    "-fno-slp-vectorize",
     "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 

@@ -88,6 +88,16 @@ __device__ __forceinline__ BB<NW> operator~(const BB<NW> &a)
     return r;
 }
 
+// c ? a : b, word by word (a whole-struct select would go through memory)
+template <int NW>
+__device__ __forceinline__ BB<NW> pick(bool c, const BB<NW> &a, const BB<NW> &b)
+{
+    BB<NW> r;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r.w[i] = c ? a.w[i] : b.w[i];
+    return r;
+}
+
 template <int NW>
 __device__ __forceinline__ bool any(const BB<NW> &a)
 {
@@ -245,19 +255,26 @@ __device__ __forceinline__ int select_in_word(uint32_t w, int k)
 template <int NW>
 __device__ __forceinline__ int select_bit(const BB<NW> &m, int k)
 {
+    // prefix popcounts; the last word whose prefix is <= k holds the bit
     uint32_t wsel = m.w[0];
-    int base = 0;
-    bool found = false;
+    int base = 0, off = 0, pre = __popc(m.w[0]);
 #pragma unroll
-    for (int i = 0; i < NW; ++i) {
-        const int c = __popc(m.w[i]);
-        const bool here = !found && k < c;
-        wsel = here ? m.w[i] : wsel;
-        base = here ? 32 * i : base;
-        k = (!found && !here) ? k - c : k;
-        found = found || here;
+    for (int i = 1; i < NW; ++i) {
+        const bool ge = k >= pre;
+        wsel = ge ? m.w[i] : wsel;
+        base = ge ? 32 * i : base;
+        off = ge ? pre : off;
+        pre += __popc(m.w[i]);
     }
-    return base + select_in_word(wsel, k);
+    return base + select_in_word(wsel, k - off);
+}
+
+// The legal action of a uniform draw: with n = popcount(m) set bits and a
+// 32-bit random word w, the k-th set bit for k = (w * n) >> 32.
+template <int NW>
+__device__ __forceinline__ int select_uniform(const BB<NW> &m, uint32_t w)
+{
+    return select_bit(m, (int)__umulhi(w, (uint32_t)popcount(m)));
 }
 
 // ---------------------------------------------------------------------------

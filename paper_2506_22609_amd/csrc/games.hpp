@@ -94,7 +94,7 @@ struct TicTacToe {
         constexpr uint32_t L[8] = {0x007u, 0x038u, 0x1C0u, 0x049u, 0x092u, 0x124u, 0x111u, 0x054u};
         bool w = false;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) w = w || ((x & L[i]) == L[i]);
+        for (int i = 0; i < 8; ++i) w = w | ((x & L[i]) == L[i]);
         return w;
     }
 
@@ -157,10 +157,11 @@ struct ConnectFour {
 
     __device__ int place(int b, int me)
     {
-        M own = (me == 1 ? p1 : p2) | onehot<NWI>(b);
-        if (me == 1) p1 = own;
-        else p2 = own;
-        if (four_along<1>(own) || four_along<S>(own) || four_along<S - 1>(own) || four_along<S + 1>(own))
+        M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
+        p1 = pick(me == 1, own, p1);
+        p2 = pick(me == 1, p2, own);
+        // all four directions, no short-circuit branches
+        if (four_along<1>(own) | four_along<S>(own) | four_along<S - 1>(own) | four_along<S + 1>(own))
             return me;
         const M occ = p1 | p2;
         if (same(occ, const_mask<Valid, NBITS, NWI>())) return 0;
@@ -173,16 +174,14 @@ struct ConnectFour {
 // ---------------------------------------------------------------------------
 // Hex NxN (App. C): parallelogram board; (r, c) touches (r-1, c), (r-1, c+1),
 // (r, c-1), (r, c+1), (r+1, c-1), (r+1, c).  Player 1 joins row 0 to row
-// N-1, player 2 column 0 to column N-1.  No draws (every full board has a
-// winner), so the only end rule is the mover's connection.
+// N-1, player 2 column 0 to column N-1.  No draws (every full board has
+// exactly one connected player), so the only end rule is the mover's
+// connection.
 //
-// Connection test (Sec. 4 keeps an incremental component structure; here
-// the incremental structure is one bitboard per player): reach[p] holds
-// player p's stones connected to p's first side.  A new stone that is on the
-// first side or touches reach[p] floods through p's stones not yet in
-// reach[p]; the mover wins when reach[p] meets the far side.  Every stone
-// enters reach[p] at most once per game.  The single-step kernel has no
-// carried reach sets and floods the new stone's group instead.
+// The single-step kernel floods the new stone's group (6-neighbour
+// dilation by shifts, repeated until it stops growing) and checks both
+// sides.  The playout kernel does not test connection ply by ply at all:
+// see k_playout_hex in kernels.hpp.
 // ---------------------------------------------------------------------------
 template <int N>
 struct Hex {
@@ -190,13 +189,19 @@ struct Hex {
     static constexpr int NWC = (CELLS + 31) / 32, NWI = NWC, NBITS = CELLS;
     static constexpr bool HAS_PASS = false;
     using M = BB<NWI>;
-    M p1, p2, r1, r2;
+    M p1, p2;
 
     struct Col0 {
         constexpr bool operator()(int b) const { return b % N == 0; }
     };
     struct ColL {
         constexpr bool operator()(int b) const { return b % N == N - 1; }
+    };
+    struct NotCol0 {
+        constexpr bool operator()(int b) const { return b % N != 0; }
+    };
+    struct NotColL {
+        constexpr bool operator()(int b) const { return b % N != N - 1; }
     };
     struct Row0 {
         constexpr bool operator()(int b) const { return b < N; }
@@ -210,71 +215,81 @@ struct Hex {
     __device__ static int action_of(int b) { return b; }
     __device__ static int bit_of(int a) { return a; }
 
-    // x plus its six neighbours, clipped to the board
+    // stones of player p on p's first / far side
+    __device__ static M first_side(const M &x, int p)
+    {
+        return p == 1 ? and_mask<Row0, NBITS, NWI>(x) : and_mask<Col0, NBITS, NWI>(x);
+    }
+    __device__ static bool meets_far_side(const M &x, int p)
+    {
+        return p == 1 ? any(and_mask<RowL, NBITS, NWI>(x)) : any(and_mask<ColL, NBITS, NWI>(x));
+    }
+    // do p's stones `x` join p's two sides?
+    __device__ static bool joins(const M &x, int p)
+    {
+        M r = first_side(x, p);
+        return flood_to_far(r, x, p);
+    }
+
+    // x plus its six neighbours, clipped to the board.  With y = x plus the
+    // right neighbours (r, c+1) and z = x plus the left neighbours (r, c-1),
+    // the row above contributes (r-1, c), (r-1, c+1) = y shifted up and the
+    // row below (r+1, c), (r+1, c-1) = z shifted down: four shifts in all.
     __device__ static M dilate(const M &x)
     {
         if constexpr (N == 1) {
             return x;
         } else {
-            // neighbours in column c+1, (r, c+1) and (r-1, c+1): a wrap lands in column 0
-            const M up_right = andnot_mask<Col0, NBITS, NWI>(shl<1>(x) | shr<N - 1>(x));
-            // neighbours in column c-1, (r, c-1) and (r+1, c-1): a wrap lands in column N-1
-            const M left_down = andnot_mask<ColL, NBITS, NWI>(shr<1>(x) | shl<N - 1>(x));
-            const M vert = shl<N>(x) | shr<N>(x);
-            return and_mask<AllBits, NBITS, NWI>(x | up_right | left_down | vert);
+            // a wrap lands in column 0 (or past the last cell) / in column N-1
+            const M y = x | and_mask<NotCol0, NBITS, NWI>(shl<1>(x));
+            const M z = x | and_mask<NotColL, NBITS, NWI>(shr<1>(x));
+            return and_mask<AllBits, NBITS, NWI>(y | z | shr<N>(y) | shl<N>(z));
         }
     }
 
-    // grow `seed` inside `allowed` to its connected closure
+    // grow `seed` inside `allowed` to its connected closure (seed within
+    // allowed); two dilations per convergence test
     __device__ static M flood(M seed, const M &allowed)
     {
         for (;;) {
-            const M next = dilate(seed) & allowed;
-            if (same(next, seed)) return seed;
-            seed = next;
+            const M n1 = dilate(seed) & allowed;
+            const M n2 = dilate(n1) & allowed;
+            seed = n2;
+            if (same(n2, n1)) return seed;
+        }
+    }
+
+    // grow `r` inside `allowed` until it stops growing or meets p's far
+    // side (growth is monotone, so testing every second dilation is
+    // enough); returns whether it met the far side
+    __device__ static bool flood_to_far(M &r, const M &allowed, int p)
+    {
+        for (;;) {
+            const M n1 = dilate(r) & allowed;
+            const M n2 = dilate(n1) & allowed;
+            r = n2;
+            if (same(n2, n1) | meets_far_side(n2, p)) return meets_far_side(n2, p);
         }
     }
 
     __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = c1; p2 = c2; }
     __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = p1; c2 = p2; }
-    __device__ void prepare()
-    {
-        r1 = flood(and_mask<Row0, NBITS, NWI>(p1), p1);
-        r2 = flood(and_mask<Col0, NBITS, NWI>(p2), p2);
-    }
+    __device__ void prepare() {}
 
     __device__ M placements(int) const { return and_mask<AllBits, NBITS, NWI>(~(p1 | p2)); }
 
-    // playout version: carried reach sets
+    // place and test the new stone's group against both sides
     __device__ int place(int b, int me)
     {
         const M s = onehot<NWI>(b);
-        M own = (me == 1 ? p1 : p2) | s;
-        M reach = me == 1 ? r1 : r2;
-        const bool first_side = me == 1 ? (b < N) : (b % N == 0);
-        const bool touches = first_side || any(dilate(s) & reach);
-        bool won = false;
-        if (touches) {
-            reach = reach | flood(s, andnot(own, reach));
-            won = me == 1 ? any(and_mask<RowL, NBITS, NWI>(reach)) : any(and_mask<ColL, NBITS, NWI>(reach));
-        }
-        if (me == 1) { p1 = own; r1 = reach; }
-        else { p2 = own; r2 = reach; }
-        return won ? me : -1;
-    }
-
-    // single-step version: flood the new stone's group
-    __device__ int place_step(int b, int me)
-    {
-        const M s = onehot<NWI>(b);
-        const M own = (me == 1 ? p1 : p2) | s;
-        if (me == 1) p1 = own;
-        else p2 = own;
+        const M own = pick(me == 1, p1, p2) | s;
+        p1 = pick(me == 1, own, p1);
+        p2 = pick(me == 1, p2, own);
         const M g = flood(s, own);
-        const bool won = me == 1 ? (any(and_mask<Row0, NBITS, NWI>(g)) && any(and_mask<RowL, NBITS, NWI>(g)))
-                                 : (any(and_mask<Col0, NBITS, NWI>(g)) && any(and_mask<ColL, NBITS, NWI>(g)));
+        const bool won = any(first_side(g, me)) && meets_far_side(g, me);
         return won ? me : -1;
     }
+    __device__ int place_step(int b, int me) { return place(b, me); }
     __device__ int pass(int &) { return -1; }
 };
 
@@ -332,8 +347,8 @@ struct Reversi {
 
     __device__ M placements(int me) const
     {
-        const M own = me == 1 ? p1 : p2;
-        const M opp = me == 1 ? p2 : p1;
+        const M own = pick(me == 1, p1, p2);
+        const M opp = pick(me == 1, p2, p1);
         const M empty = ~(p1 | p2);
         // walking from the mover's discs over a run of the opponent's along
         // D lands on exactly the empty cells that flank along -D; all eight
@@ -359,8 +374,8 @@ struct Reversi {
     __device__ int place(int b, int me)
     {
         const M s = onehot<2>(b);
-        M own = me == 1 ? p1 : p2;
-        M opp = me == 1 ? p2 : p1;
+        M own = pick(me == 1, p1, p2);
+        M opp = pick(me == 1, p2, p1);
         M f = bb_zero<2>();
         static_for<8>([&](auto Dc) {
             constexpr int D = Dc;
@@ -368,8 +383,8 @@ struct Reversi {
         });
         own = own | f | s;
         opp = andnot(opp, f);
-        if (me == 1) { p1 = own; p2 = opp; }
-        else { p2 = own; p1 = opp; }
+        p1 = pick(me == 1, own, opp);
+        p2 = pick(me == 1, opp, own);
         return -1;
     }
 
@@ -426,10 +441,10 @@ struct Gomoku {
 
     __device__ int place(int b, int me)
     {
-        M own = (me == 1 ? p1 : p2) | onehot<NWI>(b);
-        if (me == 1) p1 = own;
-        else p2 = own;
-        if (five_along<1>(own) || five_along<S>(own) || five_along<S - 1>(own) || five_along<S + 1>(own))
+        M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
+        p1 = pick(me == 1, own, p1);
+        p2 = pick(me == 1, p2, own);
+        if (five_along<1>(own) | five_along<S>(own) | five_along<S - 1>(own) | five_along<S + 1>(own))
             return me;
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;

@@ -14,9 +14,12 @@
 //              written in place, optional next mask
 //   k_playout  the whole uniform-random game in registers: mask -> Philox
 //              -> k-th legal action -> apply -> end rules, until every lane
-//              of the wave has ended; final board written back through LDS,
-//              step and outcome counters reduced per wave, one atomic each
+//              of the wave has ended; final board written back through LDS
+//   k_playout_hex  the same result for Hex by fill-then-resolve
+//   k_stats    step and outcome counters (a difference of two reductions)
 #pragma once
+
+#include <type_traits>
 
 #include "games.hpp"
 #include "ludax_internal.hpp"
@@ -101,13 +104,6 @@ __device__ __forceinline__ void write_mask_row(int8_t *p, const typename G::M &m
     if constexpr (G::HAS_PASS) p[G::CELLS] = pass_legal ? 1 : 0;
 }
 
-__device__ __forceinline__ int wave_sum(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // ---------------------------------------------------------------------------
 // a1: start positions
 // ---------------------------------------------------------------------------
@@ -154,16 +150,15 @@ __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t 
     stage_in<G::CELLS>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
     const bool valid = t < nb;
+    // every lane reads (lanes past the batch end read env e0 and an unused
+    // LDS row, and are then ignored), which keeps the state in registers
+    const int64_t ec = valid ? e0 + t : e0;
+    BB<G::NWC> c1, c2;
+    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
     G g;
-    int me = 1;
-    bool running = false;
-    if (valid) {
-        BB<G::NWC> c1, c2;
-        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-        g.load(c1, c2);
-        me = st.to_move[e0 + t];
-        running = st.status[e0 + t] == RUNNING;
-    }
+    g.load(c1, c2);
+    const int me = st.to_move[ec];
+    const bool running = valid && st.status[ec] == RUNNING;
     typename G::M m = bb_zero<G::NWI>();
     if (running) m = g.placements(me);
     const bool pass_legal = G::HAS_PASS && running && !any(m);
@@ -191,20 +186,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
     const int64_t e = e0 + t;
     const bool valid = t < nb;
 
+    const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
+    BB<G::NWC> c1, c2;
+    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
     G g;
-    int me = 1, status = ILLEGAL, winner = -1, passes = 0, ply = 0, last = -1, a = 0;
-    if (valid) {
-        BB<G::NWC> c1, c2;
-        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-        g.load(c1, c2);
-        me = st.to_move[e];
-        status = st.status[e];
-        winner = st.winner[e];
-        passes = st.passes[e];
-        ply = st.ply[e];
-        last = st.last_action[e];
-        a = action[e];
-    }
+    g.load(c1, c2);
+    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
+    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    const int a = action[ec];
     int r1 = 0, r2 = 0;
     bool changed = false;
     if (valid && status == RUNNING) {
@@ -287,8 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
                                                    uint32_t key0, uint32_t key1, int64_t gid_base,
                                                    const int64_t *__restrict__ gid,
                                                    int8_t *__restrict__ reward,
-                                                   uint8_t *__restrict__ terminal,
-                                                   unsigned long long *__restrict__ stats)
+                                                   uint8_t *__restrict__ terminal)
 {
     __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
@@ -298,30 +286,33 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
     const int64_t e = e0 + t;
     const bool valid = t < nb;
 
+    const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
+    BB<G::NWC> c1, c2;
+    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
     G g;
-    int me = 1, status = ILLEGAL, winner = -1, passes = 0, ply = 0, last = -1;
-    uint64_t id = 0;
-    if (valid) {
-        BB<G::NWC> c1, c2;
-        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-        g.load(c1, c2);
-        me = st.to_move[e];
-        status = st.status[e];
-        winner = st.winner[e];
-        passes = st.passes[e];
-        ply = st.ply[e];
-        last = st.last_action[e];
-        id = (uint64_t)(gid != nullptr ? gid[e] : gid_base + e);
-    }
+    g.load(c1, c2);
+    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
+    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
     const bool was_running = valid && status == RUNNING;
     if (was_running) g.prepare();
     const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
 
-    int r1 = 0, r2 = 0, steps = 0;
-    uint32_t blk_q = 0xFFFFFFFFu;
-    Philox4 blk;
-    blk.v[0] = blk.v[1] = blk.v[2] = blk.v[3] = 0u;
+    int r1 = 0, r2 = 0;
+    // Philox words are consumed in order; w0 is the word of the current
+    // ply.  A block serves plies 4q .. 4q+3; the first block may be entered
+    // part-way when the starting ply is not a multiple of four.
+    uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+    if (was_running) {
+        const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
+        const int r = ply & 3;
+        w0 = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
+        w1 = r == 0 ? f.v[1] : (r == 1 ? f.v[2] : f.v[3]);
+        w2 = r == 0 ? f.v[2] : f.v[3];
+        w3 = f.v[3];
+    }
     bool running = was_running;
+    bool first = true;
     while (running) {
         const typename G::M m = g.placements(me);
         const int np = popcount(m);
@@ -330,14 +321,18 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
             status = ILLEGAL;
             break;
         }
-        const uint32_t q = (uint32_t)ply >> 2;
-        if (q != blk_q) {
-            blk = philox4x32_10(q, id_lo, id_hi, 0u, key0, key1);
-            blk_q = q;
+        if ((ply & 3) == 0 && !first) {
+            const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
+            w0 = f.v[0];
+            w1 = f.v[1];
+            w2 = f.v[2];
+            w3 = f.v[3];
         }
-        const int j = ply & 3;
-        const uint32_t w = j == 0 ? blk.v[0] : (j == 1 ? blk.v[1] : (j == 2 ? blk.v[2] : blk.v[3]));
-        const int k = (int)__umulhi(w, (uint32_t)nl);
+        first = false;
+        const int k = (int)__umulhi(w0, (uint32_t)nl);
+        w0 = w1;
+        w1 = w2;
+        w2 = w3;
         int outcome, a;
         if (G::HAS_PASS && np == 0) {
             a = G::A - 1;
@@ -350,7 +345,6 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
         }
         ply += 1;
         last = a;
-        steps += 1;
         if (outcome >= 0) {
             status = TERMINAL;
             winner = outcome;
@@ -381,19 +375,186 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
         terminal[e] = 1;
     }
     stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
-    if (stats != nullptr) {
-        const bool ended = was_running && status == TERMINAL;
-        const int s = wave_sum(steps);
-        const int w1 = __popcll(__ballot(ended && winner == 1));
-        const int w2 = __popcll(__ballot(ended && winner == 2));
-        const int d = __popcll(__ballot(ended && winner == 0));
-        if (t == 0) {
-            atomicAdd(&stats[0], (unsigned long long)s);
-            atomicAdd(&stats[1], (unsigned long long)w1);
-            atomicAdd(&stats[2], (unsigned long long)w2);
-            atomicAdd(&stats[3], (unsigned long long)d);
+}
+
+// ---------------------------------------------------------------------------
+// a2-a7 fused for Hex: fill, then resolve.
+//
+// Which cells get played does not depend on whether the game has already
+// been won: the legal set is "every empty cell" either way.  So each lane
+// first plays its random sequence until the board is full (or max_plies),
+// with no end test at all, recording the cell of every ply in LDS.  Then it
+// finds the ply at which the game really ended.  Connection of a player's
+// stones only grows as stones are added, a full board has exactly one
+// connected player, and two opposing chains cannot both cross, so: the
+// winner W is the player connected at the end of the window, and the end
+// ply is W's m*-th move for the smallest m* whose prefix of W's moves
+// connects -- found by binary search, each probe a flood from W's first
+// side that restarts from the largest prefix already known not to connect.
+// Finally the moves after the end ply are taken off the board again.  The
+// per-ply work drops to mask, draw, select and place; the connection floods
+// run once per game instead of being the per-ply maximum over the 64 lanes.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, int max_plies,
+                                                       uint32_t key0, uint32_t key1, int64_t gid_base,
+                                                       const int64_t *__restrict__ gid,
+                                                       int8_t *__restrict__ reward,
+                                                       uint8_t *__restrict__ terminal)
+{
+    using G = Hex<N>;
+    using M = typename G::M;
+    constexpr int NW = G::NWI;
+    using E = typename std::conditional<(G::CELLS <= 256), uint8_t, uint16_t>::type;
+    constexpr int STAGE = BLOCK * G::CELLS;
+    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(E);
+    __shared__ __align__(16) int8_t lds[STAGE > LIST ? STAGE : LIST];
+    E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: cell of window ply j
+
+    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
+    const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
+    stage_in<G::CELLS>(st.board, e0, nb, lds);
+    const int t = threadIdx.x;
+    const int64_t e = e0 + t;
+    const bool valid = t < nb;
+
+    const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
+    M b1, b2;
+    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, b1, b2);
+    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
+    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
+    __syncthreads(); // the staging area becomes the move list
+
+    const bool run = valid && status == RUNNING;
+    const M valid_cells = const_mask<AllBits, G::NBITS, NW>();
+    const int empties = run ? G::CELLS - popcount(b1 | b2) : 0;
+    const int room = max_plies - ply > 1 ? max_plies - ply : 1;
+    const int T = empties < room ? empties : room; // plies in the window
+    const int me0 = me, ply0 = ply;
+    const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
+
+    // ---- fill: the random sequence, no end test ----
+    // One Philox block serves the four plies 4q .. 4q+3.  The window is cut
+    // into a head (up to the next multiple of four), whole blocks of four
+    // plies, and a tail, so that no ply tests whether it needs a new block.
+    M cur = pick(me0 == 1, b1, b2); // stones of the player to move at ply0
+    M oth = pick(me0 == 1, b2, b1);
+    // one ply by the owner of `mine` with random word w; window ply j
+    auto play = [&](M &mine, const M &theirs, int j, uint32_t w) {
+        const M m = andnot(valid_cells, mine | theirs);
+        const int b = select_uniform(m, w);
+        moves[j * BLOCK + t] = (E)b;
+        mine = mine | onehot<NW>(b);
+    };
+    auto swap_sides = [&]() {
+        const M x = cur;
+        cur = oth;
+        oth = x;
+    };
+    int j = 0;
+    const int r0 = ply0 & 3;
+    const int head = r0 == 0 ? 0 : (T < 4 - r0 ? T : 4 - r0);
+    if (head > 0) {
+        const Philox4 f = philox4x32_10((uint32_t)ply0 >> 2, id_lo, id_hi, 0u, key0, key1);
+        for (; j < head; ++j) {
+            const int wi = r0 + j;
+            play(cur, oth, j, wi == 1 ? f.v[1] : (wi == 2 ? f.v[2] : f.v[3]));
+            swap_sides();
         }
     }
+    for (; j + 4 <= T; j += 4) {
+        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
+        play(cur, oth, j, f.v[0]);
+        play(oth, cur, j + 1, f.v[1]);
+        play(cur, oth, j + 2, f.v[2]);
+        play(oth, cur, j + 3, f.v[3]);
+    }
+    if (j < T) {
+        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
+        for (int i = 0; j < T; ++j, ++i) {
+            play(cur, oth, j, i == 0 ? f.v[0] : (i == 1 ? f.v[1] : f.v[2]));
+            swap_sides();
+        }
+    }
+    // cur belongs to the player to move after the window; give it back to
+    // the player who moved first
+    if (T & 1) swap_sides();
+    const M end1 = pick(me0 == 1, cur, oth); // boards after the window
+    const M end2 = pick(me0 == 1, oth, cur);
+
+    // ---- resolve: who connected, and at which ply ----
+    int W = 0;
+    if (T > 0) {
+        if (G::joins(end1, 1)) W = 1;
+        else if (empties == T || G::joins(end2, 2)) W = 2; // a full board always has a winner
+    }
+    const int jw0 = W == me0 ? 0 : 1;          // W's first ply in the window
+    const int MW = W ? (T - jw0 + 1) >> 1 : 0; // W's moves in the window
+    int jstar = -1;
+    if (MW > 0) {
+        M s_lo = pick(W == 1, b1, b2); // W's stones before its lo-th window move
+        M r_lo = G::flood(G::first_side(s_lo, W), s_lo);
+        int lo = 1, hi = MW, next = 1; // next = first move not yet in s_lo
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            M s = s_lo;
+            for (int k = next; k <= mid; ++k) s = s | onehot<NW>((int)moves[(jw0 + 2 * (k - 1)) * BLOCK + t]);
+            M r = r_lo | G::first_side(s, W);
+            if (G::flood_to_far(r, s, W)) {
+                hi = mid;
+            } else {
+                lo = mid + 1;
+                s_lo = s;
+                r_lo = r;
+                next = mid + 1;
+            }
+        }
+        jstar = jw0 + 2 * (lo - 1);
+    }
+
+    // ---- the final position ----
+    const int played = jstar >= 0 ? jstar + 1 : T;
+    M f1 = end1, f2 = end2;
+    for (int j = played; j < T; ++j) { // take back the plies after the end
+        const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+        const int who = ((j & 1) == 0) ? me0 : 3 - me0;
+        if (who == 1) f1 = andnot(f1, x);
+        else f2 = andnot(f2, x);
+    }
+    int r1 = 0, r2 = 0;
+    if (run) {
+        if (T == 0) {
+            status = ILLEGAL; // RUNNING with no empty cell: only a hand-edited board
+        } else {
+            ply = ply0 + played;
+            last = (int)moves[(played - 1) * BLOCK + t];
+            if (jstar >= 0) {
+                status = TERMINAL;
+                winner = W;
+                me = W;
+                r1 = W == 1 ? 1 : -1;
+                r2 = -r1;
+            } else {
+                me = (T & 1) ? 3 - me0 : me0;
+                status = ply >= max_plies ? TRUNCATED : ILLEGAL;
+            }
+        }
+    }
+    __syncthreads(); // the move list becomes the staging area again
+    if (valid) {
+        write_board<G::CELLS, G::NWC>(lds + t * G::CELLS, f1, f2);
+        st.to_move[e] = (int8_t)me;
+        st.status[e] = (int8_t)status;
+        st.winner[e] = (int8_t)winner;
+        st.passes[e] = (int8_t)passes;
+        st.ply[e] = (int16_t)ply;
+        st.last_action[e] = (int16_t)last;
+        reward[2 * e] = (int8_t)r1;
+        reward[2 * e + 1] = (int8_t)r2;
+        terminal[e] = 1;
+    }
+    stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -428,10 +589,19 @@ struct Launch {
                               uint8_t *terminal, int64_t *stats, hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL(k_playout<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
-                           (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward, terminal,
-                           reinterpret_cast<unsigned long long *>(stats));
-        return hipGetLastError();
+        hipError_t err = hipSuccess;
+        if (stats != nullptr && (err = launch_stats(st, n, -1, stats, s)) != hipSuccess) return err;
+        if constexpr (G::KIND == 3) {
+            hipLaunchKernelGGL(k_playout_hex<G::H>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
+                               max_plies, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward,
+                               terminal);
+        } else {
+            hipLaunchKernelGGL(k_playout<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                               (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward, terminal);
+        }
+        if ((err = hipGetLastError()) != hipSuccess) return err;
+        if (stats != nullptr) return launch_stats(st, n, +1, stats, s);
+        return hipSuccess;
     }
     static constexpr GameOps ops()
     {

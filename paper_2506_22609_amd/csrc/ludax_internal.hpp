@@ -29,6 +29,10 @@ struct GameOps {
                           uint8_t *, int64_t *, hipStream_t);
 };
 
+// Step and outcome counters: stats[0..3] += sign * (sum of ply, number of
+// TERMINAL envs won by player 1, by player 2, drawn) over the n envs.
+hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats, hipStream_t s);
+
 // Lookup per game kind; NULL when the size is not supported.
 const GameOps *ops_tictactoe(int rows, int cols);
 const GameOps *ops_connect_four(int rows, int cols);

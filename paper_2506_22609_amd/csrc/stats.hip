@@ -1,0 +1,99 @@
+// stats.hip -- the step and outcome counters of ludax_playout.
+//
+// Launched before (sign -1) and after (sign +1) a playout on the same
+// stream: an env that was not RUNNING is unchanged by the playout and
+// cancels out, so the difference counts the plies applied and the games
+// ended by the playout.  Each thread reads 16 envs with 16-byte loads
+// (all four loads in flight at once), a block reduces through wave
+// shuffles and LDS, and adds its totals with four atomics; few blocks keep
+// same-address atomics rare.
+#include "ludax_internal.hpp"
+
+namespace lx {
+
+namespace {
+
+constexpr int SB = 256;      // threads per block
+constexpr int PER = 16;      // envs per thread per pass
+constexpr int TERMINAL_STATUS = 1;
+
+__device__ __forceinline__ void tally(int st, int w, int &w1, int &w2, int &d)
+{
+    const bool term = st == TERMINAL_STATUS;
+    w1 += term && w == 1;
+    w2 += term && w == 2;
+    d += term && w == 0;
+}
+
+__global__ __launch_bounds__(SB) void k_stats(const int8_t *__restrict__ status,
+                                              const int8_t *__restrict__ winner,
+                                              const int16_t *__restrict__ ply, int64_t n, int64_t nvec,
+                                              int sign, unsigned long long *__restrict__ stats)
+{
+    int64_t s = 0;
+    int w1 = 0, w2 = 0, d = 0;
+    const int64_t stride = (int64_t)gridDim.x * SB;
+    // vector part: groups of 16 envs (pointers are 16-byte aligned when nvec > 0)
+    for (int64_t g = (int64_t)blockIdx.x * SB + threadIdx.x; g < nvec; g += stride) {
+        const uint4 sv = reinterpret_cast<const uint4 *>(status)[g];
+        const uint4 wv = reinterpret_cast<const uint4 *>(winner)[g];
+        const uint4 p0 = reinterpret_cast<const uint4 *>(ply)[2 * g];
+        const uint4 p1 = reinterpret_cast<const uint4 *>(ply)[2 * g + 1];
+        const uint32_t sw[4] = {sv.x, sv.y, sv.z, sv.w};
+        const uint32_t ww[4] = {wv.x, wv.y, wv.z, wv.w};
+        const uint32_t pw[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += (int16_t)(pw[k] & 0xFFFFu) + (int16_t)(pw[k] >> 16);
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            tally((int8_t)(sw[k >> 2] >> (8 * (k & 3))), (int8_t)(ww[k >> 2] >> (8 * (k & 3))), w1, w2, d);
+    }
+    // scalar tail
+    for (int64_t i = nvec * PER + (int64_t)blockIdx.x * SB + threadIdx.x; i < n; i += stride) {
+        s += ply[i];
+        tally(status[i], winner[i], w1, w2, d);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        w1 += __shfl_xor(w1, o, 64);
+        w2 += __shfl_xor(w2, o, 64);
+        d += __shfl_xor(d, o, 64);
+    }
+    __shared__ long long part[SB / 64][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[wv][0] = s;
+        part[wv][1] = w1;
+        part[wv][2] = w2;
+        part[wv][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        long long v = 0;
+#pragma unroll
+        for (int k = 0; k < SB / 64; ++k) v += part[k][threadIdx.x];
+        if (v != 0) atomicAdd(&stats[threadIdx.x], (unsigned long long)(sign * v));
+    }
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+} // namespace
+
+hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats, hipStream_t s)
+{
+    const bool vec = aligned16(st.status) && aligned16(st.winner) && aligned16(st.ply);
+    const int64_t nvec = vec ? n / PER : 0;
+    // one group of 16 envs per thread (latency, not bandwidth, is the
+    // cost here), at most 128 blocks so that atomics stay few
+    const int64_t work = nvec > 0 ? nvec : n;
+    int64_t blocks = (work + SB - 1) / SB;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 128) blocks = 128;
+    hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(SB), 0, s, st.status, st.winner, st.ply, n,
+                       nvec, sign, reinterpret_cast<unsigned long long *>(stats));
+    return hipGetLastError();
+}
+
+} // namespace lx
