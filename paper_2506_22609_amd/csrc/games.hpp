@@ -88,6 +88,16 @@ struct TicTacToe {
         return m;
     }
 
+    // legal placements for either player given both stone sets, and the
+    // win predicate of one player's stones (both monotone in the stones)
+    __device__ static M open_cells(const M &a, const M &b)
+    {
+        M m;
+        m.w[0] = ~(a.w[0] | b.w[0]) & 0x1FFu;
+        return m;
+    }
+    __device__ static bool line(const M &x) { return three(x.w[0]); }
+
     __device__ static bool three(uint32_t x)
     {
         // rows, columns, diagonals of the 3x3 board
@@ -140,12 +150,20 @@ struct ConnectFour {
     __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = to_canon(p1); c2 = to_canon(p2); }
     __device__ void prepare() {}
 
-    __device__ M placements(int) const
+    // legal placements for either player given both stone sets: empty
+    // cells whose lower neighbour (bit + 8) is occupied, or on the floor
+    __device__ static M open_cells(const M &a, const M &b)
     {
-        const M occ = p1 | p2;
-        // empty cells whose lower neighbour (bit + 8) is occupied, or on the floor
+        const M occ = a | b;
         const M support = shr<S>(occ) | const_mask<Floor, NBITS, NWI>();
         return and_mask<Valid, NBITS, NWI>(andnot(support, occ));
+    }
+    __device__ M placements(int) const { return open_cells(p1, p2); }
+
+    // the win predicate of one player's stones: four or more in a line
+    __device__ static bool line(const M &x)
+    {
+        return four_along<1>(x) | four_along<S>(x) | four_along<S - 1>(x) | four_along<S + 1>(x);
     }
 
     template <int D>
@@ -160,9 +178,7 @@ struct ConnectFour {
         M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
         p1 = pick(me == 1, own, p1);
         p2 = pick(me == 1, p2, own);
-        // all four directions, no short-circuit branches
-        if (four_along<1>(own) | four_along<S>(own) | four_along<S - 1>(own) | four_along<S + 1>(own))
-            return me;
+        if (line(own)) return me;
         const M occ = p1 | p2;
         if (same(occ, const_mask<Valid, NBITS, NWI>())) return 0;
         return -1;
@@ -276,7 +292,8 @@ struct Hex {
     __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = p1; c2 = p2; }
     __device__ void prepare() {}
 
-    __device__ M placements(int) const { return and_mask<AllBits, NBITS, NWI>(~(p1 | p2)); }
+    __device__ static M open_cells(const M &a, const M &b) { return and_mask<AllBits, NBITS, NWI>(~(a | b)); }
+    __device__ M placements(int) const { return open_cells(p1, p2); }
 
     // place and test the new stone's group against both sides
     __device__ int place(int b, int me)

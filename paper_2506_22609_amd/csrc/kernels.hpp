@@ -378,6 +378,62 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
 }
 
 // ---------------------------------------------------------------------------
+// The random sequence of a window of T plies, without any end test: ply j
+// (from ply0) is played by the owner of `cur` for even j and of `oth` for
+// odd j, on a uniformly drawn cell of G::open_cells, and its internal bit is
+// recorded in moves[j * BLOCK + lane].  One Philox block serves the plies
+// 4q .. 4q+3; the window is cut into a head (up to the next multiple of
+// four), whole blocks of four plies and a tail, so that no ply tests
+// whether it needs a new block.  On return cur / oth again hold the stones
+// of the player who moved first / second.
+// ---------------------------------------------------------------------------
+template <class G, class E>
+__device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &oth, int T, int ply0,
+                                            uint32_t id_lo, uint32_t id_hi, uint32_t key0, uint32_t key1,
+                                            E *moves, int t)
+{
+    using M = typename G::M;
+    auto play = [&](M &mine, const M &theirs, int j, uint32_t w) {
+        const int b = select_uniform(G::open_cells(mine, theirs), w);
+        moves[j * BLOCK + t] = (E)b;
+        mine = mine | onehot<G::NWI>(b);
+    };
+    auto swap_sides = [&]() {
+        const M x = cur;
+        cur = oth;
+        oth = x;
+    };
+    int j = 0;
+    const int r0 = ply0 & 3;
+    const int head = r0 == 0 ? 0 : (T < 4 - r0 ? T : 4 - r0);
+    if (head > 0) {
+        const Philox4 f = philox4x32_10((uint32_t)ply0 >> 2, id_lo, id_hi, 0u, key0, key1);
+        for (; j < head; ++j) {
+            const int wi = r0 + j;
+            play(cur, oth, j, wi == 1 ? f.v[1] : (wi == 2 ? f.v[2] : f.v[3]));
+            swap_sides();
+        }
+    }
+    for (; j + 4 <= T; j += 4) {
+        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
+        play(cur, oth, j, f.v[0]);
+        play(oth, cur, j + 1, f.v[1]);
+        play(cur, oth, j + 2, f.v[2]);
+        play(oth, cur, j + 3, f.v[3]);
+    }
+    if (j < T) {
+        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
+        for (int i = 0; j < T; ++j, ++i) {
+            play(cur, oth, j, i == 0 ? f.v[0] : (i == 1 ? f.v[1] : f.v[2]));
+            swap_sides();
+        }
+    }
+    // cur belongs to the player to move after the window; give it back to
+    // the player who moved first
+    if (T & 1) swap_sides();
+}
+
+// ---------------------------------------------------------------------------
 // a2-a7 fused for Hex: fill, then resolve.
 //
 // Which cells get played does not depend on whether the game has already
@@ -427,7 +483,6 @@ __global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, i
     __syncthreads(); // the staging area becomes the move list
 
     const bool run = valid && status == RUNNING;
-    const M valid_cells = const_mask<AllBits, G::NBITS, NW>();
     const int empties = run ? G::CELLS - popcount(b1 | b2) : 0;
     const int room = max_plies - ply > 1 ? max_plies - ply : 1;
     const int T = empties < room ? empties : room; // plies in the window
@@ -435,51 +490,9 @@ __global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, i
     const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
 
     // ---- fill: the random sequence, no end test ----
-    // One Philox block serves the four plies 4q .. 4q+3.  The window is cut
-    // into a head (up to the next multiple of four), whole blocks of four
-    // plies, and a tail, so that no ply tests whether it needs a new block.
     M cur = pick(me0 == 1, b1, b2); // stones of the player to move at ply0
     M oth = pick(me0 == 1, b2, b1);
-    // one ply by the owner of `mine` with random word w; window ply j
-    auto play = [&](M &mine, const M &theirs, int j, uint32_t w) {
-        const M m = andnot(valid_cells, mine | theirs);
-        const int b = select_uniform(m, w);
-        moves[j * BLOCK + t] = (E)b;
-        mine = mine | onehot<NW>(b);
-    };
-    auto swap_sides = [&]() {
-        const M x = cur;
-        cur = oth;
-        oth = x;
-    };
-    int j = 0;
-    const int r0 = ply0 & 3;
-    const int head = r0 == 0 ? 0 : (T < 4 - r0 ? T : 4 - r0);
-    if (head > 0) {
-        const Philox4 f = philox4x32_10((uint32_t)ply0 >> 2, id_lo, id_hi, 0u, key0, key1);
-        for (; j < head; ++j) {
-            const int wi = r0 + j;
-            play(cur, oth, j, wi == 1 ? f.v[1] : (wi == 2 ? f.v[2] : f.v[3]));
-            swap_sides();
-        }
-    }
-    for (; j + 4 <= T; j += 4) {
-        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
-        play(cur, oth, j, f.v[0]);
-        play(oth, cur, j + 1, f.v[1]);
-        play(cur, oth, j + 2, f.v[2]);
-        play(oth, cur, j + 3, f.v[3]);
-    }
-    if (j < T) {
-        const Philox4 f = philox4x32_10((uint32_t)(ply0 + j) >> 2, id_lo, id_hi, 0u, key0, key1);
-        for (int i = 0; j < T; ++j, ++i) {
-            play(cur, oth, j, i == 0 ? f.v[0] : (i == 1 ? f.v[1] : f.v[2]));
-            swap_sides();
-        }
-    }
-    // cur belongs to the player to move after the window; give it back to
-    // the player who moved first
-    if (T & 1) swap_sides();
+    fill_window<G>(cur, oth, T, ply0, id_lo, id_hi, key0, key1, moves, t);
     const M end1 = pick(me0 == 1, cur, oth); // boards after the window
     const M end2 = pick(me0 == 1, oth, cur);
 
@@ -558,6 +571,136 @@ __global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, i
 }
 
 // ---------------------------------------------------------------------------
+// a2-a7 fused for the line games (Tic-Tac-Toe, Connect Four): fill, then
+// resolve.  As for Hex, the legal set does not depend on whether the game
+// is over (empty cells; Connect Four: empty cells resting on the floor or a
+// piece), so each lane plays its random sequence to the end of the window
+// first.  "Some player holds a line of n or more" only becomes true by the
+// owner's own placement and then stays true, so the ply that ended the
+// game is the first prefix of the window at which it holds -- found by
+// binary search over the window, each probe two shift-AND line tests.
+// Without a line, a full board is a draw (wins are tested before draws).
+// ---------------------------------------------------------------------------
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_playout_lines(DevState st, int64_t n, int max_plies,
+                                                         uint32_t key0, uint32_t key1, int64_t gid_base,
+                                                         const int64_t *__restrict__ gid,
+                                                         int8_t *__restrict__ reward,
+                                                         uint8_t *__restrict__ terminal)
+{
+    using M = typename G::M;
+    constexpr int NW = G::NWI;
+    using E = uint8_t; // internal bit indices are below 64
+    __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS];
+    E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: internal bit of window ply j
+
+    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
+    const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
+    stage_in<G::CELLS>(st.board, e0, nb, lds);
+    const int t = threadIdx.x;
+    const int64_t e = e0 + t;
+    const bool valid = t < nb;
+
+    const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
+    BB<G::NWC> c1, c2;
+    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
+    const M b1 = G::from_canon(c1), b2 = G::from_canon(c2);
+    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
+    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
+    __syncthreads(); // the staging area becomes the move list
+
+    const bool run = valid && status == RUNNING;
+    const int empties = run ? G::CELLS - popcount(b1 | b2) : 0;
+    const int room = max_plies - ply > 1 ? max_plies - ply : 1;
+    const int me0 = me, ply0 = ply;
+    const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
+    // the window ends where the board is full, at max_plies, or where no
+    // legal cell is left (Connect Four columns fill; equal to "full" here)
+    const int T = empties < room ? empties : room;
+
+    M cur = pick(me0 == 1, b1, b2);
+    M oth = pick(me0 == 1, b2, b1);
+    fill_window<G>(cur, oth, T, ply0, id_lo, id_hi, key0, key1, moves, t);
+    const M end1 = pick(me0 == 1, cur, oth);
+    const M end2 = pick(me0 == 1, oth, cur);
+
+    // ---- resolve: the first prefix with a line ----
+    int jstar = -1;
+    if (T > 0 && (G::line(end1) | G::line(end2))) {
+        M s1 = b1, s2 = b2; // stones before window ply lo
+        int lo = 0, hi = T - 1, next = 0;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            M a1 = s1, a2 = s2;
+            for (int j = next; j <= mid; ++j) {
+                const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+                const bool p1 = ((j & 1) == 0) == (me0 == 1);
+                a1 = pick(p1, a1 | x, a1);
+                a2 = pick(p1, a2, a2 | x);
+            }
+            if (G::line(a1) | G::line(a2)) {
+                hi = mid;
+            } else {
+                lo = mid + 1;
+                s1 = a1;
+                s2 = a2;
+                next = mid + 1;
+            }
+        }
+        jstar = lo;
+    }
+
+    // ---- the final position ----
+    const int played = jstar >= 0 ? jstar + 1 : T;
+    M f1 = end1, f2 = end2;
+    for (int j = played; j < T; ++j) { // take back the plies after the end
+        const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+        const bool p1 = ((j & 1) == 0) == (me0 == 1);
+        f1 = pick(p1, andnot(f1, x), f1);
+        f2 = pick(p1, f2, andnot(f2, x));
+    }
+    int r1 = 0, r2 = 0;
+    if (run) {
+        if (T == 0) {
+            status = ILLEGAL; // RUNNING with no empty cell: only a hand-edited board
+        } else {
+            ply = ply0 + played;
+            last = G::action_of((int)moves[(played - 1) * BLOCK + t]);
+            const int mover = ((played - 1) & 1) == 0 ? me0 : 3 - me0; // of the last ply
+            if (jstar >= 0) {
+                status = TERMINAL;
+                winner = mover;
+                me = mover;
+                r1 = mover == 1 ? 1 : -1;
+                r2 = -r1;
+            } else if (T == empties) {
+                status = TERMINAL; // full board without a line: draw
+                winner = 0;
+                me = mover;
+            } else {
+                me = 3 - mover;
+                status = TRUNCATED;
+            }
+        }
+    }
+    __syncthreads(); // the move list becomes the staging area again
+    if (valid) {
+        write_board<G::CELLS, G::NWC>(lds + t * G::CELLS, G::to_canon(f1), G::to_canon(f2));
+        st.to_move[e] = (int8_t)me;
+        st.status[e] = (int8_t)status;
+        st.winner[e] = (int8_t)winner;
+        st.passes[e] = (int8_t)passes;
+        st.ply[e] = (int16_t)ply;
+        st.last_action[e] = (int16_t)last;
+        reward[2 * e] = (int8_t)r1;
+        reward[2 * e + 1] = (int8_t)r2;
+        terminal[e] = 1;
+    }
+    stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <class G>
@@ -593,6 +736,10 @@ struct Launch {
         if (stats != nullptr && (err = launch_stats(st, n, -1, stats, s)) != hipSuccess) return err;
         if constexpr (G::KIND == 3) {
             hipLaunchKernelGGL(k_playout_hex<G::H>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
+                               max_plies, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward,
+                               terminal);
+        } else if constexpr (G::KIND == 1 || G::KIND == 2) {
+            hipLaunchKernelGGL(k_playout_lines<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
                                max_plies, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward,
                                terminal);
         } else {
