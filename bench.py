@@ -5,9 +5,10 @@ Workload: single-game batches of 65536 environments each, Connect Four 6x7
 and Hex 11x11 (int8 boards), uniform-random playouts from the start
 position to the end of every game.  One benchmark step = for each batch:
 ludax_init (start positions) + ludax_playout (legal mask, Philox draw,
-k-th legal action, apply, end rules, repeated until every game has ended,
-plus the step/outcome counters).  Every step uses fresh game ids, so no
-two steps play the same games.
+k-th legal action, apply, end rules, repeated until every game has ended)
++ the step/outcome counters (ludax_state_stats before and after, which is
+what ludax_playout's own stats argument runs).  Every step uses fresh game
+ids, so no two steps play the same games.
 
 Prints one JSON line: env-steps/s over the timed steps (all plies applied
 by all environments / wall time between two device synchronisations), the
@@ -26,12 +27,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Integer VALU work per env-step of the playout kernels (lane operations),
-# from the static instruction count of one pass of the playout loop body
-# along the path every ply takes; see the roofline section of the design
-# notes for the derivation.  Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 164, "hex11x11_n65536": 186}
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3 T lane-ops/s
+# Integer VALU work per env-step of the playout kernels (lane-operations):
+# SQ_INSTS_VALU x 64 / env-steps of one launch, measured with rocprofv3 on
+# this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt).  Peak:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (the fp64
+# vector rate 78.6 TFLOP/s counts an FMA as two operations).
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 284, "hex11x11_n65536": 181}
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# HBM bytes of one Hex playout launch: FETCH_SIZE and WRITE_SIZE scaled by
+# a 256 MiB copy (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
+HEX_TRAFFIC_BYTES = 17.78e6
+HBM_PEAK_GBS = 8000.0
 
 
 def _cpu_baseline(batches, budget_s: float):
@@ -67,6 +73,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed steps, one plain device copy of this many MiB "
+                         "(a known-size reference for HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the playouts are independent per game; "
@@ -92,16 +101,21 @@ def main():
     ev = {b.name: [] for b in batches}
 
     def one_step(k: int, record: bool):
+        # ludax_playout(stats=st) is state_stats(-1) + the playout kernel +
+        # state_stats(+1); the three are issued separately here so that the
+        # events bracket the playout kernel alone
         for b, g, s, r, t, st in zip(batches, games, states, rewards, terms, stats):
             ludax.init(g, s, stream=stream)
+            ludax.state_stats(g, s, -1, st, stream=stream)
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ludax.playout(g, s, args.seed, W.game_id_base(k, b), reward=r, terminal=t, stats=st,
+            ludax.playout(g, s, args.seed, W.game_id_base(k, b), reward=r, terminal=t, stats=None,
                           stream=stream)
             if record:
                 e1.record(stream)
                 ev[b.name].append((e0, e1))
+            ludax.state_stats(g, s, +1, st, stream=stream)
 
     for k in range(args.warmup):
         one_step(k, False)
@@ -114,6 +128,13 @@ def main():
         one_step(k, True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+
+    if args.copy_mb > 0:
+        src = torch.ones(args.copy_mb << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     per = {}
     total_steps = 0
@@ -128,13 +149,15 @@ def main():
 
     d = per[dominant]
     steps_per_launch = d["env_steps"] / args.steps
+    kern_s = d["playout_kernel_ms"] / 1e3
     ops = VALU_OPS_PER_STEP[dominant] * steps_per_launch
-    achieved = ops / (d["playout_kernel_ms"] / 1e3) / 1e12
+    achieved = ops / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                "kernel": f"k_playout<Hex<11>> ({dominant})",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": HEX_TRAFFIC_BYTES,
+                "kernel": f"k_playout_hex<11> ({dominant})",
                 "ops_per_env_step": VALU_OPS_PER_STEP[dominant],
-                "env_steps_per_launch": steps_per_launch}
+                "env_steps_per_launch": steps_per_launch,
+                "hbm_frac": HEX_TRAFFIC_BYTES / kern_s / 1e9 / HBM_PEAK_GBS}
 
     out = {
         "metric": "env-steps/s (plain random playouts, single-game batches)",

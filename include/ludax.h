@@ -164,6 +164,15 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed,
                   int64_t game_id_base, const int64_t *game_id, int8_t *reward,
                   uint8_t *terminal, int64_t *stats, int64_t n, hipStream_t stream);
 
+/* Counter reduction used by ludax_playout's stats, exposed on its own:
+ * stats[0..3] += sign * (sum of ply, number of TERMINAL envs won by player
+ * 1, won by player 2, drawn) over the n envs; sign is +1 or -1.  Calling
+ * it with sign -1 before and +1 after any sequence of calls on the same
+ * stream adds the plies applied and the games ended in between -- exactly
+ * what ludax_playout's stats argument adds. */
+int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t sign, int64_t *stats,
+                      int64_t n, hipStream_t stream);
+
 /* Text of a return code; never NULL. */
 const char *ludax_strerror(int code);
 

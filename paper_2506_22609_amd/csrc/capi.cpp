@@ -190,6 +190,18 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed, int
                                            terminal, stats, stream));
 }
 
+int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t sign, int64_t *stats,
+                      int64_t n, hipStream_t stream)
+{
+    if (game == nullptr || n < 0 || n > MAX_ENVS || (sign != 1 && sign != -1)) return LUDAX_E_INVALID;
+    if (n == 0) return LUDAX_OK;
+    if (stats == nullptr) return LUDAX_E_INVALID;
+    lx::DevState d;
+    int rc = check_state(state, &d);
+    if (rc) return rc;
+    return device_error(lx::launch_stats(d, n, sign, stats, stream));
+}
+
 const char *ludax_strerror(int code)
 {
     switch (code) {

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 
 # every symbol the public header declares
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
-           "ludax_legal_mask", "ludax_step", "ludax_playout", "ludax_strerror",
+           "ludax_legal_mask", "ludax_step", "ludax_playout", "ludax_state_stats", "ludax_strerror",
            "ludax_last_device_error")
 
 _lock = threading.Lock()
@@ -69,12 +69,14 @@ def _load():
             L.ludax_step.argtypes = [vp, P(_State), vp, vp, vp, vp, i64, vp]
             L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
                                         vp]
+            L.ludax_state_stats.argtypes = [vp, P(_State), ctypes.c_int32, vp, i64, vp]
             L.ludax_strerror.argtypes = [ctypes.c_int]
             L.ludax_strerror.restype = ctypes.c_char_p
             L.ludax_last_device_error.argtypes = []
             L.ludax_last_device_error.restype = ctypes.c_char_p
             for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
-                         "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_playout"):
+                         "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_playout",
+                         "ludax_state_stats"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -245,3 +247,12 @@ def playout(game: Game, state: State, seed: int, game_id_base: int = 0, game_id=
                                  _ptr(reward), _ptr(terminal), _ptr(stats), state.n,
                                  _stream(stream)), "ludax_playout")
     return reward, terminal, stats
+
+
+def state_stats(game: Game, state: State, sign: int, stats: torch.Tensor, stream=None):
+    """stats += sign * (sum of ply, TERMINAL wins of player 1, of player 2,
+    draws) over the batch (see ludax_state_stats)."""
+    _need(stats, torch.int64, (4,), "stats")
+    _check(_load().ludax_state_stats(game.handle, ctypes.byref(state._c()), sign, _ptr(stats),
+                                     state.n, _stream(stream)), "ludax_state_stats")
+    return stats

@@ -106,6 +106,10 @@ def test_host_argument_checks_need_no_gpu():
     assert L.ludax_step(h, None, None, None, None, None, 0, s) == 0
     assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, 16, None, 0, s) == 0
     assert L.ludax_playout(h, None, 1, 0, None, None, None, None, 0, s) == 0
+    assert L.ludax_state_stats(h, ctypes.byref(st), 1, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_state_stats(h, ctypes.byref(st), 2, 16, 1, s) == ludax.E_INVALID
+    assert L.ludax_state_stats(h, ctypes.byref(st), 0, 16, 1, s) == ludax.E_INVALID
+    assert L.ludax_state_stats(h, None, 1, None, 0, s) == 0
     assert L.ludax_init(None, None, 0, s) == ludax.E_INVALID
     L.ludax_game_destroy(h)
 

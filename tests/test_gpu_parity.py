@@ -188,3 +188,21 @@ def test_zero_envs():
     ludax.step(dg, d, torch.zeros(0, dtype=torch.int32, device="cuda"))
     _, _, st = ludax.playout(dg, d, 1, 0)
     assert st.cpu().numpy().tolist() == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("g", GAMES[:5], ids=IDS[:5])
+def test_state_stats_brackets_equal_playout_stats(g):
+    """ludax_state_stats(-1) ... ludax_state_stats(+1) around a playout adds
+    what the playout's own stats argument adds."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(21)
+    s = random_states(og, 300, 12, rng)
+    s.status[::9] = ref.ILLEGAL
+    d1, d2 = to_device(dg, s), to_device(dg, s)
+    _, _, st1 = ludax.playout(dg, d1, 4, 77)
+    st2 = torch.full((4,), 5, dtype=torch.int64, device="cuda")
+    ludax.state_stats(dg, d2, -1, st2)
+    ludax.playout(dg, d2, 4, 77, stats=None)
+    ludax.state_stats(dg, d2, +1, st2)
+    assert (st2.cpu() - 5).tolist() == st1.cpu().tolist()
+    assert_same_state(from_device(d1), from_device(d2))
