@@ -173,6 +173,53 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed,
 int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t sign, int64_t *stats,
                       int64_t n, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Mixed persistent batch.  Several rule sets share the device in one call:
+ * the games of a batch are the ids id_base + j, j in [0, n_games), and game
+ * id g has kind games[g mod n_kinds] and plays from that game's start
+ * position under the uniform-random policy of ludax_playout (same Philox
+ * convention, so game g's result equals a one-env ludax_playout with game
+ * id g).  Each kind runs its own persistent kernel over `slots` lanes
+ * (envs in flight); a lane whose game ends takes the kind's next game from
+ * a queue (64 games per atomic), so no lane waits for the longest game of
+ * a fixed batch.  The kinds' kernels run concurrently on internal streams
+ * forked from and joined back into the caller's stream, so the whole call
+ * can be captured into a graph and replayed.
+ * ------------------------------------------------------------------------ */
+typedef struct ludax_mixed ludax_mixed;
+
+/* 1 <= n_kinds <= 8 game handles (they must outlive the mixed handle).
+ * Creates the internal streams and events; the default plan gives every
+ * kind 65536 slots.  A mixed handle serves one host thread at a time. */
+int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mixed **out);
+int ludax_mixed_destroy(ludax_mixed *mixed);
+
+/* Lanes per kind: multiples of 64, at least 64 and at most 2^24 each. */
+int ludax_mixed_set_slots(ludax_mixed *mixed, const int32_t *slots);
+int ludax_mixed_get_slots(const ludax_mixed *mixed, int32_t *slots);
+
+/* Play every game of the batch to its end.  Device outputs indexed by j:
+ * winner [n_games] int8 (0 draw, 1, 2; -1 if truncated at max_plies),
+ * plies [n_games] int16 (plies of the game), last_action [n_games] int16.
+ * stats [n_kinds][4] int64 or NULL is ADDED to per kind: {plies, player-1
+ * wins, player-2 wins, draws}.  workspace: n_kinds uint32 device words
+ * (queue counters, cleared by the call).  id_base >= 0 and
+ * id_base + n_games < 2^62. */
+int ludax_mixed_playout(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int64_t n_games,
+                        int8_t *winner, int16_t *plies, int16_t *last_action, int64_t *stats,
+                        uint32_t *workspace, hipStream_t stream);
+
+/* The slot autotuner: times each kind alone at total_slots / n_kinds lanes
+ * to estimate its work, then times whole batches under candidate splits of
+ * total_slots (equal, proportional to the work, to its square root, and
+ * the proportional split with the largest kind's share moved by +-25 %)
+ * and keeps the fastest as the handle's plan.  Runs real batches with the
+ * given arguments (outputs are overwritten) and SYNCHRONISES the stream.
+ * *best_ms (may be NULL) receives the chosen plan's time. */
+int ludax_mixed_autotune(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int64_t n_games,
+                         int32_t total_slots, int8_t *winner, int16_t *plies, int16_t *last_action,
+                         uint32_t *workspace, hipStream_t stream, float *best_ms);
+
 /* Text of a return code; never NULL. */
 const char *ludax_strerror(int code);
 

@@ -5,10 +5,13 @@
 // synchronises a stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ludax.h"
 #include "ludax_internal.hpp"
@@ -200,6 +203,243 @@ int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t 
     int rc = check_state(state, &d);
     if (rc) return rc;
     return device_error(lx::launch_stats(d, n, sign, stats, stream));
+}
+
+struct ludax_mixed {
+    int n;
+    const ludax_game *games[8];
+    int32_t slots[8];
+    hipStream_t streams[8];
+    hipEvent_t fork, join[8];
+};
+
+namespace {
+
+constexpr int MAX_KINDS = 8;
+constexpr int64_t MAX_GAME_ID = (int64_t)1 << 62;
+
+int check_slots(const int32_t *slots, int n)
+{
+    for (int k = 0; k < n; ++k)
+        if (slots[k] < 64 || slots[k] > (1 << 24) || (slots[k] & 63) != 0) return LUDAX_E_INVALID;
+    return LUDAX_OK;
+}
+
+// j0 and count of kind k among the ids id_base + j, j < n_games
+void kind_range(int64_t id_base, int64_t n_games, int n, int k, int64_t *j0, int64_t *count)
+{
+    const int64_t first = ((int64_t)k - id_base % n + n) % n;
+    *j0 = first;
+    *count = first < n_games ? (n_games - 1 - first) / n + 1 : 0;
+}
+
+// Enqueue a batch under `slots` for the kinds whose bit is set in `mask`.
+int mixed_run(ludax_mixed *m, const int32_t *slots, unsigned mask, uint64_t seed, int64_t id_base,
+              int64_t n_games, int8_t *winner, int16_t *plies, int16_t *last, int64_t *stats,
+              uint32_t *workspace, hipStream_t stream)
+{
+    hipError_t e = lx::launch_zero_counters(workspace, m->n, stream);
+    if (e == hipSuccess) e = hipEventRecord(m->fork, stream);
+    for (int k = 0; k < m->n && e == hipSuccess; ++k) {
+        if (!((mask >> k) & 1u)) continue;
+        lx::MixedArgs a;
+        kind_range(id_base, n_games, m->n, k, &a.j0, &a.count);
+        if (a.count == 0) continue;
+        a.id_base = id_base;
+        a.stride = m->n;
+        a.max_plies = m->games[k]->max_plies;
+        a.key0 = (uint32_t)seed;
+        a.key1 = (uint32_t)(seed >> 32);
+        a.winner = winner;
+        a.plies = plies;
+        a.last = last;
+        a.counter = workspace + k;
+        // no more lanes than games
+        const int64_t need = (a.count + 63) / 64 * 64;
+        const int lanes = (int)std::min<int64_t>(slots[k], need);
+        e = hipStreamWaitEvent(m->streams[k], m->fork, 0);
+        if (e == hipSuccess) e = m->games[k]->ops->persist(a, lanes, m->streams[k]);
+        if (e == hipSuccess) e = hipEventRecord(m->join[k], m->streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(stream, m->join[k], 0);
+    }
+    if (e == hipSuccess && stats != nullptr)
+        e = lx::launch_mixed_stats(winner, plies, n_games, id_base, m->n, stats, stream);
+    return device_error(e);
+}
+
+int mixed_args_ok(const ludax_mixed *m, int64_t id_base, int64_t n_games, int8_t *winner, int16_t *plies,
+                  int16_t *last, uint32_t *workspace)
+{
+    if (m == nullptr || id_base < 0 || n_games < 0 || id_base > MAX_GAME_ID - n_games ||
+        n_games > MAX_ENVS)
+        return LUDAX_E_INVALID;
+    if (n_games > 0 && (winner == nullptr || plies == nullptr || last == nullptr || workspace == nullptr))
+        return LUDAX_E_INVALID;
+    return LUDAX_OK;
+}
+
+// wall time of one batch (ms), measured with events on the stream
+int timed_run(ludax_mixed *m, const int32_t *slots, unsigned mask, uint64_t seed, int64_t id_base,
+              int64_t n_games, int8_t *winner, int16_t *plies, int16_t *last, uint32_t *workspace,
+              hipStream_t stream, float *ms)
+{
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return LUDAX_E_DEVICE;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return LUDAX_E_DEVICE;
+    }
+    int rc = device_error(hipEventRecord(a, stream));
+    if (rc == LUDAX_OK)
+        rc = mixed_run(m, slots, mask, seed, id_base, n_games, winner, plies, last, nullptr, workspace, stream);
+    if (rc == LUDAX_OK) rc = device_error(hipEventRecord(b, stream));
+    if (rc == LUDAX_OK) rc = device_error(hipEventSynchronize(b));
+    if (rc == LUDAX_OK) rc = device_error(hipEventElapsedTime(ms, a, b));
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    return rc;
+}
+
+// split `total` lanes in proportion to w (multiples of 64, at least 64 each)
+void split(const double *w, int n, int32_t total, int32_t *out)
+{
+    double sum = 0;
+    for (int k = 0; k < n; ++k) sum += w[k];
+    for (int k = 0; k < n; ++k) {
+        const double share = sum > 0 ? w[k] / sum : 1.0 / n;
+        int32_t s = (int32_t)std::lround(share * total / 64.0) * 64;
+        out[k] = std::max<int32_t>(64, std::min<int32_t>(s, 1 << 24));
+    }
+}
+
+} // namespace
+
+int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mixed **out)
+{
+    if (games == nullptr || out == nullptr || n_kinds < 1 || n_kinds > MAX_KINDS) return LUDAX_E_INVALID;
+    *out = nullptr;
+    for (int k = 0; k < n_kinds; ++k)
+        if (games[k] == nullptr) return LUDAX_E_INVALID;
+    ludax_mixed *m = new (std::nothrow) ludax_mixed;
+    if (m == nullptr) return LUDAX_E_INVALID;
+    m->n = n_kinds;
+    int created = 0;
+    hipError_t e = hipEventCreateWithFlags(&m->fork, hipEventDisableTiming);
+    for (int k = 0; k < n_kinds && e == hipSuccess; ++k) {
+        m->games[k] = games[k];
+        m->slots[k] = 65536;
+        e = hipStreamCreateWithFlags(&m->streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join[k], hipEventDisableTiming);
+        if (e == hipSuccess) created = k + 1;
+    }
+    if (e != hipSuccess) {
+        for (int k = 0; k < created; ++k) {
+            hipStreamDestroy(m->streams[k]);
+            hipEventDestroy(m->join[k]);
+        }
+        delete m;
+        return device_error(e);
+    }
+    *out = m;
+    return LUDAX_OK;
+}
+
+int ludax_mixed_destroy(ludax_mixed *m)
+{
+    if (m == nullptr) return LUDAX_E_INVALID;
+    for (int k = 0; k < m->n; ++k) {
+        hipStreamDestroy(m->streams[k]);
+        hipEventDestroy(m->join[k]);
+    }
+    hipEventDestroy(m->fork);
+    delete m;
+    return LUDAX_OK;
+}
+
+int ludax_mixed_set_slots(ludax_mixed *m, const int32_t *slots)
+{
+    if (m == nullptr || slots == nullptr || check_slots(slots, m->n) != LUDAX_OK) return LUDAX_E_INVALID;
+    for (int k = 0; k < m->n; ++k) m->slots[k] = slots[k];
+    return LUDAX_OK;
+}
+
+int ludax_mixed_get_slots(const ludax_mixed *m, int32_t *slots)
+{
+    if (m == nullptr || slots == nullptr) return LUDAX_E_INVALID;
+    for (int k = 0; k < m->n; ++k) slots[k] = m->slots[k];
+    return LUDAX_OK;
+}
+
+int ludax_mixed_playout(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t n_games, int8_t *winner,
+                        int16_t *plies, int16_t *last_action, int64_t *stats, uint32_t *workspace,
+                        hipStream_t stream)
+{
+    int rc = mixed_args_ok(m, id_base, n_games, winner, plies, last_action, workspace);
+    if (rc) return rc;
+    if (n_games == 0) return LUDAX_OK;
+    return mixed_run(m, m->slots, 0xFFu, seed, id_base, n_games, winner, plies, last_action, stats, workspace,
+                     stream);
+}
+
+int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t n_games, int32_t total_slots,
+                         int8_t *winner, int16_t *plies, int16_t *last_action, uint32_t *workspace,
+                         hipStream_t stream, float *best_ms)
+{
+    int rc = mixed_args_ok(m, id_base, n_games, winner, plies, last_action, workspace);
+    if (rc) return rc;
+    if (n_games == 0 || total_slots < 64 * m->n) return LUDAX_E_INVALID;
+    const int n = m->n;
+    // 1. each kind alone at an equal share: its work in lane-milliseconds
+    int32_t eq[MAX_KINDS];
+    double w[MAX_KINDS], root[MAX_KINDS];
+    const double ones[MAX_KINDS] = {1, 1, 1, 1, 1, 1, 1, 1};
+    split(ones, n, total_slots, eq);
+    for (int k = 0; k < n; ++k) {
+        float ms = 0.f;
+        rc = timed_run(m, eq, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream, &ms);
+        if (rc) return rc;
+        w[k] = (double)ms * eq[k];
+        root[k] = std::sqrt(w[k]);
+    }
+    // 2. candidate splits of the whole batch
+    std::vector<std::vector<int32_t>> plans;
+    auto add = [&](const double *weights) {
+        std::vector<int32_t> p(n);
+        split(weights, n, total_slots, p.data());
+        plans.push_back(p);
+    };
+    add(ones);
+    add(w);
+    add(root);
+    int big = 0;
+    for (int k = 1; k < n; ++k)
+        if (w[k] > w[big]) big = k;
+    for (double f : {0.75, 1.25}) {
+        double v[MAX_KINDS];
+        for (int k = 0; k < n; ++k) v[k] = k == big ? w[k] * f : w[k];
+        add(v);
+    }
+    // 3. keep the fastest (a warm-up run first)
+    float best = 0.f;
+    int best_i = -1;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        float ms = 0.f;
+        if (i == 0) {
+            rc = timed_run(m, plans[i].data(), 0xFFu, seed, id_base, n_games, winner, plies, last_action,
+                           workspace, stream, &ms);
+            if (rc) return rc;
+        }
+        rc = timed_run(m, plans[i].data(), 0xFFu, seed, id_base, n_games, winner, plies, last_action, workspace,
+                       stream, &ms);
+        if (rc) return rc;
+        if (best_i < 0 || ms < best) {
+            best = ms;
+            best_i = (int)i;
+        }
+    }
+    for (int k = 0; k < n; ++k) m->slots[k] = plans[best_i][k];
+    if (best_ms) *best_ms = best;
+    return LUDAX_OK;
 }
 
 const char *ludax_strerror(int code)

@@ -67,7 +67,7 @@ __device__ __forceinline__ BB<NWT> restride(const BB<NWF> &x)
 // Tic-Tac-Toe (App. C): a line of three wins, then a full board draws.
 // ---------------------------------------------------------------------------
 struct TicTacToe {
-    static constexpr int KIND = 1, H = 3, W = 3, CELLS = 9, A = 9, NWC = 1, NWI = 1;
+    static constexpr int KIND = 1, H = 3, W = 3, CELLS = 9, A = 9, NWC = 1, NWI = 1, NBITS = 9;
     static constexpr bool HAS_PASS = false;
     using M = BB<1>;
     M p1, p2;

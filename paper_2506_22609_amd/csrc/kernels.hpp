@@ -268,6 +268,48 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
     }
 }
 
+// One ply of a running game with random word w: legal set, the k-th legal
+// action for k = (w * n_legal) >> 32, apply, end rules, advance.  Returns
+// whether the game goes on.  A RUNNING state with no legal action (only on
+// a hand-edited board) becomes ILLEGAL without consuming the ply.
+template <class G>
+__device__ __forceinline__ bool random_ply(G &g, int &me, int &passes, int &ply, int &last, int &status,
+                                           int &winner, uint32_t w, int max_plies)
+{
+    const typename G::M m = g.placements(me);
+    const int np = popcount(m);
+    const int nl = G::HAS_PASS ? (np > 0 ? np : 1) : np;
+    if (nl == 0) {
+        status = ILLEGAL;
+        return false;
+    }
+    const int k = (int)__umulhi(w, (uint32_t)nl);
+    int outcome, a;
+    if (G::HAS_PASS && np == 0) {
+        a = G::A - 1;
+        outcome = g.pass(passes);
+    } else {
+        const int b = select_bit(m, k);
+        a = G::action_of(b);
+        outcome = g.place(b, me);
+        passes = 0;
+    }
+    ply += 1;
+    last = a;
+    if (outcome >= 0) {
+        status = TERMINAL;
+        winner = outcome;
+        return false;
+    }
+    me = 3 - me;
+    if (ply >= max_plies) {
+        status = TRUNCATED;
+        winner = -1;
+        return false;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // a2-a8 fused: uniform-random playout to the end of every game
 // ---------------------------------------------------------------------------
@@ -314,13 +356,6 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
     bool running = was_running;
     bool first = true;
     while (running) {
-        const typename G::M m = g.placements(me);
-        const int np = popcount(m);
-        const int nl = G::HAS_PASS ? (np > 0 ? np : 1) : np;
-        if (nl == 0) { // only reachable from a hand-edited board
-            status = ILLEGAL;
-            break;
-        }
         if ((ply & 3) == 0 && !first) {
             const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
             w0 = f.v[0];
@@ -329,36 +364,14 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
             w3 = f.v[3];
         }
         first = false;
-        const int k = (int)__umulhi(w0, (uint32_t)nl);
+        running = random_ply(g, me, passes, ply, last, status, winner, w0, max_plies);
         w0 = w1;
         w1 = w2;
         w2 = w3;
-        int outcome, a;
-        if (G::HAS_PASS && np == 0) {
-            a = G::A - 1;
-            outcome = g.pass(passes);
-        } else {
-            const int b = select_bit(m, k);
-            a = G::action_of(b);
-            outcome = g.place(b, me);
-            passes = 0;
-        }
-        ply += 1;
-        last = a;
-        if (outcome >= 0) {
-            status = TERMINAL;
-            winner = outcome;
-            r1 = outcome == 1 ? 1 : (outcome == 2 ? -1 : 0);
-            r2 = -r1;
-            running = false;
-        } else {
-            me = 3 - me;
-            if (ply >= max_plies) {
-                status = TRUNCATED;
-                winner = -1;
-                running = false;
-            }
-        }
+    }
+    if (was_running && status == TERMINAL) {
+        r1 = winner == 1 ? 1 : (winner == 2 ? -1 : 0);
+        r2 = -r1;
     }
     if (valid) {
         BB<G::NWC> c1, c2;
@@ -450,44 +463,42 @@ __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &o
 // Finally the moves after the end ply are taken off the board again.  The
 // per-ply work drops to mask, draw, select and place; the connection floods
 // run once per game instead of being the per-ply maximum over the 64 lanes.
+//
+// The line games (Tic-Tac-Toe, Connect Four) use the same scheme: their
+// legal set is also independent of the game being over (Connect Four:
+// empty cells resting on the floor or a piece), and "some player holds a
+// line of n or more" only becomes true by the owner's own placement and
+// then stays true, so the end ply is the first prefix of the window at
+// which it holds -- again by binary search, each probe two shift-AND line
+// tests.  Without a line, a full board is a draw (wins before draws).
 // ---------------------------------------------------------------------------
-template <int N>
-__global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, int max_plies,
-                                                       uint32_t key0, uint32_t key1, int64_t gid_base,
-                                                       const int64_t *__restrict__ gid,
-                                                       int8_t *__restrict__ reward,
-                                                       uint8_t *__restrict__ terminal)
+
+// The outcome of one lane's window.
+template <class G>
+struct Window {
+    typename G::M f1, f2; // final stones of players 1 and 2
+    int status;           // TERMINAL, TRUNCATED, or ILLEGAL (no legal cell)
+    int winner, me, ply, last;
+};
+
+// Move-list entry type: internal bit indices of boards up to 256 bits fit a byte.
+template <class G>
+using MoveT = typename std::conditional<(G::NBITS <= 256), uint8_t, uint16_t>::type;
+
+// Play and resolve one window from stones b1 / b2, player me0 to move at
+// ply0.  Only meaningful for run == true (otherwise T = 0 and nothing is
+// played); `empties` legal cells remain at ply0.
+template <class G>
+__device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const typename G::M &b2,
+                                                 bool run, int me0, int ply0, int max_plies,
+                                                 uint32_t id_lo, uint32_t id_hi, uint32_t key0,
+                                                 uint32_t key1, MoveT<G> *moves, int t)
 {
-    using G = Hex<N>;
     using M = typename G::M;
     constexpr int NW = G::NWI;
-    using E = typename std::conditional<(G::CELLS <= 256), uint8_t, uint16_t>::type;
-    constexpr int STAGE = BLOCK * G::CELLS;
-    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(E);
-    __shared__ __align__(16) int8_t lds[STAGE > LIST ? STAGE : LIST];
-    E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: cell of window ply j
-
-    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
-    const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
-    stage_in<G::CELLS>(st.board, e0, nb, lds);
-    const int t = threadIdx.x;
-    const int64_t e = e0 + t;
-    const bool valid = t < nb;
-
-    const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
-    M b1, b2;
-    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, b1, b2);
-    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
-    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
-    const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
-    __syncthreads(); // the staging area becomes the move list
-
-    const bool run = valid && status == RUNNING;
     const int empties = run ? G::CELLS - popcount(b1 | b2) : 0;
-    const int room = max_plies - ply > 1 ? max_plies - ply : 1;
+    const int room = max_plies - ply0 > 1 ? max_plies - ply0 : 1;
     const int T = empties < room ? empties : room; // plies in the window
-    const int me0 = me, ply0 = ply;
-    const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
 
     // ---- fill: the random sequence, no end test ----
     M cur = pick(me0 == 1, b1, b2); // stones of the player to move at ply0
@@ -496,102 +507,112 @@ __global__ __launch_bounds__(BLOCK) void k_playout_hex(DevState st, int64_t n, i
     const M end1 = pick(me0 == 1, cur, oth); // boards after the window
     const M end2 = pick(me0 == 1, oth, cur);
 
-    // ---- resolve: who connected, and at which ply ----
-    int W = 0;
-    if (T > 0) {
-        if (G::joins(end1, 1)) W = 1;
-        else if (empties == T || G::joins(end2, 2)) W = 2; // a full board always has a winner
-    }
-    const int jw0 = W == me0 ? 0 : 1;          // W's first ply in the window
-    const int MW = W ? (T - jw0 + 1) >> 1 : 0; // W's moves in the window
+    // ---- resolve: the ply that ended the game (-1: none in the window) ----
     int jstar = -1;
-    if (MW > 0) {
-        M s_lo = pick(W == 1, b1, b2); // W's stones before its lo-th window move
-        M r_lo = G::flood(G::first_side(s_lo, W), s_lo);
-        int lo = 1, hi = MW, next = 1; // next = first move not yet in s_lo
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            M s = s_lo;
-            for (int k = next; k <= mid; ++k) s = s | onehot<NW>((int)moves[(jw0 + 2 * (k - 1)) * BLOCK + t]);
-            M r = r_lo | G::first_side(s, W);
-            if (G::flood_to_far(r, s, W)) {
-                hi = mid;
-            } else {
-                lo = mid + 1;
-                s_lo = s;
-                r_lo = r;
-                next = mid + 1;
-            }
+    if constexpr (G::KIND == 3) {
+        int W = 0;
+        if (T > 0) {
+            if (G::joins(end1, 1)) W = 1;
+            else if (empties == T || G::joins(end2, 2)) W = 2; // a full board always has a winner
         }
-        jstar = jw0 + 2 * (lo - 1);
+        const int jw0 = W == me0 ? 0 : 1;          // W's first ply in the window
+        const int MW = W ? (T - jw0 + 1) >> 1 : 0; // W's moves in the window
+        if (MW > 0) {
+            M s_lo = pick(W == 1, b1, b2); // W's stones before its lo-th window move
+            M r_lo = G::flood(G::first_side(s_lo, W), s_lo);
+            int lo = 1, hi = MW, next = 1; // next = first move not yet in s_lo
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                M s = s_lo;
+                for (int k = next; k <= mid; ++k) s = s | onehot<NW>((int)moves[(jw0 + 2 * (k - 1)) * BLOCK + t]);
+                M r = r_lo | G::first_side(s, W);
+                if (G::flood_to_far(r, s, W)) {
+                    hi = mid;
+                } else {
+                    lo = mid + 1;
+                    s_lo = s;
+                    r_lo = r;
+                    next = mid + 1;
+                }
+            }
+            jstar = jw0 + 2 * (lo - 1);
+        }
+    } else {
+        if (T > 0 && (G::line(end1) | G::line(end2))) {
+            M s1 = b1, s2 = b2; // stones before window ply lo
+            int lo = 0, hi = T - 1, next = 0;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                M a1 = s1, a2 = s2;
+                for (int j = next; j <= mid; ++j) {
+                    const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+                    const bool p1 = ((j & 1) == 0) == (me0 == 1);
+                    a1 = pick(p1, a1 | x, a1);
+                    a2 = pick(p1, a2, a2 | x);
+                }
+                if (G::line(a1) | G::line(a2)) {
+                    hi = mid;
+                } else {
+                    lo = mid + 1;
+                    s1 = a1;
+                    s2 = a2;
+                    next = mid + 1;
+                }
+            }
+            jstar = lo;
+        }
     }
 
     // ---- the final position ----
+    Window<G> w;
     const int played = jstar >= 0 ? jstar + 1 : T;
-    M f1 = end1, f2 = end2;
+    w.f1 = end1;
+    w.f2 = end2;
     for (int j = played; j < T; ++j) { // take back the plies after the end
         const M x = onehot<NW>((int)moves[j * BLOCK + t]);
-        const int who = ((j & 1) == 0) ? me0 : 3 - me0;
-        if (who == 1) f1 = andnot(f1, x);
-        else f2 = andnot(f2, x);
+        const bool p1 = ((j & 1) == 0) == (me0 == 1);
+        w.f1 = pick(p1, andnot(w.f1, x), w.f1);
+        w.f2 = pick(p1, w.f2, andnot(w.f2, x));
     }
-    int r1 = 0, r2 = 0;
-    if (run) {
-        if (T == 0) {
-            status = ILLEGAL; // RUNNING with no empty cell: only a hand-edited board
+    w.winner = -1;
+    w.ply = ply0 + played;
+    w.me = me0;
+    w.last = -1;
+    if (T == 0) {
+        w.status = ILLEGAL; // RUNNING with no legal cell: only a hand-edited board
+    } else {
+        w.last = G::action_of((int)moves[(played - 1) * BLOCK + t]);
+        const int mover = ((played - 1) & 1) == 0 ? me0 : 3 - me0; // of the last ply
+        if (jstar >= 0) {
+            w.status = TERMINAL;
+            w.winner = mover;
+            w.me = mover;
+        } else if (T == empties && G::KIND != 3) {
+            w.status = TERMINAL; // full board without a line: draw
+            w.winner = 0;
+            w.me = mover;
         } else {
-            ply = ply0 + played;
-            last = (int)moves[(played - 1) * BLOCK + t];
-            if (jstar >= 0) {
-                status = TERMINAL;
-                winner = W;
-                me = W;
-                r1 = W == 1 ? 1 : -1;
-                r2 = -r1;
-            } else {
-                me = (T & 1) ? 3 - me0 : me0;
-                status = ply >= max_plies ? TRUNCATED : ILLEGAL;
-            }
+            w.me = 3 - mover;
+            w.status = w.ply >= max_plies ? TRUNCATED : ILLEGAL;
         }
     }
-    __syncthreads(); // the move list becomes the staging area again
-    if (valid) {
-        write_board<G::CELLS, G::NWC>(lds + t * G::CELLS, f1, f2);
-        st.to_move[e] = (int8_t)me;
-        st.status[e] = (int8_t)status;
-        st.winner[e] = (int8_t)winner;
-        st.passes[e] = (int8_t)passes;
-        st.ply[e] = (int16_t)ply;
-        st.last_action[e] = (int16_t)last;
-        reward[2 * e] = (int8_t)r1;
-        reward[2 * e + 1] = (int8_t)r2;
-        terminal[e] = 1;
-    }
-    stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
+    return w;
 }
 
-// ---------------------------------------------------------------------------
-// a2-a7 fused for the line games (Tic-Tac-Toe, Connect Four): fill, then
-// resolve.  As for Hex, the legal set does not depend on whether the game
-// is over (empty cells; Connect Four: empty cells resting on the floor or a
-// piece), so each lane plays its random sequence to the end of the window
-// first.  "Some player holds a line of n or more" only becomes true by the
-// owner's own placement and then stays true, so the ply that ended the
-// game is the first prefix of the window at which it holds -- found by
-// binary search over the window, each probe two shift-AND line tests.
-// Without a line, a full board is a draw (wins are tested before draws).
-// ---------------------------------------------------------------------------
+// Fill-then-resolve playout of a batch of states (Hex, Tic-Tac-Toe,
+// Connect Four).
 template <class G>
-__global__ __launch_bounds__(BLOCK) void k_playout_lines(DevState st, int64_t n, int max_plies,
-                                                         uint32_t key0, uint32_t key1, int64_t gid_base,
-                                                         const int64_t *__restrict__ gid,
-                                                         int8_t *__restrict__ reward,
-                                                         uint8_t *__restrict__ terminal)
+__global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, int max_plies,
+                                                        uint32_t key0, uint32_t key1, int64_t gid_base,
+                                                        const int64_t *__restrict__ gid,
+                                                        int8_t *__restrict__ reward,
+                                                        uint8_t *__restrict__ terminal)
 {
     using M = typename G::M;
-    constexpr int NW = G::NWI;
-    using E = uint8_t; // internal bit indices are below 64
-    __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS];
+    using E = MoveT<G>;
+    constexpr int STAGE = BLOCK * G::CELLS;
+    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(E);
+    __shared__ __align__(16) int8_t lds[STAGE > LIST ? STAGE : LIST];
     E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: internal bit of window ply j
 
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
@@ -611,78 +632,20 @@ __global__ __launch_bounds__(BLOCK) void k_playout_lines(DevState st, int64_t n,
     __syncthreads(); // the staging area becomes the move list
 
     const bool run = valid && status == RUNNING;
-    const int empties = run ? G::CELLS - popcount(b1 | b2) : 0;
-    const int room = max_plies - ply > 1 ? max_plies - ply : 1;
-    const int me0 = me, ply0 = ply;
-    const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
-    // the window ends where the board is full, at max_plies, or where no
-    // legal cell is left (Connect Four columns fill; equal to "full" here)
-    const int T = empties < room ? empties : room;
-
-    M cur = pick(me0 == 1, b1, b2);
-    M oth = pick(me0 == 1, b2, b1);
-    fill_window<G>(cur, oth, T, ply0, id_lo, id_hi, key0, key1, moves, t);
-    const M end1 = pick(me0 == 1, cur, oth);
-    const M end2 = pick(me0 == 1, oth, cur);
-
-    // ---- resolve: the first prefix with a line ----
-    int jstar = -1;
-    if (T > 0 && (G::line(end1) | G::line(end2))) {
-        M s1 = b1, s2 = b2; // stones before window ply lo
-        int lo = 0, hi = T - 1, next = 0;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            M a1 = s1, a2 = s2;
-            for (int j = next; j <= mid; ++j) {
-                const M x = onehot<NW>((int)moves[j * BLOCK + t]);
-                const bool p1 = ((j & 1) == 0) == (me0 == 1);
-                a1 = pick(p1, a1 | x, a1);
-                a2 = pick(p1, a2, a2 | x);
-            }
-            if (G::line(a1) | G::line(a2)) {
-                hi = mid;
-            } else {
-                lo = mid + 1;
-                s1 = a1;
-                s2 = a2;
-                next = mid + 1;
-            }
-        }
-        jstar = lo;
-    }
-
-    // ---- the final position ----
-    const int played = jstar >= 0 ? jstar + 1 : T;
-    M f1 = end1, f2 = end2;
-    for (int j = played; j < T; ++j) { // take back the plies after the end
-        const M x = onehot<NW>((int)moves[j * BLOCK + t]);
-        const bool p1 = ((j & 1) == 0) == (me0 == 1);
-        f1 = pick(p1, andnot(f1, x), f1);
-        f2 = pick(p1, f2, andnot(f2, x));
-    }
+    const Window<G> w = play_window<G>(b1, b2, run, me, ply, max_plies, (uint32_t)id, (uint32_t)(id >> 32),
+                                       key0, key1, moves, t);
+    M f1 = b1, f2 = b2;
     int r1 = 0, r2 = 0;
     if (run) {
-        if (T == 0) {
-            status = ILLEGAL; // RUNNING with no empty cell: only a hand-edited board
-        } else {
-            ply = ply0 + played;
-            last = G::action_of((int)moves[(played - 1) * BLOCK + t]);
-            const int mover = ((played - 1) & 1) == 0 ? me0 : 3 - me0; // of the last ply
-            if (jstar >= 0) {
-                status = TERMINAL;
-                winner = mover;
-                me = mover;
-                r1 = mover == 1 ? 1 : -1;
-                r2 = -r1;
-            } else if (T == empties) {
-                status = TERMINAL; // full board without a line: draw
-                winner = 0;
-                me = mover;
-            } else {
-                me = 3 - mover;
-                status = TRUNCATED;
-            }
-        }
+        f1 = w.f1;
+        f2 = w.f2;
+        status = w.status;
+        winner = w.winner;
+        me = w.me;
+        ply = w.ply;
+        last = w.last;
+        r1 = winner == 1 ? 1 : (winner == 2 ? -1 : 0);
+        r2 = -r1;
     }
     __syncthreads(); // the move list becomes the staging area again
     if (valid) {
@@ -698,6 +661,139 @@ __global__ __launch_bounds__(BLOCK) void k_playout_lines(DevState st, int64_t n,
         terminal[e] = 1;
     }
     stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed persistent batch: one kernel per game kind, all kinds launched
+// concurrently.  A kind's games are the global indices j0, j0 + stride,
+// j0 + 2 stride, ... of the batch (count of them); game j has id
+// id_base + j.  A wave takes its games from the kind's queue 64 at a time
+// (one atomic per 64 games) and writes each game's winner (-1 if
+// truncated), ply count and last action at its global index.
+// ---------------------------------------------------------------------------
+
+// Start position of a lane (Reversi: the four discs; the rest: empty).
+template <class G>
+__device__ __forceinline__ void start_position(G &g)
+{
+    if constexpr (G::KIND == 4) {
+        // player 1 on E4 (row 3, col 4) and D5 (row 4, col 3); player 2 on D4 and E5
+        g.p1 = onehot<G::NWI>(3 * 8 + 4) | onehot<G::NWI>(4 * 8 + 3);
+        g.p2 = onehot<G::NWI>(3 * 8 + 3) | onehot<G::NWI>(4 * 8 + 4);
+    } else {
+        g.p1 = bb_zero<G::NWI>();
+        g.p2 = bb_zero<G::NWI>();
+    }
+}
+
+// next chunk of 64 games of this kind for the calling wave (wave-uniform)
+__device__ __forceinline__ int64_t next_chunk(unsigned int *counter)
+{
+    unsigned int c = 0u;
+    if (threadIdx.x == 0) c = atomicAdd(counter, 1u);
+    return (int64_t)__shfl(c, 0, 64);
+}
+
+// Per-ply kinds (Reversi, Gomoku): every lane plays one game at a time and
+// starts a new one as soon as its game has ended.  New games start only on
+// wave steps s = 0 mod 4, so every lane's ply is then a multiple of four
+// and one Philox block per lane serves the next four steps: the block
+// refresh is uniform across the wave, and a finished lane idles at most
+// three steps.
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_persist_ply(MixedArgs a)
+{
+    const int t = threadIdx.x;
+    const uint64_t below = (1ull << t) - 1ull;
+    G g;
+    start_position(g);
+    int me = 1, passes = 0, ply = 0, last = -1, status = RUNNING, winner = -1;
+    int64_t i = -1; // game of this kind played by the lane, -1 = idle
+    uint32_t id_lo = 0u, id_hi = 0u, w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+    int64_t pool = 0, pool_end = 0; // wave-uniform: unassigned games [pool, pool_end)
+    bool exhausted = false;
+    for (int s = 0;; ++s) {
+        if ((s & 3) == 0) {
+            uint64_t need = __ballot(i < 0);
+            while (need != 0ull && !exhausted) {
+                if (pool == pool_end) {
+                    pool = next_chunk(a.counter) * BLOCK;
+                    pool_end = pool + BLOCK < a.count ? pool + BLOCK : a.count;
+                    if (pool >= a.count) {
+                        exhausted = true;
+                        break;
+                    }
+                }
+                const int take = (int)(pool_end - pool) < __popcll(need) ? (int)(pool_end - pool) : __popcll(need);
+                const int rank = __popcll(need & below);
+                if (((need >> t) & 1ull) && rank < take) {
+                    i = pool + rank;
+                    const uint64_t id = (uint64_t)(a.id_base + a.j0 + i * a.stride);
+                    id_lo = (uint32_t)id;
+                    id_hi = (uint32_t)(id >> 32);
+                    start_position(g);
+                    me = 1;
+                    passes = 0;
+                    ply = 0;
+                    last = -1;
+                    status = RUNNING;
+                    winner = -1;
+                }
+                pool += take;
+                need = __ballot(i < 0);
+            }
+            if (__ballot(i >= 0) == 0ull) break;
+            if (i >= 0) {
+                const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, a.key0, a.key1);
+                w0 = f.v[0];
+                w1 = f.v[1];
+                w2 = f.v[2];
+                w3 = f.v[3];
+            }
+        }
+        if (i >= 0) {
+            const bool going = random_ply(g, me, passes, ply, last, status, winner, w0, a.max_plies);
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            if (!going) {
+                const int64_t j = a.j0 + i * a.stride;
+                a.winner[j] = (int8_t)(status == TERMINAL ? winner : -1);
+                a.plies[j] = (int16_t)ply;
+                a.last[j] = (int16_t)last;
+                i = -1;
+            }
+        }
+    }
+}
+
+// Fill-then-resolve kinds (Hex, Tic-Tac-Toe, Connect Four): every game of
+// a chunk fills the same number of plies from the start position, so the
+// 64 lanes of a wave play 64 games in lockstep and then take the next chunk.
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_persist_fill(MixedArgs a)
+{
+    using M = typename G::M;
+    using E = MoveT<G>;
+    __shared__ __align__(16) E moves[BLOCK * G::CELLS];
+    const int t = threadIdx.x;
+    const M zero = bb_zero<G::NWI>();
+    for (;;) {
+        const int64_t c = next_chunk(a.counter) * BLOCK;
+        if (c >= a.count) break;
+        const int64_t i = c + t;
+        const bool valid = i < a.count;
+        const int64_t j = a.j0 + (valid ? i : c) * a.stride;
+        const uint64_t id = (uint64_t)(a.id_base + j);
+        const Window<G> w = play_window<G>(zero, zero, valid, 1, 0, a.max_plies, (uint32_t)id,
+                                           (uint32_t)(id >> 32), a.key0, a.key1, moves, t);
+        if (valid) {
+            a.winner[j] = (int8_t)(w.status == TERMINAL ? w.winner : -1);
+            a.plies[j] = (int16_t)w.ply;
+            a.last[j] = (int16_t)w.last;
+        }
+        __syncthreads(); // the move list is reused by the next chunk
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -734,12 +830,8 @@ struct Launch {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
         hipError_t err = hipSuccess;
         if (stats != nullptr && (err = launch_stats(st, n, -1, stats, s)) != hipSuccess) return err;
-        if constexpr (G::KIND == 3) {
-            hipLaunchKernelGGL(k_playout_hex<G::H>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
-                               max_plies, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward,
-                               terminal);
-        } else if constexpr (G::KIND == 1 || G::KIND == 2) {
-            hipLaunchKernelGGL(k_playout_lines<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
+        if constexpr (G::KIND == 1 || G::KIND == 2 || G::KIND == 3) {
+            hipLaunchKernelGGL(k_playout_fill<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n,
                                max_plies, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid, reward,
                                terminal);
         } else {
@@ -750,9 +842,19 @@ struct Launch {
         if (stats != nullptr) return launch_stats(st, n, +1, stats, s);
         return hipSuccess;
     }
+    static hipError_t persist(const MixedArgs &a, int slots, hipStream_t s)
+    {
+        const int blocks = (slots + BLOCK - 1) / BLOCK;
+        if constexpr (G::KIND == 1 || G::KIND == 2 || G::KIND == 3) {
+            hipLaunchKernelGGL(k_persist_fill<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, a);
+        } else {
+            hipLaunchKernelGGL(k_persist_ply<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, a);
+        }
+        return hipGetLastError();
+    }
     static constexpr GameOps ops()
     {
-        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &playout};
+        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &playout, &persist};
     }
 };
 

@@ -17,6 +17,18 @@ struct DevState {
     int16_t *last_action;
 };
 
+// One game kind of a mixed persistent batch (see k_persist_ply /
+// k_persist_fill): its games are the global indices j0 + i * stride for
+// i < count, game j has id id_base + j; results go to index j.
+struct MixedArgs {
+    int64_t id_base, j0, count, stride;
+    int32_t max_plies;
+    uint32_t key0, key1;
+    int8_t *winner;
+    int16_t *plies, *last;
+    unsigned int *counter;
+};
+
 // Kernel entry points of one (game, board size), filled in by the
 // instantiation units.
 struct GameOps {
@@ -27,7 +39,12 @@ struct GameOps {
                        hipStream_t);
     hipError_t (*playout)(const DevState &, int64_t, int, uint64_t, int64_t, const int64_t *, int8_t *,
                           uint8_t *, int64_t *, hipStream_t);
+    hipError_t (*persist)(const MixedArgs &, int, hipStream_t);
 };
+
+hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s);
+hipError_t launch_mixed_stats(const int8_t *winner, const int16_t *plies, int64_t n_games, int64_t id_base,
+                              int n_kinds, int64_t *stats, hipStream_t s);
 
 // Step and outcome counters: stats[0..3] += sign * (sum of ply, number of
 // TERMINAL envs won by player 1, by player 2, drawn) over the n envs.

@@ -96,4 +96,76 @@ hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats,
     return hipGetLastError();
 }
 
+namespace {
+
+// Zero the queue counters (a kernel, not a memset, so that a captured
+// graph can replay it).
+__global__ void k_zero_counters(unsigned int *c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0u;
+}
+
+// Per-kind counters of a mixed batch: block (x, k) reduces the games of
+// kind k, i.e. the global indices j with (id_base + j) mod n_kinds == k.
+__global__ __launch_bounds__(SB) void k_mixed_stats(const int8_t *__restrict__ winner,
+                                                    const int16_t *__restrict__ plies, int64_t n_games,
+                                                    int64_t id_base, int n_kinds,
+                                                    unsigned long long *__restrict__ stats)
+{
+    const int k = blockIdx.y;
+    const int64_t j0 = ((int64_t)k - id_base % n_kinds + n_kinds) % n_kinds;
+    int64_t s = 0;
+    int w1 = 0, w2 = 0, d = 0;
+    for (int64_t j = j0 + ((int64_t)blockIdx.x * SB + threadIdx.x) * n_kinds; j < n_games;
+         j += (int64_t)gridDim.x * SB * n_kinds) {
+        s += plies[j];
+        const int w = winner[j];
+        w1 += w == 1;
+        w2 += w == 2;
+        d += w == 0;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s += __shfl_xor(s, o, 64);
+        w1 += __shfl_xor(w1, o, 64);
+        w2 += __shfl_xor(w2, o, 64);
+        d += __shfl_xor(d, o, 64);
+    }
+    __shared__ long long part[SB / 64][4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        part[wv][0] = s;
+        part[wv][1] = w1;
+        part[wv][2] = w2;
+        part[wv][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        long long v = 0;
+#pragma unroll
+        for (int q = 0; q < SB / 64; ++q) v += part[q][threadIdx.x];
+        if (v != 0) atomicAdd(&stats[4 * k + threadIdx.x], (unsigned long long)v);
+    }
+}
+
+} // namespace
+
+hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed_stats(const int8_t *winner, const int16_t *plies, int64_t n_games, int64_t id_base,
+                              int n_kinds, int64_t *stats, hipStream_t s)
+{
+    const int64_t per_kind = (n_games + n_kinds - 1) / n_kinds;
+    int64_t blocks = (per_kind + 4 * SB - 1) / (4 * SB);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 128) blocks = 128;
+    hipLaunchKernelGGL(k_mixed_stats, dim3((unsigned)blocks, (unsigned)n_kinds), dim3(SB), 0, s, winner, plies,
+                       n_games, id_base, n_kinds, reinterpret_cast<unsigned long long *>(stats));
+    return hipGetLastError();
+}
+
 } // namespace lx

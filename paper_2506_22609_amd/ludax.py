@@ -22,7 +22,9 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 
 # every symbol the public header declares
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
-           "ludax_legal_mask", "ludax_step", "ludax_playout", "ludax_state_stats", "ludax_strerror",
+           "ludax_legal_mask", "ludax_step", "ludax_playout", "ludax_state_stats",
+           "ludax_mixed_create", "ludax_mixed_destroy", "ludax_mixed_set_slots",
+           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune", "ludax_strerror",
            "ludax_last_device_error")
 
 _lock = threading.Lock()
@@ -70,13 +72,22 @@ def _load():
             L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
                                         vp]
             L.ludax_state_stats.argtypes = [vp, P(_State), ctypes.c_int32, vp, i64, vp]
+            L.ludax_mixed_create.argtypes = [vp, i32, P(vp)]
+            L.ludax_mixed_destroy.argtypes = [vp]
+            L.ludax_mixed_set_slots.argtypes = [vp, vp]
+            L.ludax_mixed_get_slots.argtypes = [vp, vp]
+            L.ludax_mixed_playout.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp, vp]
+            L.ludax_mixed_autotune.argtypes = [vp, ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp,
+                                               P(ctypes.c_float)]
             L.ludax_strerror.argtypes = [ctypes.c_int]
             L.ludax_strerror.restype = ctypes.c_char_p
             L.ludax_last_device_error.argtypes = []
             L.ludax_last_device_error.restype = ctypes.c_char_p
             for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
                          "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_playout",
-                         "ludax_state_stats"):
+                         "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy",
+                         "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
+                         "ludax_mixed_autotune"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -256,3 +267,79 @@ def state_stats(game: Game, state: State, sign: int, stats: torch.Tensor, stream
     _check(_load().ludax_state_stats(game.handle, ctypes.byref(state._c()), sign, _ptr(stats),
                                      state.n, _stream(stream)), "ludax_state_stats")
     return stats
+
+
+class MixedResult:
+    """Per-game outputs of a mixed batch (device tensors)."""
+
+    def __init__(self, n_games: int, n_kinds: int, device="cuda"):
+        self.winner = torch.empty(n_games, dtype=torch.int8, device=device)
+        self.plies = torch.empty(n_games, dtype=torch.int16, device=device)
+        self.last_action = torch.empty(n_games, dtype=torch.int16, device=device)
+        self.workspace = torch.zeros(n_kinds, dtype=torch.int32, device=device)
+
+    def _ptrs(self):
+        return _ptr(self.winner), _ptr(self.plies), _ptr(self.last_action), _ptr(self.workspace)
+
+
+class Mixed:
+    """A mixed persistent batch over several game handles: game id g has
+    kind games[g % len(games)] (see ludax_mixed_playout)."""
+
+    def __init__(self, games):
+        self.games = list(games)  # the handles must outlive this object
+        n = len(self.games)
+        arr = (ctypes.c_void_p * n)(*[g.handle.value for g in self.games])
+        h = ctypes.c_void_p()
+        _check(_load().ludax_mixed_create(arr, n, ctypes.byref(h)), "ludax_mixed_create")
+        self._h = h
+        self.n_kinds = n
+
+    @property
+    def slots(self):
+        out = (ctypes.c_int32 * self.n_kinds)()
+        _check(_load().ludax_mixed_get_slots(self._h, out), "ludax_mixed_get_slots")
+        return list(out)
+
+    @slots.setter
+    def slots(self, values):
+        arr = (ctypes.c_int32 * self.n_kinds)(*values)
+        _check(_load().ludax_mixed_set_slots(self._h, arr), "ludax_mixed_set_slots")
+
+    def _check_out(self, n_games, out):
+        if out is None:
+            out = MixedResult(n_games, self.n_kinds)
+        _need(out.winner, torch.int8, (n_games,), "winner")
+        _need(out.plies, torch.int16, (n_games,), "plies")
+        _need(out.last_action, torch.int16, (n_games,), "last_action")
+        _need(out.workspace, torch.int32, (self.n_kinds,), "workspace")
+        return out
+
+    def playout(self, seed: int, id_base: int, n_games: int, out: MixedResult | None = None,
+                stats=True, stream=None):
+        out = self._check_out(n_games, out)
+        if stats is True:
+            stats = torch.zeros((self.n_kinds, 4), dtype=torch.int64, device=out.winner.device)
+        if stats is not None:
+            _need(stats, torch.int64, (self.n_kinds, 4), "stats")
+        w, p, l, ws = out._ptrs()
+        _check(_load().ludax_mixed_playout(self._h, ctypes.c_uint64(seed & (2**64 - 1)), id_base, n_games,
+                                           w, p, l, _ptr(stats), ws, _stream(stream)),
+               "ludax_mixed_playout")
+        return out, stats
+
+    def autotune(self, seed: int, id_base: int, n_games: int, total_slots: int,
+                 out: MixedResult | None = None, stream=None) -> float:
+        out = self._check_out(n_games, out)
+        best = ctypes.c_float()
+        w, p, l, ws = out._ptrs()
+        _check(_load().ludax_mixed_autotune(self._h, ctypes.c_uint64(seed & (2**64 - 1)), id_base,
+                                            n_games, total_slots, w, p, l, ws, _stream(stream),
+                                            ctypes.byref(best)), "ludax_mixed_autotune")
+        return best.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ludax_mixed_destroy(h)
+            self._h = None

@@ -119,3 +119,20 @@ def test_strerror():
     for code in (0, -1, -2, -3, 5):
         assert isinstance(L.ludax_strerror(code), bytes) and L.ludax_strerror(code)
     assert L.ludax_last_device_error() == b""
+
+
+def test_mixed_argument_checks_need_no_gpu():
+    L = _lib()
+    out = ctypes.c_void_p()
+    assert L.ludax_mixed_create(None, 1, ctypes.byref(out)) == ludax.E_INVALID
+    rc, h = _create(3, 11, 11)
+    arr = (ctypes.c_void_p * 1)(h.value)
+    assert L.ludax_mixed_create(arr, 0, ctypes.byref(out)) == ludax.E_INVALID
+    assert L.ludax_mixed_create(arr, 9, ctypes.byref(out)) == ludax.E_INVALID
+    nulls = (ctypes.c_void_p * 2)(h.value, None)
+    assert L.ludax_mixed_create(nulls, 2, ctypes.byref(out)) == ludax.E_INVALID
+    assert L.ludax_mixed_destroy(None) == ludax.E_INVALID
+    assert L.ludax_mixed_set_slots(None, None) == ludax.E_INVALID
+    assert L.ludax_mixed_get_slots(None, None) == ludax.E_INVALID
+    assert L.ludax_mixed_playout(None, 1, 0, 10, 16, 16, 16, None, 16, None) == ludax.E_INVALID
+    L.ludax_game_destroy(h)
