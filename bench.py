@@ -65,6 +65,85 @@ def _cpu_baseline(batches, budget_s: float):
                       f"{steps} env-steps in {el:.1f} s"}
 
 
+def _mixed_section(seed: int, steps: int, warmup: int):
+    """Mixed persistent batch (Reversi 8x8, Gomoku 15x15, Hex 11x11,
+    Connect Four 6x7; game id g has kind g mod 4): 4 x 262144 game ids
+    played through 262144 slots with refill, slot split autotuned, the call
+    captured in a graph and replayed; beside it the same games as four
+    plain single-kind batches of 262144 envs (init + playout each)."""
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    mb = W.MIXED4
+    games = [ludax.Game(b.kind, b.rows, b.cols) for b in mb.kinds]
+    m = ludax.Mixed(games)
+    n = mb.n_games
+    out = ludax.MixedResult(n, len(games))
+    tune_ms = m.autotune(seed, 0, n, mb.slots, out=out)
+    stats = torch.zeros((len(games), 4), dtype=torch.int64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        m.playout(seed, 0, n, out=out, stats=stats)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        m.playout(seed, 0, n, out=out, stats=stats)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    stats.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    g_el = time.perf_counter() - t0
+    per_kind = stats.cpu().tolist()
+    g_steps = sum(r[0] for r in per_kind)
+    # eager calls with fresh game ids every step
+    stats.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        m.playout(seed, (k + 1) * n, n, out=out, stats=stats)
+    torch.cuda.synchronize()
+    e_el = time.perf_counter() - t0
+    e_steps = int(stats[:, 0].sum().item())
+    # the same games as four plain single-kind batches
+    per = n // len(games)
+    states = [ludax.State(g, per) for g in games]
+    ids = [torch.arange(k, n, len(games), dtype=torch.int64, device="cuda") for k in range(len(games))]
+    pst = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for g, s_, i in zip(games, states, ids):
+        ludax.init(g, s_)
+        ludax.playout(g, s_, seed, 0, game_id=i, stats=None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for g, s_, i in zip(games, states, ids):
+            ludax.init(g, s_)
+            ludax.playout(g, s_, seed, 0, game_id=i, stats=pst)
+    torch.cuda.synchronize()
+    p_el = time.perf_counter() - t0
+    p_steps = int(pst[0].item())
+    return {
+        "workload": f"{mb.name}: {n} game ids, kind = id mod 4 "
+                    f"({', '.join(b.name for b in mb.kinds)}), {mb.slots} slots with refill",
+        "slots_per_kind": m.slots, "autotuned_ms": tune_ms,
+        "mixed_graph_env_steps_per_s": g_steps / g_el,
+        "mixed_graph_ms_per_batch": g_el / steps * 1e3,
+        "mixed_eager_env_steps_per_s": e_steps / e_el,
+        "plain_env_steps_per_s": p_steps / p_el,
+        "plain_ms_per_batch": p_el / steps * 1e3,
+        "env_steps_per_batch": g_steps // steps,
+        "per_kind_env_steps_per_batch": [r[0] // steps for r in per_kind],
+        "note": "graph replays repeat the captured game ids; eager calls use new ids each batch",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +152,9 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed persistent batch section")
+    ap.add_argument("--mixed-steps", type=int, default=5)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB "
                          "(a known-size reference for HBM byte counters under a profiler)")
@@ -176,6 +258,8 @@ def main():
                    "envs_per_batch": batches[0].n, "seed": args.seed, "per_game": per},
         "roofline": roofline,
     }
+    if not args.no_mixed:
+        out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = _cpu_baseline(batches, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -37,3 +37,19 @@ BENCH_BATCHES = (C4_65536, HEX11_65536)
 def game_id_base(step: int, batch: Batch) -> int:
     """Distinct game ids per benchmark step: step * n."""
     return step * batch.n
+
+
+@dataclass(frozen=True)
+class MixedBatch:
+    name: str
+    kinds: tuple
+    n_games: int
+    slots: int
+
+
+# the mixed persistent batch: 4 x 262144 game ids, kind = id mod 4
+# (Reversi, Gomoku 15x15, Hex 11x11, Connect Four), 262144 slots
+MIXED4 = MixedBatch("mixed4_n1048576_slots262144",
+                    (Batch("reversi8x8", REVERSI, 8, 8, 0), Batch("gomoku15x15", GOMOKU, 15, 15, 0),
+                     Batch("hex11x11", HEX, 11, 11, 0), Batch("connect4_6x7", CONNECT_FOUR, 6, 7, 0)),
+                    4 * 262144, 262144)
