@@ -144,6 +144,109 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     }
 
 
+def _plain_step_section(batches, seed: int, reps: int):
+    """The per-ply loop with the state in HBM between plies: ludax_init,
+    then ludax_random_step launched max_plies times (the game's natural
+    bound, so every game ends inside the loop), captured in one graph per
+    batch and replayed.  Algorithmic HBM bytes: per env-step the board and
+    8 B of scalars read, 8 B of scalars + 2 B reward + 1 B terminal + the
+    1-byte board delta written (cells + 20 B); per env the init writes
+    cells + 8 B.  The replay time includes the launches of the tail, when
+    few games are still running, and the gaps between graph nodes."""
+    import torch
+    from paper_2506_22609_amd import ludax
+
+    out = {}
+    for b in batches:
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        s = ludax.State(g, b.n)
+        r = torch.empty((b.n, 2), dtype=torch.int8, device="cuda")
+        t = torch.empty(b.n, dtype=torch.uint8, device="cuda")
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        base = 7 * b.n
+
+        def loop():
+            ludax.init(g, s)
+            for _ in range(g.max_plies):
+                ludax.random_step(g, s, seed, base, reward=r, terminal=t)
+
+        # eager run bracketed by the counters: env-steps of one loop
+        ludax.init(g, s)
+        ludax.state_stats(g, s, -1, st)
+        for _ in range(g.max_plies):
+            ludax.random_step(g, s, seed, base, reward=r, terminal=t)
+        ludax.state_stats(g, s, +1, st)
+        torch.cuda.synchronize()
+        steps = int(st[0].item())
+        running_after = int((s.status == 0).sum().item())
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            loop()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            loop()
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            graph.replay()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        alg = steps * (g.cells + 20) + b.n * (g.cells + 8)
+        out[b.name] = {"launches": g.max_plies, "env_steps": steps, "ms_per_loop": el * 1e3,
+                       "env_steps_per_s": steps / el, "alg_bytes_per_env_step": g.cells + 20,
+                       "alg_bytes_per_loop": alg, "achieved_GBs": alg / el / 1e9,
+                       "hbm_frac": alg / el / 1e9 / HBM_PEAK_GBS,
+                       "still_running_after_loop": running_after}
+        del graph, s
+        torch.cuda.synchronize()
+    return out
+
+
+def _large_section(batches, seed: int, reps: int):
+    """Plain fused playouts (ludax_init + ludax_playout) of the large
+    single-game batches, the playout kernel timed with events."""
+    import torch
+    from paper_2506_22609_amd import ludax
+
+    out = {}
+    for b in batches:
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        s = ludax.State(g, b.n)
+        r = torch.empty((b.n, 2), dtype=torch.int8, device="cuda")
+        t = torch.empty(b.n, dtype=torch.uint8, device="cuda")
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ludax.init(g, s)
+        ludax.playout(g, s, seed, 0, reward=r, terminal=t, stats=None)
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for k in range(reps):
+            ludax.init(g, s)
+            ludax.state_stats(g, s, -1, st)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ludax.playout(g, s, seed, (k + 1) * b.n, reward=r, terminal=t, stats=None)
+            e1.record()
+            evs.append((e0, e1))
+            ludax.state_stats(g, s, +1, st)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        kern = sum(a.elapsed_time(c) for a, c in evs) / reps / 1e3
+        v = st.cpu().tolist()
+        out[b.name] = {"env_steps_per_batch": v[0] // reps, "games_per_batch": b.n,
+                       "ms_per_batch": el * 1e3, "playout_kernel_ms": kern * 1e3,
+                       "env_steps_per_s": v[0] / reps / el, "playouts_per_s": b.n / el,
+                       "mean_plies": v[0] / reps / b.n,
+                       "p1_wins": v[1], "p2_wins": v[2], "draws": v[3]}
+        del s
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,6 +258,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed persistent batch section")
     ap.add_argument("--mixed-steps", type=int, default=5)
+    ap.add_argument("--no-plain-step", action="store_true",
+                    help="skip the per-ply (ludax_random_step loop) section")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 19x19 large-board section")
+    ap.add_argument("--section-reps", type=int, default=3)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB "
                          "(a known-size reference for HBM byte counters under a profiler)")
@@ -236,7 +344,7 @@ def main():
     achieved = ops / kern_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                 "frac": achieved / VALU_PEAK_TOPS, "traffic": HEX_TRAFFIC_BYTES,
-                "kernel": f"k_playout_hex<11> ({dominant})",
+                "kernel": f"k_playout_fill<Hex<11>> ({dominant})",
                 "ops_per_env_step": VALU_OPS_PER_STEP[dominant],
                 "env_steps_per_launch": steps_per_launch,
                 "hbm_frac": HEX_TRAFFIC_BYTES / kern_s / 1e9 / HBM_PEAK_GBS}
@@ -260,6 +368,11 @@ def main():
     }
     if not args.no_mixed:
         out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
+    if not args.no_plain_step:
+        out["plain_step"] = _plain_step_section(
+            tuple(batches) + (() if args.no_large else W.LARGE_BATCHES), args.seed, args.section_reps)
+    if not args.no_large:
+        out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = _cpu_baseline(batches, args.cpu_seconds)
     print(json.dumps(out), flush=True)

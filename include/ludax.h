@@ -164,6 +164,19 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed,
                   int64_t game_id_base, const int64_t *game_id, int8_t *reward,
                   uint8_t *terminal, int64_t *stats, int64_t n, hipStream_t stream);
 
+/* One ply of the uniform-random policy of ludax_playout for every
+ * environment (Sec. 6), with the state left in HBM between calls: a
+ * RUNNING env draws the action of its current ply exactly as
+ * ludax_playout does (same Philox word, same k-th legal action) and steps
+ * as ludax_step does; a RUNNING env with no legal action is set ILLEGAL.
+ * Repeating the call until no env is RUNNING gives the same states as one
+ * ludax_playout with the same seed and game ids.  reward [n][2] and
+ * terminal [n] as in ludax_step (an env that was not RUNNING: 0/0 and 1);
+ * game ids as in ludax_playout. */
+int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed,
+                      int64_t game_id_base, const int64_t *game_id, int8_t *reward,
+                      uint8_t *terminal, int64_t n, hipStream_t stream);
+
 /* Counter reduction used by ludax_playout's stats, exposed on its own:
  * stats[0..3] += sign * (sum of ply, number of TERMINAL envs won by player
  * 1, won by player 2, drawn) over the n envs; sign is +1 or -1.  Calling

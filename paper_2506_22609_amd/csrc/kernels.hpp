@@ -10,8 +10,8 @@
 //
 //   k_init     start positions, 16-byte stores
 //   k_mask     legal mask [n][A], staged through LDS for coalesced stores
-//   k_step     one ply per env for a caller-chosen action; board delta
-//              written in place, optional next mask
+//   k_step     one ply per env for a caller-chosen action (or the uniform
+//              random one); board delta written in place, optional next mask
 //   k_playout  the whole uniform-random game in registers: mask -> Philox
 //              -> k-th legal action -> apply -> end rules, until every lane
 //              of the wave has ended; final board written back through LDS
@@ -168,11 +168,18 @@ __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t 
 }
 
 // ---------------------------------------------------------------------------
-// a4-a6 for a given action: ludax_step
+// a4-a6 for one ply: ludax_step (caller-chosen action, RANDOM = false) and
+// ludax_random_step (the uniform-random action of a3, RANDOM = true).  The
+// state stays in HBM between launches, so this kernel is bound by its bytes:
+// the block's statuses are read first and a block with no RUNNING env reads
+// no board; only envs that were RUNNING write their scalars back, and a
+// placement writes the one cell it changed (Reversi: the whole 64-cell board).
 // ---------------------------------------------------------------------------
-template <class G>
+template <class G, bool RANDOM>
 __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_plies,
-                                                const int32_t *__restrict__ action,
+                                                const int32_t *__restrict__ action, uint32_t key0,
+                                                uint32_t key1, int64_t gid_base,
+                                                const int64_t *__restrict__ gid,
                                                 int8_t *__restrict__ reward,
                                                 uint8_t *__restrict__ terminal,
                                                 uint8_t *__restrict__ next_mask)
@@ -181,27 +188,58 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
     __shared__ __align__(16) int8_t lds[BLOCK * LB];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
-    stage_in<G::CELLS>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
-
     const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
+    int status = valid ? (int)st.status[ec] : ILLEGAL;
+    const bool was_running = status == RUNNING;
+
+    if (!__syncthreads_or(was_running)) {
+        // nothing to play in this block: every env is a no-op
+        if (valid) {
+            reward[2 * e] = 0;
+            reward[2 * e + 1] = 0;
+            terminal[e] = 1;
+        }
+        if (next_mask != nullptr) {
+            uint8_t *dst = next_mask + e0 * G::A;
+            const int bytes = nb * G::A, full = bytes >> 4;
+            for (int j = t; j < full; j += BLOCK) reinterpret_cast<uint4 *>(dst)[j] = uint4{0u, 0u, 0u, 0u};
+            for (int j = (full << 4) + t; j < bytes; j += BLOCK) dst[j] = 0;
+        }
+        return;
+    }
+
+    stage_in<G::CELLS>(st.board, e0, nb, lds);
     BB<G::NWC> c1, c2;
     read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
     G g;
     g.load(c1, c2);
-    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
+    int me = st.to_move[ec], winner = st.winner[ec];
     int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
-    const int a = action[ec];
-    int r1 = 0, r2 = 0;
+    int r1 = 0, r2 = 0, a = 0;
     bool changed = false;
-    if (valid && status == RUNNING) {
+    if (was_running) {
         const typename G::M m = g.placements(me);
-        const bool is_pass = G::HAS_PASS && a == G::A - 1;
-        bool legal;
-        if (is_pass) legal = !any(m);
-        else legal = a >= 0 && a < G::CELLS && test_bit(m, G::bit_of(a));
+        bool legal, is_pass;
+        if constexpr (RANDOM) {
+            // the ply's word of the game's Philox stream, k-th legal action
+            const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
+            const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
+            const int r = ply & 3;
+            const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
+            const int np = popcount(m);
+            is_pass = G::HAS_PASS && np == 0;
+            legal = np > 0 || is_pass; // a hand-edited board may leave no action
+            if (np > 0) a = G::action_of(select_bit(m, (int)__umulhi(w, (uint32_t)np)));
+            if (is_pass) a = G::A - 1;
+        } else {
+            a = action[ec];
+            is_pass = G::HAS_PASS && a == G::A - 1;
+            if (is_pass) legal = !any(m);
+            else legal = a >= 0 && a < G::CELLS && test_bit(m, G::bit_of(a));
+        }
         if (!legal) {
             status = ILLEGAL;
         } else {
@@ -230,12 +268,14 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
         }
     }
     if (valid) {
-        st.to_move[e] = (int8_t)me;
-        st.status[e] = (int8_t)status;
-        st.winner[e] = (int8_t)winner;
-        st.passes[e] = (int8_t)passes;
-        st.ply[e] = (int16_t)ply;
-        st.last_action[e] = (int16_t)last;
+        if (was_running) {
+            st.to_move[e] = (int8_t)me;
+            st.status[e] = (int8_t)status;
+            st.winner[e] = (int8_t)winner;
+            st.passes[e] = (int8_t)passes;
+            st.ply[e] = (int16_t)ply;
+            st.last_action[e] = (int16_t)last;
+        }
         reward[2 * e] = (int8_t)r1;
         reward[2 * e + 1] = (int8_t)r2;
         terminal[e] = status != RUNNING ? 1 : 0;
@@ -819,8 +859,18 @@ struct Launch {
                            int8_t *reward, uint8_t *terminal, uint8_t *next_mask, hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL(k_step<G>, dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
-                           action, reward, terminal, next_mask);
+        hipLaunchKernelGGL((k_step<G, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                           action, 0u, 0u, (int64_t)0, (const int64_t *)nullptr, reward, terminal, next_mask);
+        return hipGetLastError();
+    }
+    static hipError_t random_step(const DevState &st, int64_t n, int max_plies, uint64_t seed,
+                                  int64_t gid_base, const int64_t *gid, int8_t *reward, uint8_t *terminal,
+                                  hipStream_t s)
+    {
+        const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+        hipLaunchKernelGGL((k_step<G, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                           (const int32_t *)nullptr, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid,
+                           reward, terminal, (uint8_t *)nullptr);
         return hipGetLastError();
     }
     static hipError_t playout(const DevState &st, int64_t n, int max_plies, uint64_t seed,
@@ -854,7 +904,7 @@ struct Launch {
     }
     static constexpr GameOps ops()
     {
-        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &playout, &persist};
+        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &playout, &persist};
     }
 };
 

@@ -33,6 +33,12 @@ GOMOKU15_65536 = Batch("gomoku15x15_n65536", GOMOKU, 15, 15, 65536)
 
 BENCH_BATCHES = (C4_65536, HEX11_65536)
 
+# large boards: Hex 19x19 and Gomoku 19x19, 524288 envs each (1,048,576
+# envs, 378.5 MB of int8 boards)
+HEX19_524288 = Batch("hex19x19_n524288", HEX, 19, 19, 524288)
+GOMOKU19_524288 = Batch("gomoku19x19_n524288", GOMOKU, 19, 19, 524288)
+LARGE_BATCHES = (HEX19_524288, GOMOKU19_524288)
+
 
 def game_id_base(step: int, batch: Batch) -> int:
     """Distinct game ids per benchmark step: step * n."""

@@ -97,6 +97,11 @@ def test_host_argument_checks_need_no_gpu():
     assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, None, 16, None, 1, s) == ludax.E_INVALID
     assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, None, None, 1, s) == ludax.E_INVALID
     assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, 16, None, 2**31, s) == ludax.E_INVALID
+    assert L.ludax_random_step(h, ctypes.byref(st), 1, 0, None, None, 16, 1, s) == ludax.E_INVALID
+    assert L.ludax_random_step(h, ctypes.byref(st), 1, 0, None, 16, None, 1, s) == ludax.E_INVALID
+    assert L.ludax_random_step(h, ctypes.byref(odd_board), 1, 0, None, 16, 16, 1, s) == ludax.E_INVALID
+    assert L.ludax_random_step(None, ctypes.byref(st), 1, 0, None, 16, 16, 1, s) == ludax.E_INVALID
+    assert L.ludax_random_step(h, ctypes.byref(st), 1, 0, None, 16, 16, -1, s) == ludax.E_INVALID
     # n = 0 is a no-op that launches nothing, whatever the buffers are
     assert L.ludax_init(h, ctypes.byref(st), 0, s) == 0
     assert L.ludax_init(h, None, 0, s) == 0
@@ -106,6 +111,7 @@ def test_host_argument_checks_need_no_gpu():
     assert L.ludax_step(h, None, None, None, None, None, 0, s) == 0
     assert L.ludax_playout(h, ctypes.byref(st), 1, 0, None, 16, 16, None, 0, s) == 0
     assert L.ludax_playout(h, None, 1, 0, None, None, None, None, 0, s) == 0
+    assert L.ludax_random_step(h, None, 1, 0, None, None, None, 0, s) == 0
     assert L.ludax_state_stats(h, ctypes.byref(st), 1, None, 1, s) == ludax.E_INVALID
     assert L.ludax_state_stats(h, ctypes.byref(st), 2, 16, 1, s) == ludax.E_INVALID
     assert L.ludax_state_stats(h, ctypes.byref(st), 0, 16, 1, s) == ludax.E_INVALID

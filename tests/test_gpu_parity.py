@@ -206,3 +206,86 @@ def test_state_stats_brackets_equal_playout_stats(g):
     ludax.state_stats(dg, d2, +1, st2)
     assert (st2.cpu() - 5).tolist() == st1.cpu().tolist()
     assert_same_state(from_device(d1), from_device(d2))
+
+
+def _oracle_random_step(og, s, seed, gid):
+    """One ply of the oracle's uniform-random policy: the ply's Philox word,
+    k = (w * n_legal) >> 32, the k-th legal action, then the oracle's step
+    (an env with no legal action gets action -1, i.e. ILLEGAL)."""
+    m = ref.legal_mask(og, s)
+    a = np.full(s.n, -1, np.int32)
+    for i in np.flatnonzero(s.status == ref.RUNNING):
+        idx = np.flatnonzero(m[i])
+        if idx.size:
+            w = ref.draw(seed, int(gid[i]), int(s.ply[i]))
+            a[i] = idx[(w * idx.size) >> 32]
+    rew, term, _ = ref.step(og, s, a, want_mask=False)
+    return rew, term
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_random_step_sequences(g):
+    """ludax_random_step ply by ply against the oracle's draw + step, from
+    mid-game states (whole blocks of ended envs, ILLEGAL ones, a ragged
+    tail) with explicit game ids, until every env has ended."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(31 + g[0] * 7 + g[1])
+    n = 333
+    s = random_states(og, n, min(og.cells, 30), rng)
+    s.status[:128] = ref.ILLEGAL  # two workgroups with nothing to play
+    s.status[200::13] = ref.ILLEGAL
+    gid = rng.integers(0, 2**62, size=n, dtype=np.int64)
+    d = to_device(dg, s)
+    dgid = torch.from_numpy(gid).cuda()
+    seed = 0x1234_5678_9ABC_DEF0 + g[0]
+    for p in range(og.cells + 130):
+        rew, term = _oracle_random_step(og, s, seed, gid)
+        grew, gterm = ludax.random_step(dg, d, seed, game_id=dgid)
+        assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
+        assert np.array_equal(term, gterm.cpu().numpy()), f"terminal at ply {p}"
+        assert_same_state(s, from_device(d), f"random step {p}")
+        if (s.status != ref.RUNNING).all():
+            break
+    assert (s.status != ref.RUNNING).all()
+
+
+@pytest.mark.parametrize("g", GAMES, ids=IDS)
+def test_random_step_loop_equals_playout(g):
+    """Repeating ludax_random_step until nothing runs reproduces the
+    oracle's whole playout with the same seed and game ids."""
+    og, dg = pair(*g)
+    n = 517 if og.cells <= 121 else 150
+    s = ref.init(og, n)
+    _, _, stats = ref.playout(og, s, 5, 1000, threads=8)
+    d = ludax.State(dg, n)
+    ludax.init(dg, d)
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ludax.state_stats(dg, d, -1, st)
+    for _ in range(og.cells + 130):
+        _, term = ludax.random_step(dg, d, 5, 1000)
+        if bool(term.all()):
+            break
+    ludax.state_stats(dg, d, +1, st)
+    assert_same_state(s, from_device(d), "random-step loop")
+    assert np.array_equal(stats, st.cpu().numpy())
+
+
+@pytest.mark.parametrize("g", GAMES[:5], ids=IDS[:5])
+def test_step_blocks_without_running_env(g):
+    """ludax_step on a batch whose first workgroups hold only ended envs
+    (the kernel skips their boards): rewards, terminal flags, the next
+    mask and the states still match the oracle."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(41)
+    n = 300
+    s = random_states(og, n, 8, rng)
+    s.status[:192] = ref.ILLEGAL
+    s.status[256:] = ref.ILLEGAL
+    d = to_device(dg, s)
+    m = ref.legal_mask(og, s)
+    a = np.array([np.flatnonzero(r)[0] if r.any() else 0 for r in m], np.int32)
+    rew, term, nm = ref.step(og, s, a)
+    grew, gterm, gnm = ludax.step(dg, d, torch.from_numpy(a).cuda())
+    assert np.array_equal(rew, grew.cpu().numpy()) and np.array_equal(term, gterm.cpu().numpy())
+    assert np.array_equal(nm, gnm.cpu().numpy())
+    assert_same_state(s, from_device(d))
