@@ -59,3 +59,39 @@ MIXED4 = MixedBatch("mixed4_n1048576_slots262144",
                     (Batch("reversi8x8", REVERSI, 8, 8, 0), Batch("gomoku15x15", GOMOKU, 15, 15, 0),
                      Batch("hex11x11", HEX, 11, 11, 0), Batch("connect4_6x7", CONNECT_FOUR, 6, 7, 0)),
                     4 * 262144, 262144)
+
+
+# ---------------------------------------------------------------------------
+# the policy/value network: seeded initial parameters and the training set
+# ---------------------------------------------------------------------------
+NET_CHANNELS = 64
+NET_LAYERS = 4
+
+
+def net_param_shapes():
+    """Flat parameter order: W1 [64][3][3][3], b1, W2..W4 [64][64][3][3]
+    with their biases, wp [64], bp [1], wv [64], bv [1]."""
+    C = NET_CHANNELS
+    shapes = [(C, 3, 3, 3), (C,)]
+    for _ in range(NET_LAYERS - 1):
+        shapes += [(C, C, 3, 3), (C,)]
+    return shapes + [(C,), (1,), (C,), (1,)]
+
+
+def init_net_params(seed: int):
+    """He-uniform conv weights (bound sqrt(6 / fan_in)), small positive conv
+    biases, small uniform head weights, zero head biases; float32."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in net_param_shapes():
+        if len(shape) == 4:
+            a = float(np.sqrt(6.0 / (shape[1] * 9)))
+            parts.append(rng.uniform(-a, a, shape))
+        elif shape == (NET_CHANNELS,) and len(parts) < 2 * NET_LAYERS:
+            parts.append(np.full(shape, 0.01))
+        elif shape == (NET_CHANNELS,):
+            parts.append(rng.uniform(-0.125, 0.125, shape))
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)

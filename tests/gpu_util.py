@@ -4,6 +4,7 @@ import numpy as np
 import torch
 
 from oracle import ref
+from tests.oracle_util import random_states  # noqa: F401 (re-exported)
 from paper_2506_22609_amd import ludax
 
 FIELDS = ("board", "to_move", "status", "winner", "passes", "ply", "last_action")
@@ -33,26 +34,3 @@ def assert_same_state(a: "ref.State", b: "ref.State", where=""):
             i = bad[0][0]
             raise AssertionError(f"{where}: field {f} differs at env {i} "
                                  f"(oracle {x[i]}, gpu {y[i]}); {len(bad)} mismatches")
-
-
-def random_states(game, n, plies, rng, illegal_every=0):
-    """Reachable states: the oracle's start position plus up to `plies`
-    uniformly chosen legal plies per env (a different count per env)."""
-    s = ref.init(game, n)
-    target = rng.integers(0, plies + 1, size=n)
-    for p in range(plies):
-        m = ref.legal_mask(game, s)
-        a = np.zeros(n, np.int32)
-        for i in range(n):
-            idx = np.flatnonzero(m[i])
-            if idx.size:
-                a[i] = idx[rng.integers(0, idx.size)]
-        live = (target > p) & (s.status == ref.RUNNING)
-        if not live.any():
-            break
-        sub = np.flatnonzero(live)
-        ss = s.subset(sub)
-        ref.step(game, ss, a[sub], want_mask=False)
-        for f in FIELDS:
-            getattr(s, f)[sub] = getattr(ss, f)
-    return s

@@ -34,3 +34,26 @@ def random_legal_actions(mask, rng):
 
 def board2d(game, s, i=0):
     return s.board[i].reshape(game.rows, game.cols)
+
+
+def random_states(game, n, plies, rng, illegal_every=0):
+    """Reachable states: the oracle's start position plus up to `plies`
+    uniformly chosen legal plies per env (a different count per env)."""
+    s = ref.init(game, n)
+    target = rng.integers(0, plies + 1, size=n)
+    for p in range(plies):
+        m = ref.legal_mask(game, s)
+        a = np.zeros(n, np.int32)
+        for i in range(n):
+            idx = np.flatnonzero(m[i])
+            if idx.size:
+                a[i] = idx[rng.integers(0, idx.size)]
+        live = (target > p) & (s.status == ref.RUNNING)
+        if not live.any():
+            break
+        sub = np.flatnonzero(live)
+        ss = s.subset(sub)
+        ref.step(game, ss, a[sub], want_mask=False)
+        for f in ref.State.FIELDS:
+            getattr(s, f)[sub] = getattr(ss, f)
+    return s
