@@ -233,6 +233,73 @@ int ludax_mixed_autotune(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int
                          int32_t total_slots, int8_t *winner, int16_t *plies, int16_t *last_action,
                          uint32_t *workspace, hipStream_t stream, float *best_ms);
 
+/* ------------------------------------------------------------------------
+ * Policy/value network (the learned part; the paper trains policy/value
+ * agents on its environments in Sec. 7 with a ResNet, this is a small
+ * convolutional one).  For an N x N board, N = 11 or 19:
+ *   planes   3 planes in the mover's frame (the mover's stones, the
+ *            opponent's, the empty cells); for player 2 the board is
+ *            transposed and the colours exchanged (the Hex symmetry that
+ *            maps player 2's left-right goal onto top-bottom);
+ *   trunk    4 x (3x3 convolution, zero padding, 64 channels, ReLU);
+ *   policy   one logit per cell (1x1 convolution);
+ *   value    tanh(wv . (channel means) + bv), the expected outcome for the
+ *            mover.
+ * Conv weights and activations are bfloat16 (round to nearest even), every
+ * sum float32, the heads float32.
+ * params: float32 [n_params], in this order: W1 [64][3][3][3] (out, in,
+ * row, column), b1 [64], W2..W4 [64][64][3][3] each followed by its bias
+ * [64], wp [64], bp [1], wv [64], bv [1].
+ * packed: a device buffer of packed_bytes holding the bfloat16 copies the
+ * kernels read; ludax_net_pack (or ludax_net_adam) rewrites it from params.
+ * workspace: a device buffer of at least ludax_net_workspace_bytes(n,
+ * training) bytes, 256-byte aligned; its contents need not persist between
+ * calls.  Calls on one stream may share it; calls that overlap on several
+ * streams need one each.
+ * ------------------------------------------------------------------------ */
+typedef struct ludax_net ludax_net;
+
+int ludax_net_create(int32_t rows, int32_t cols, ludax_net **out);
+int ludax_net_destroy(ludax_net *net);
+int ludax_net_info(const ludax_net *net, int64_t *n_params, int64_t *packed_bytes);
+int ludax_net_workspace_bytes(const ludax_net *net, int64_t n, int32_t training, int64_t *bytes);
+int ludax_net_pack(const ludax_net *net, const float *params, void *packed, hipStream_t stream);
+
+/* Forward pass of n positions (board [n][N*N] int8 and to_move [n] int8, as
+ * in ludax_state; to_move must be 1 or 2).  logits [n][N*N] float32 in
+ * ACTION order (the cells of the board, not of the mover's frame); value
+ * [n] float32, for the mover. */
+int ludax_net_forward(const ludax_net *net, const float *params, const void *packed, const int8_t *board,
+                      const int8_t *to_move, int64_t n, float *logits, float *value, void *workspace,
+                      hipStream_t stream);
+
+/* Loss and gradient of a batch of n samples (position, action[i] = the cell
+ * played in it, which must be empty, z[i] = the final outcome for the mover,
+ * +1 / 0 / -1):
+ *   L = (1/n) sum_i (v_i - z_i)^2 + beta (z_i - v_i) (-log pi_i[action_i])
+ * where pi_i is the softmax of the logits over the empty cells and the
+ * factor (z_i - v_i) of the second term is held constant.  loss [2] float32
+ * receives the two parts; grads [n_params] float32 is overwritten with dL /
+ * d(params).  Gradients of the trunk flow through bfloat16: each layer's
+ * pre-activation gradient is rounded to bfloat16 before it multiplies
+ * anything.  n >= 1. */
+int ludax_net_loss_grad(const ludax_net *net, const float *params, const void *packed, const int8_t *board,
+                        const int8_t *to_move, const int16_t *action, const float *z, int64_t n, float beta,
+                        float *loss, float *grads, void *workspace, hipStream_t stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected, step >= 1) on params with the
+ * moments m, v [n_params] float32; then repacks into packed (if not NULL). */
+int ludax_net_adam(const ludax_net *net, float *params, const float *grads, float *m, float *v, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *packed, hipStream_t stream);
+
+/* Value cutoff: an estimate of each env's final outcome for player 1.  A
+ * TERMINAL env gives its result (+1 player 1 won, -1 player 2 won, 0 draw),
+ * a RUNNING one the network's value mapped to player 1 (v if player 1 is
+ * to move, else -v), any other status 0.  The board must be game's size
+ * (rows = cols = N of the net). */
+int ludax_net_estimate(const ludax_net *net, const float *params, const void *packed, const ludax_state *state,
+                       int64_t n, float *estimate, void *workspace, hipStream_t stream);
+
 /* Text of a return code; never NULL. */
 const char *ludax_strerror(int code);
 

@@ -456,6 +456,100 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
     return LUDAX_OK;
 }
 
+struct ludax_net {
+    int32_t n;
+};
+
+int ludax_net_create(int32_t rows, int32_t cols, ludax_net **out)
+{
+    if (out == nullptr) return LUDAX_E_INVALID;
+    *out = nullptr;
+    if (rows != cols || !lx::net_size_supported(rows)) return LUDAX_E_UNSUPPORTED;
+    ludax_net *h = new (std::nothrow) ludax_net{rows};
+    if (h == nullptr) return LUDAX_E_INVALID;
+    *out = h;
+    return LUDAX_OK;
+}
+
+int ludax_net_destroy(ludax_net *net)
+{
+    delete net;
+    return LUDAX_OK;
+}
+
+int ludax_net_info(const ludax_net *net, int64_t *n_params, int64_t *packed_bytes)
+{
+    if (net == nullptr) return LUDAX_E_INVALID;
+    if (n_params) *n_params = lx::net_n_params();
+    if (packed_bytes) *packed_bytes = lx::net_packed_bytes();
+    return LUDAX_OK;
+}
+
+int ludax_net_workspace_bytes(const ludax_net *net, int64_t n, int32_t training, int64_t *bytes)
+{
+    if (net == nullptr || bytes == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    *bytes = training ? lx::net_train_ws_bytes(net->n, n) : lx::net_forward_ws_bytes(net->n, n);
+    return LUDAX_OK;
+}
+
+namespace {
+bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+} // namespace
+
+int ludax_net_pack(const ludax_net *net, const float *params, void *packed, hipStream_t stream)
+{
+    if (net == nullptr || params == nullptr || packed == nullptr || !aligned16(packed)) return LUDAX_E_INVALID;
+    return device_error(lx::net_pack(params, packed, stream));
+}
+
+int ludax_net_forward(const ludax_net *net, const float *params, const void *packed, const int8_t *board,
+                      const int8_t *to_move, int64_t n, float *logits, float *value, void *workspace,
+                      hipStream_t stream)
+{
+    if (net == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (n == 0) return LUDAX_OK;
+    if (params == nullptr || packed == nullptr || !aligned16(packed) || board == nullptr || to_move == nullptr ||
+        logits == nullptr || value == nullptr || workspace == nullptr || !aligned256(workspace))
+        return LUDAX_E_INVALID;
+    return device_error(lx::net_forward(net->n, params, packed, board, to_move, n, logits, value, workspace, stream));
+}
+
+int ludax_net_loss_grad(const ludax_net *net, const float *params, const void *packed, const int8_t *board,
+                        const int8_t *to_move, const int16_t *action, const float *z, int64_t n, float beta,
+                        float *loss, float *grads, void *workspace, hipStream_t stream)
+{
+    if (net == nullptr || n < 1 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (params == nullptr || packed == nullptr || !aligned16(packed) || board == nullptr || to_move == nullptr ||
+        action == nullptr || z == nullptr || loss == nullptr || grads == nullptr || workspace == nullptr ||
+        !aligned256(workspace))
+        return LUDAX_E_INVALID;
+    return device_error(lx::net_loss_grad(net->n, params, packed, board, to_move, action, z, n, beta, loss, grads,
+                                          workspace, stream));
+}
+
+int ludax_net_adam(const ludax_net *net, float *params, const float *grads, float *m, float *v, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *packed, hipStream_t stream)
+{
+    if (net == nullptr || params == nullptr || grads == nullptr || m == nullptr || v == nullptr || step < 1 ||
+        !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || (packed && !aligned16(packed)))
+        return LUDAX_E_INVALID;
+    return device_error(lx::net_adam(params, grads, m, v, step, lr, beta1, beta2, eps, packed, stream));
+}
+
+int ludax_net_estimate(const ludax_net *net, const float *params, const void *packed, const ludax_state *state,
+                       int64_t n, float *estimate, void *workspace, hipStream_t stream)
+{
+    if (net == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (n == 0) return LUDAX_OK;
+    lx::DevState d;
+    int rc = check_state(state, &d);
+    if (rc) return rc;
+    if (params == nullptr || packed == nullptr || !aligned16(packed) || estimate == nullptr ||
+        workspace == nullptr || !aligned256(workspace))
+        return LUDAX_E_INVALID;
+    return device_error(lx::net_estimate(net->n, params, packed, d, n, estimate, workspace, stream));
+}
+
 const char *ludax_strerror(int code)
 {
     switch (code) {

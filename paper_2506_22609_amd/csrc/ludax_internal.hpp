@@ -52,6 +52,25 @@ hipError_t launch_mixed_stats(const int8_t *winner, const int16_t *plies, int64_
 // TERMINAL envs won by player 1, by player 2, drawn) over the n envs.
 hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats, hipStream_t s);
 
+// The policy/value network (net.hip); N = board side, 11 or 19.
+int64_t net_n_params();
+int64_t net_packed_bytes();
+bool net_size_supported(int N);
+int64_t net_forward_ws_bytes(int N, int64_t n);
+int64_t net_train_ws_bytes(int N, int64_t n);
+hipError_t net_pack(const float *params, void *packed, hipStream_t s);
+hipError_t net_forward(int N, const float *params, const void *packed, const int8_t *board, const int8_t *to_move,
+                       int64_t n, float *logits, float *value, void *ws, hipStream_t s);
+hipError_t net_loss_grad(int N, const float *params, const void *packed, const int8_t *board,
+                         const int8_t *to_move, const int16_t *action, const float *z, int64_t n, float beta,
+                         float *loss, float *grads, void *ws, hipStream_t s);
+// estimate [n] = outcome for player 1 (TERMINAL), +-value (RUNNING), 0 else;
+// workspace: forward size plus n * (N * N + 1) floats
+hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,
+                        float *estimate, void *ws, hipStream_t s);
+hipError_t net_adam(float *params, const float *grads, float *m, float *v, int step, float lr, float b1, float b2,
+                    float eps, void *packed, hipStream_t s);
+
 // Lookup per game kind; NULL when the size is not supported.
 const GameOps *ops_tictactoe(int rows, int cols);
 const GameOps *ops_connect_four(int rows, int cols);

@@ -1,0 +1,802 @@
+// net.hip -- the small convolutional policy/value network on bf16 MFMA.
+//
+// Network (the model of the paper's "Trained Agents" section made small):
+// 3 mover-frame planes -> 4 x (conv3x3, 64 channels, ReLU) -> a policy head
+// (a 1x1 convolution to one logit per cell) and a value head (tanh of a
+// linear map of the channel means).  Conv weights and activations are
+// bfloat16, every sum is float32; the heads are float32.
+//
+// Activation layout: NHWC with a zero ring, [n][N+2][N+2][C] bf16, so a 3x3
+// tap is a plain pointer offset and needs no bounds test.  The first layer's
+// input has C = 4 (mover, opponent, empty, zero).
+//
+// Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16: M = the cells of
+// one board (16-cell tiles, up to 8 tiles per wave), N = 64 output channels
+// (4 tiles), K = 9 taps x C input channels.  A wave owns one (board, group of
+// 8 cell tiles) and keeps 8 x 4 accumulator tiles in registers; the block's
+// weights ([64][K] bf16, rows padded by 8 elements) sit in LDS and are
+// shared by the block's four waves.  The same kernel computes the gradient
+// with respect to the input (the transposed convolution is a convolution of
+// dZ with the weights flipped in space and with input and output channels
+// exchanged), masked by the ReLU of the layer below.
+//
+// Weight gradients: dW[o][i][t] = sum over boards and cells of dZ[p][o] x
+// X[p + tap t][i]: M = 64 output channels, N = (tap, input channel), K =
+// cells, on the same MFMA; each block stages one board at a time in LDS
+// (dZ transposed so a fragment is one 16-byte read) and accumulates over its
+// share of the batch; per-block partial sums are added by a second kernel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "ludax_internal.hpp"
+
+namespace lx {
+namespace net {
+
+constexpr int C = 64;
+constexpr int WAVE = 64;
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest, ties to even (finite values)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// ---------------------------------------------------------------------------
+// parameter offsets in the flat float32 vector
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int64_t w_off(int l) // l = 1..4
+{
+    return l == 1 ? 0 : (int64_t)(C * 27 + C) + (int64_t)(l - 2) * (C * C * 9 + C);
+}
+__host__ __device__ constexpr int64_t b_off(int l) { return w_off(l) + (l == 1 ? C * 27 : C * C * 9); }
+constexpr int64_t WP_OFF = (int64_t)(C * 27 + C) + 3 * (int64_t)(C * C * 9 + C);
+constexpr int64_t BP_OFF = WP_OFF + C;
+constexpr int64_t WV_OFF = BP_OFF + 1;
+constexpr int64_t BV_OFF = WV_OFF + C;
+constexpr int64_t N_PARAMS = BV_OFF + 1;
+static_assert(N_PARAMS == 112706, "parameter count");
+
+// Packed bf16 weights: forward [64 out][K] with k = tap * C_in + in (layer 1:
+// C_in = 4, the fourth channel zero, K padded to 64), then for layers 2..4
+// the data-gradient weights [64 in][576] with k = tap' * 64 + out and
+// tap' = 8 - tap.
+constexpr int K1 = 64, K2 = 576;
+__host__ __device__ constexpr int64_t pf_off(int l) { return l == 1 ? 0 : (int64_t)C * K1 + (int64_t)(l - 2) * C * K2; }
+__host__ __device__ constexpr int64_t pb_off(int l) { return (int64_t)C * K1 + 3 * (int64_t)C * K2 + (int64_t)(l - 2) * C * K2; }
+constexpr int64_t PACKED_ELEMS = (int64_t)C * K1 + 6 * (int64_t)C * K2;
+
+__global__ void k_pack(const float *__restrict__ p, uint16_t *__restrict__ out)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < PACKED_ELEMS;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        if (j < C * K1) {
+            const int o = (int)(j / K1), k = (int)(j % K1), t = k >> 2, i = k & 3;
+            if (t < 9 && i < 3) v = p[w_off(1) + (o * 3 + i) * 9 + t];
+        } else if (j < pb_off(2)) {
+            const int64_t r = j - C * K1;
+            const int l = 2 + (int)(r / (C * K2));
+            const int q = (int)(r % (C * K2)), o = q / K2, k = q % K2, t = k >> 6, i = k & 63;
+            v = p[w_off(l) + (o * C + i) * 9 + t];
+        } else {
+            const int64_t r = j - pb_off(2);
+            const int l = 2 + (int)(r / (C * K2));
+            const int q = (int)(r % (C * K2)), i = q / K2, k = q % K2, tp = k >> 6, o = k & 63;
+            v = p[w_off(l) + (o * C + i) * 9 + (8 - tp)];
+        }
+        out[j] = f2bf(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// encode: boards -> layer-1 input planes [n][NP][NP][4] (ring zero)
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ void k_encode(const int8_t *__restrict__ board, const int8_t *__restrict__ to_move, int64_t n,
+                         uint2 *__restrict__ a0)
+{
+    constexpr int NP = N + 2, PP = NP * NP;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n * PP) return;
+    const int64_t b = j / PP;
+    const int q = (int)(j % PP), R = q / NP, Q = q % NP;
+    uint2 v = {0u, 0u};
+    if (R >= 1 && R <= N && Q >= 1 && Q <= N) {
+        const int r = R - 1, c = Q - 1, me = to_move[b];
+        const int cell = me == 2 ? c * N + r : r * N + c; // player 2 sees the transpose
+        const int x = board[b * (N * N) + cell];
+        const uint32_t one = 0x3F80u; // bf16 1.0
+        const uint32_t c0 = x == me ? one : 0u, c1 = (x != 0 && x != me) ? one : 0u, c2 = x == 0 ? one : 0u;
+        v.x = c0 | (c1 << 16);
+        v.y = c2;
+    }
+    a0[j] = v;
+}
+
+// ring cell j (0 <= j < 4 * (NP - 1)) of a padded NP x NP frame
+template <int NP>
+__device__ __forceinline__ int ring_cell(int j)
+{
+    if (j < NP) return j;                               // top row
+    if (j < 2 * NP) return (NP - 1) * NP + (j - NP);    // bottom row
+    const int k = j - 2 * NP;                           // sides, rows 1 .. NP-2
+    return (1 + (k >> 1)) * NP + ((k & 1) ? NP - 1 : 0);
+}
+
+// zero the ring of one board's [NP][NP][64] bf16 activation (one wave)
+template <int N>
+__device__ __forceinline__ void zero_ring(uint16_t *act_b, int lane)
+{
+    constexpr int NP = N + 2, RING = 4 * (NP - 1);
+    for (int j = lane; j < RING * 8; j += WAVE) {
+        const int cell = ring_cell<NP>(j >> 3);
+        reinterpret_cast<uint4 *>(act_b + (int64_t)cell * C)[j & 7] = uint4{0u, 0u, 0u, 0u};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, implicit GEMM on MFMA.
+//   MODE 0 (forward):  out = bf16(relu(conv(X, W) + bias))
+//   MODE 1 (data gradient): out = bf16(conv(X, W) * [mask > 0]), X = dZ of the
+//          layer above, W = its flipped, transposed weights, mask = the
+//          forward activation of the layer below.
+// CIN = 4 (layer-1 planes) or 64.  Grid: 4 waves per block, one wave per
+// (board, group of up to 8 cell tiles).
+// ---------------------------------------------------------------------------
+template <int N, int CIN, int MODE>
+__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+                                              const float *__restrict__ bias,
+                                              const uint16_t *__restrict__ mask, uint16_t *__restrict__ out,
+                                              int64_t n)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
+    constexpr int K = CIN == 4 ? K1 : K2, KS = K + 8;
+    __shared__ __align__(16) uint16_t ws[C * KS];
+
+    // stage the weights (all 256 threads), 16 bytes at a time
+    for (int j = threadIdx.x; j < C * K / 8; j += 256) {
+        const int o = j / (K / 8), k8 = j % (K / 8);
+        reinterpret_cast<uint4 *>(ws + o * KS)[k8] = reinterpret_cast<const uint4 *>(w + (int64_t)o * K)[k8];
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t item = (int64_t)blockIdx.x * 4 + wave;
+    if (item >= n * NG) return;
+    const int64_t b = item / NG;
+    const int g = (int)(item % NG);
+    const uint16_t *xb = x + b * (int64_t)PP * CIN;
+    uint16_t *ob = out + b * (int64_t)PP * C;
+    if (g == 0) zero_ring<N>(ob, lane);
+
+    const int row = lane & 15, quad = lane >> 4;
+    // the A rows (cells) of this lane in each tile, as offsets of the
+    // top-left tap in the padded frame; cells past the board read cell 0
+    int cell_off[8];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const int p = (g * 8 + mt) * 16 + row;
+        const int pc = p < PIX ? p : 0;
+        cell_off[mt] = ((pc / N) * NP + (pc % N)) * CIN;
+    }
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int ks = 0; ks < K / 32; ++ks) {
+        const int k0 = ks * 32 + quad * 8; // this lane's 8 consecutive k
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * KS + k0));
+        int off0, off1;
+        if constexpr (CIN == 4) {
+            // k = tap * 4 + channel: two taps per lane; taps >= 9 read tap 0
+            // (their weights are zero)
+            const int t0 = k0 >> 2, t1 = t0 + 1;
+            const int u0 = t0 < 9 ? t0 : 0, u1 = t1 < 9 ? t1 : 0;
+            off0 = ((u0 / 3) * NP + (u0 % 3)) * CIN;
+            off1 = ((u1 / 3) * NP + (u1 % 3)) * CIN;
+        } else {
+            const int t = k0 >> 6;
+            off0 = ((t / 3) * NP + (t % 3)) * CIN + (k0 & 63);
+            off1 = 0;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            if (g * 8 + mt >= MT) break;
+            bf16x8 a;
+            if constexpr (CIN == 4) {
+                const uint2 lo = *reinterpret_cast<const uint2 *>(xb + cell_off[mt] + off0);
+                const uint2 hi = *reinterpret_cast<const uint2 *>(xb + cell_off[mt] + off1);
+                a = as_bf16x8(uint4{lo.x, lo.y, hi.x, hi.y});
+            } else {
+                a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + cell_off[mt] + off0));
+            }
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+        }
+    }
+
+    // epilogue: lane holds rows 4 * quad + i (cells) of column row (channel)
+    const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        if (g * 8 + mt >= MT) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = (g * 8 + mt) * 16 + quad * 4 + i;
+            if (p >= PIX) continue;
+            const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int co = nt * 16 + row;
+                float v = acc[mt][nt][i];
+                if constexpr (MODE == 0) {
+                    v += bias[co];
+                    v = v > 0.f ? v : 0.f;
+                } else {
+                    const uint16_t m = mb[o + co];
+                    v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
+                }
+                ob[o + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// heads, forward: one wave per board, lanes over cells.
+// logits in action order (the frame of player 2 is transposed back), and
+// optionally in the mover's frame; value = tanh(wv . mean + bv).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_heads(const uint16_t *__restrict__ y4, const float *__restrict__ p,
+                                               const int8_t *__restrict__ to_move, int64_t n,
+                                               float *__restrict__ logits, float *__restrict__ logits_frame,
+                                               float *__restrict__ value)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    __shared__ float hw[2 * C];
+    if (threadIdx.x < C) hw[threadIdx.x] = p[WP_OFF + threadIdx.x];
+    else if (threadIdx.x < 2 * C) hw[threadIdx.x] = p[WV_OFF + threadIdx.x - C];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= n) return;
+    const uint16_t *yb = y4 + b * (int64_t)PP * C;
+    const int me = to_move[b];
+    const float bp = p[BP_OFF];
+    float sv = 0.f;
+    for (int q = lane; q < PIX; q += WAVE) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(yb + (int64_t)(((q / N) + 1) * NP + (q % N) + 1) * C);
+        float lp = 0.f, lv = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint4 v = src[j];
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const float y0 = __uint_as_float(wd[h] << 16), y1 = __uint_as_float(wd[h] & 0xFFFF0000u);
+                const int c0 = j * 8 + 2 * h;
+                lp += y0 * hw[c0] + y1 * hw[c0 + 1];
+                lv += y0 * hw[C + c0] + y1 * hw[C + c0 + 1];
+            }
+        }
+        const float l = lp + bp;
+        const int r = q / N, c = q % N;
+        const int cell = me == 2 ? c * N + r : q;
+        logits[b * PIX + cell] = l;
+        if (logits_frame) logits_frame[b * PIX + q] = l;
+        sv += lv;
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) sv += __shfl_xor(sv, s);
+    if (lane == 0) value[b] = tanhf(sv / (float)PIX + p[BV_OFF]);
+}
+
+// ---------------------------------------------------------------------------
+// heads, backward: one wave per sample.  Masked softmax over the empty cells
+// of the mover's frame, d(loss)/d(logit), d(loss)/d(pre-tanh value), the
+// per-sample loss terms, and dZ4 = bf16((dlogit wp + du wv / PIX) * [Y4 > 0])
+// into the padded gradient buffer (ring zeroed).
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ y4, const uint2 *__restrict__ a0,
+                                                   const float *__restrict__ p,
+                                                   const float *__restrict__ logits_frame,
+                                                   const float *__restrict__ value,
+                                                   const int8_t *__restrict__ to_move,
+                                                   const int16_t *__restrict__ action, const float *__restrict__ z,
+                                                   int64_t n, float beta, float inv_n, float *__restrict__ dlog,
+                                                   float *__restrict__ du_out, float *__restrict__ loss_terms,
+                                                   uint16_t *__restrict__ g4)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N, QL = (PIX + 63) / 64;
+    __shared__ float hw[2 * C];
+    if (threadIdx.x < C) hw[threadIdx.x] = p[WP_OFF + threadIdx.x];
+    else if (threadIdx.x < 2 * C) hw[threadIdx.x] = p[WV_OFF + threadIdx.x - C];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= n) return;
+    const int me = to_move[b];
+    const int act = action[b];
+    const int a = me == 2 ? (act % N) * N + act / N : act; // frame index of the move
+    const float v = value[b], zb = z[b];
+
+    float l[QL];
+    bool legal[QL];
+    float mx = -3.0e38f;
+#pragma unroll
+    for (int j = 0; j < QL; ++j) {
+        const int q = lane + 64 * j;
+        legal[j] = false;
+        l[j] = 0.f;
+        if (q < PIX) {
+            const int R = q / N + 1, Q = q % N + 1;
+            legal[j] = a0[(int64_t)b * PP + R * NP + Q].y != 0u; // the empty plane
+            l[j] = logits_frame[b * PIX + q];
+            if (legal[j]) mx = fmaxf(mx, l[j]);
+        }
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+    float e[QL], se = 0.f;
+#pragma unroll
+    for (int j = 0; j < QL; ++j) {
+        e[j] = legal[j] ? expf(l[j] - mx) : 0.f;
+        se += e[j];
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) se += __shfl_xor(se, s);
+    const float adv = zb - v;
+    const float du = 2.f * (v - zb) * inv_n * (1.f - v * v);
+    if (lane == 0) {
+        du_out[b] = du;
+        loss_terms[2 * b] = (v - zb) * (v - zb) * inv_n;
+    }
+    uint16_t *gb = g4 + b * (int64_t)PP * C;
+    zero_ring<N>(gb, lane);
+    const uint16_t *yb = y4 + b * (int64_t)PP * C;
+    const float dv = du / (float)PIX;
+#pragma unroll
+    for (int j = 0; j < QL; ++j) {
+        const int q = lane + 64 * j;
+        if (q >= PIX) continue;
+        const float pi = e[j] / se;
+        float d = legal[j] ? beta * adv * pi : 0.f;
+        if (q == a) {
+            d -= beta * adv;
+            loss_terms[2 * b + 1] = beta * adv * -(l[j] - mx - logf(se)) * inv_n;
+        }
+        d *= inv_n;
+        dlog[b * PIX + q] = d;
+        const int64_t o = (int64_t)((q / N + 1) * NP + (q % N) + 1) * C;
+        const uint4 *src = reinterpret_cast<const uint4 *>(yb + o);
+        uint4 *dst = reinterpret_cast<uint4 *>(gb + o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint4 yv = src[k];
+            const uint32_t wd[4] = {yv.x, yv.y, yv.z, yv.w};
+            uint32_t od[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int c0 = k * 8 + 2 * h;
+                const uint16_t y0 = (uint16_t)(wd[h] & 0xFFFFu), y1 = (uint16_t)(wd[h] >> 16);
+                const float g0 = (y0 != 0 && (y0 & 0x8000u) == 0) ? d * hw[c0] + dv * hw[C + c0] : 0.f;
+                const float g1 = (y1 != 0 && (y1 & 0x8000u) == 0) ? d * hw[c0 + 1] + dv * hw[C + c0 + 1] : 0.f;
+                od[h] = (uint32_t)f2bf(g0) | ((uint32_t)f2bf(g1) << 16);
+            }
+            dst[k] = uint4{od[0], od[1], od[2], od[3]};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// head weight gradients, per block partial sums over a share of the batch:
+// in parameter order: part[blk][c] = sum dlog[b][q] Y4[b][q][c] (wp),
+// part[blk][64] = sum dlog (bp), part[blk][65 + c] = sum du[b] Y4[b][q][c] /
+// PIX (wv), part[blk][129] = sum du (bv)
+// ---------------------------------------------------------------------------
+constexpr int HEAD_PART = 2 * C + 2;
+
+template <int N>
+__global__ __launch_bounds__(64) void k_head_wgrad(const uint16_t *__restrict__ y4, const float *__restrict__ dlog,
+                                                   const float *__restrict__ du, int64_t n,
+                                                   float *__restrict__ part)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    const int c = threadIdx.x;
+    float ap = 0.f, av = 0.f, sp = 0.f, sv = 0.f;
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const uint16_t *yb = y4 + b * (int64_t)PP * C;
+        const float dub = du[b];
+        float mv = 0.f;
+        for (int q = 0; q < PIX; ++q) {
+            const float y = bf2f(yb[(int64_t)((q / N + 1) * NP + (q % N) + 1) * C + c]);
+            const float d = dlog[b * PIX + q];
+            ap += d * y;
+            mv += y;
+            if (c == 0) sp += d;
+        }
+        av += dub * mv / (float)PIX;
+        if (c == 0) sv += dub;
+    }
+    float *o = part + (int64_t)blockIdx.x * HEAD_PART;
+    o[c] = ap;
+    o[C + 1 + c] = av;
+    if (c == 0) {
+        o[C] = sp;
+        o[2 * C + 1] = sv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// conv weight gradient: dW[o][i][t] = sum_{b,p} dZ[b][p][o] X[b][p + tap t][i]
+// and db[o] = sum dZ[b][p][o], per block partial sums.  M = 64 output
+// channels (4 tiles), N = (tap, input channel) columns, K = cells (padded to
+// 32 per board).  Four waves split the column tiles.
+// part layout per block: [64 * CR * 9] (param order o, i, t) then [64] db.
+// ---------------------------------------------------------------------------
+template <int N, int CIN>
+__global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
+                                                    int64_t n, float *__restrict__ part)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    constexpr int PIXP = (PIX + 31) / 32 * 32, DS = PIXP + 8; // dZ^T row stride
+    constexpr int PPS = PP + 8;                               // X^T row stride
+    constexpr int CR = CIN == 4 ? 3 : CIN;                    // real input channels
+    constexpr int NCOL = 9 * CIN, NT = (NCOL + 15) / 16;      // column tiles
+    constexpr int NTW = (NT + 3) / 4;                         // column tiles per wave
+    constexpr int PART = C * CR * 9 + C;
+    __shared__ __align__(16) uint16_t dzt[C * DS];
+    __shared__ __align__(16) uint16_t xt[CIN * PPS];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, quad = lane >> 4;
+    f32x4 acc[4][NTW];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    // this lane's B column in each of its tiles: (tap offset, channel)
+    int col_off[NTW], col_ch[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        const int col = (wave * NTW + j) * 16 + row;
+        const int cc = col < NCOL ? col : 0;
+        const int t = cc / CIN, i = cc % CIN;
+        col_off[j] = (t / 3) * NP + (t % 3);
+        col_ch[j] = i;
+    }
+    // zero the padded cells of dZ^T once (cells PIX .. PIXP-1)
+    for (int j = threadIdx.x; j < C * (PIXP - PIX); j += 256)
+        dzt[(j / (PIXP - PIX)) * DS + PIX + j % (PIXP - PIX)] = 0;
+
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();
+        const uint16_t *db = dz + b * (int64_t)PP * C;
+        const uint16_t *xb = x + b * (int64_t)PP * CIN;
+        for (int j = threadIdx.x; j < PIX * 8; j += 256) { // interior cells of dZ, 8 channels each
+            const int q = j >> 3, c0 = (j & 7) * 8;
+            const uint4 v = *reinterpret_cast<const uint4 *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C + c0);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                dzt[(c0 + 2 * h) * DS + q] = (uint16_t)(wd[h] & 0xFFFFu);
+                dzt[(c0 + 2 * h + 1) * DS + q] = (uint16_t)(wd[h] >> 16);
+            }
+        }
+        if constexpr (CIN == 4) {
+            for (int q = threadIdx.x; q < PP; q += 256) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(xb + (int64_t)q * 4);
+                xt[0 * PPS + q] = (uint16_t)(v.x & 0xFFFFu);
+                xt[1 * PPS + q] = (uint16_t)(v.x >> 16);
+                xt[2 * PPS + q] = (uint16_t)(v.y & 0xFFFFu);
+                xt[3 * PPS + q] = (uint16_t)(v.y >> 16);
+            }
+        } else {
+            for (int j = threadIdx.x; j < PP * 8; j += 256) {
+                const int q = j >> 3, c0 = (j & 7) * 8;
+                const uint4 v = *reinterpret_cast<const uint4 *>(xb + (int64_t)q * C + c0);
+                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    xt[(c0 + 2 * h) * PPS + q] = (uint16_t)(wd[h] & 0xFFFFu);
+                    xt[(c0 + 2 * h + 1) * PPS + q] = (uint16_t)(wd[h] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < C) { // bias gradient: row sums of dZ^T
+            float s = 0.f;
+            for (int q = 0; q < PIX; ++q) s += bf2f(dzt[threadIdx.x * DS + q]);
+            dbias += s;
+        }
+        for (int ks = 0; ks < PIXP / 32; ++ks) {
+            const int p0 = ks * 32 + quad * 8; // this lane's 8 consecutive cells
+            bf16x8 afr[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                afr[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(dzt + (mt * 16 + row) * DS + p0));
+            int cq[8]; // top-left tap of each of the 8 cells in the padded frame
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int p = p0 + i < PIX ? p0 + i : 0;
+                cq[i] = (p / N) * NP + p % N;
+            }
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                if (wave * NTW + j >= NT) break;
+                const uint16_t *xr = xt + col_ch[j] * PPS + col_off[j];
+                uint32_t u[4];
+#pragma unroll
+                for (int h = 0; h < 4; ++h) u[h] = (uint32_t)xr[cq[2 * h]] | ((uint32_t)xr[cq[2 * h + 1]] << 16);
+                const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][j], 0, 0, 0);
+            }
+        }
+    }
+    float *o = part + (int64_t)blockIdx.x * PART;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        const int col = (wave * NTW + j) * 16 + row;
+        if (wave * NTW + j >= NT || col >= NCOL) continue;
+        const int t = col / CIN, i = col % CIN;
+        if (i >= CR) continue;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = mt * 16 + quad * 4 + r;
+                o[(co * CR + i) * 9 + t] = acc[mt][j][r];
+            }
+    }
+    if (threadIdx.x < C) o[C * CR * 9 + threadIdx.x] = dbias;
+}
+
+// out[j] (+)= sum over rows r < rows of part[r * stride + j], j < cols
+__global__ void k_sum_rows(const float *__restrict__ part, int64_t rows, int stride, int cols,
+                           float *__restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cols) return;
+    float s = 0.f;
+    for (int64_t r = 0; r < rows; ++r) s += part[r * stride + j];
+    out[j] = s;
+}
+
+// value cutoff estimate for player 1
+__global__ void k_estimate(const int8_t *__restrict__ status, const int8_t *__restrict__ winner,
+                           const int8_t *__restrict__ to_move, const float *__restrict__ value, int64_t n,
+                           float *__restrict__ est)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int st = status[i];
+    float e = 0.f;
+    if (st == 1) e = winner[i] == 1 ? 1.f : (winner[i] == 2 ? -1.f : 0.f);
+    else if (st == 0) e = to_move[i] == 1 ? value[i] : -value[i];
+    est[i] = e;
+}
+
+// Adam (Kingma & Ba) with bias correction, float32 master weights
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int64_t np, float lr, float b1, float b2, float eps, float c1,
+                       float c2)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= np) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.f - b1) * gj;
+    const float vj = b2 * v[j] + (1.f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    p[j] -= lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+constexpr int WG_BLOCKS = 256; // blocks of the weight-gradient reductions
+
+int64_t blocks_min(int64_t n, int64_t cap) { return n < cap ? n : cap; }
+
+struct Carve {
+    char *base;
+    int64_t off = 0;
+    template <class T>
+    T *take(int64_t bytes)
+    {
+        T *p = reinterpret_cast<T *>(base + off);
+        off += align256(bytes);
+        return p;
+    }
+};
+
+template <int N>
+struct Sizes {
+    static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    static constexpr int64_t a0(int64_t n) { return n * PP * 8; }
+    static constexpr int64_t act(int64_t n) { return n * PP * C * 2; }
+    static constexpr int64_t forward_ws(int64_t n) { return align256(a0(n)) + 2 * align256(act(n)); }
+    static constexpr int64_t train_ws(int64_t n)
+    {
+        return align256(a0(n)) + 6 * align256(act(n)) + 3 * align256(n * PIX * 4) + 3 * align256(n * 4) +
+               align256(n * 8) + align256((int64_t)WG_BLOCKS * (C * C * 9 + C) * 4) +
+               align256((int64_t)WG_BLOCKS * HEAD_PART * 4);
+    }
+};
+
+template <int N>
+hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
+                     int64_t n, float *logits, float *value, void *ws, hipStream_t s)
+{
+    using S = Sizes<N>;
+    constexpr int MT = (S::PIX + 15) / 16, NG = (MT + 7) / 8;
+    Carve cv{static_cast<char *>(ws)};
+    uint2 *a0 = cv.take<uint2>(S::a0(n));
+    uint16_t *ya = cv.take<uint16_t>(S::act(n));
+    uint16_t *yb = cv.take<uint16_t>(S::act(n));
+    const unsigned eb = (unsigned)((n * S::PP + 255) / 256), cb = (unsigned)((n * NG + 3) / 4),
+                   hb = (unsigned)((n + 3) / 4);
+    hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
+    hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, reinterpret_cast<const uint16_t *>(a0),
+                       packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
+    uint16_t *in = ya, *out = yb;
+    for (int l = 2; l <= 4; ++l) {
+        hipLaunchKernelGGL((k_conv<N, 64, 0>), dim3(cb), dim3(256), 0, s, in, packed + pf_off(l),
+                           params + b_off(l), (const uint16_t *)nullptr, out, n);
+        uint16_t *t = in;
+        in = out;
+        out = t;
+    }
+    hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, in, params, to_move, n, logits, (float *)nullptr,
+                       value);
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
+                       const int16_t *action, const float *z, int64_t n, float beta, float *loss, float *grads,
+                       void *ws, hipStream_t s)
+{
+    using S = Sizes<N>;
+    constexpr int MT = (S::PIX + 15) / 16, NG = (MT + 7) / 8;
+    Carve cv{static_cast<char *>(ws)};
+    uint2 *a0 = cv.take<uint2>(S::a0(n));
+    uint16_t *y[5];
+    y[0] = reinterpret_cast<uint16_t *>(a0);
+    for (int l = 1; l <= 4; ++l) y[l] = cv.take<uint16_t>(S::act(n));
+    uint16_t *ga = cv.take<uint16_t>(S::act(n)), *gb = cv.take<uint16_t>(S::act(n));
+    float *logits = cv.take<float>(n * S::PIX * 4);
+    float *lframe = cv.take<float>(n * S::PIX * 4);
+    float *dlog = cv.take<float>(n * S::PIX * 4);
+    float *value = cv.take<float>(n * 4);
+    float *du = cv.take<float>(n * 4);
+    cv.take<float>(n * 4);
+    float *lterms = cv.take<float>(n * 8);
+    float *part = cv.take<float>((int64_t)WG_BLOCKS * (C * C * 9 + C) * 4);
+    float *hpart = cv.take<float>((int64_t)WG_BLOCKS * HEAD_PART * 4);
+
+    const unsigned eb = (unsigned)((n * S::PP + 255) / 256), cb = (unsigned)((n * NG + 3) / 4),
+                   hb = (unsigned)((n + 3) / 4);
+    const unsigned wb = (unsigned)blocks_min(n, WG_BLOCKS);
+    hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
+    hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, y[0], packed + pf_off(1), params + b_off(1),
+                       (const uint16_t *)nullptr, y[1], n);
+    for (int l = 2; l <= 4; ++l)
+        hipLaunchKernelGGL((k_conv<N, 64, 0>), dim3(cb), dim3(256), 0, s, y[l - 1], packed + pf_off(l),
+                           params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+    hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
+    hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
+                       action, z, n, beta, 1.f / (float)n, dlog, du, lterms, ga);
+    hipLaunchKernelGGL(k_head_wgrad<N>, dim3(wb), dim3(64), 0, s, y[4], dlog, du, n, hpart);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, hpart, (int64_t)wb, HEAD_PART, HEAD_PART,
+                       grads + WP_OFF);
+    constexpr int PART64 = C * C * 9 + C, PART4 = C * 27 + C;
+    for (int l = 4; l >= 2; --l) {
+        hipLaunchKernelGGL((k_conv_wgrad<N, 64>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
+        hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 255) / 256), dim3(256), 0, s, part, (int64_t)wb, PART64,
+                           PART64, grads + w_off(l));
+        hipLaunchKernelGGL((k_conv<N, 64, 1>), dim3(cb), dim3(256), 0, s, ga, packed + pb_off(l),
+                           (const float *)nullptr, y[l - 1], gb, n);
+        uint16_t *t = ga;
+        ga = gb;
+        gb = t;
+    }
+    hipLaunchKernelGGL((k_conv_wgrad<N, 4>), dim3(wb), dim3(256), 0, s, ga, y[0], n, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 255) / 256), dim3(256), 0, s, part, (int64_t)wb, PART4, PART4,
+                       grads + w_off(1));
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, s, lterms, n, 2, 2, loss);
+    return hipGetLastError();
+}
+
+} // namespace
+} // namespace net
+
+int64_t net_n_params() { return net::N_PARAMS; }
+int64_t net_packed_bytes() { return net::PACKED_ELEMS * 2; }
+bool net_size_supported(int N) { return N == 11 || N == 19; }
+
+int64_t net_forward_ws_bytes(int N, int64_t n)
+{
+    // the forward's buffers, then the logits and values of ludax_net_estimate
+    const int64_t f = N == 11 ? net::Sizes<11>::forward_ws(n) : net::Sizes<19>::forward_ws(n);
+    return f + net::align256(n * N * N * 4) + net::align256(n * 4);
+}
+int64_t net_train_ws_bytes(int N, int64_t n)
+{
+    return N == 11 ? net::Sizes<11>::train_ws(n) : net::Sizes<19>::train_ws(n);
+}
+
+hipError_t net_pack(const float *params, void *packed, hipStream_t s)
+{
+    hipLaunchKernelGGL(net::k_pack, dim3(256), dim3(256), 0, s, params, static_cast<uint16_t *>(packed));
+    return hipGetLastError();
+}
+
+hipError_t net_forward(int N, const float *params, const void *packed, const int8_t *board, const int8_t *to_move,
+                       int64_t n, float *logits, float *value, void *ws, hipStream_t s)
+{
+    const uint16_t *pk = static_cast<const uint16_t *>(packed);
+    return N == 11 ? net::forward_t<11>(params, pk, board, to_move, n, logits, value, ws, s)
+                   : net::forward_t<19>(params, pk, board, to_move, n, logits, value, ws, s);
+}
+
+hipError_t net_loss_grad(int N, const float *params, const void *packed, const int8_t *board,
+                         const int8_t *to_move, const int16_t *action, const float *z, int64_t n, float beta,
+                         float *loss, float *grads, void *ws, hipStream_t s)
+{
+    const uint16_t *pk = static_cast<const uint16_t *>(packed);
+    return N == 11 ? net::loss_grad_t<11>(params, pk, board, to_move, action, z, n, beta, loss, grads, ws, s)
+                   : net::loss_grad_t<19>(params, pk, board, to_move, action, z, n, beta, loss, grads, ws, s);
+}
+
+hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,
+                        float *estimate, void *ws, hipStream_t s)
+{
+    const int64_t f = N == 11 ? net::Sizes<11>::forward_ws(n) : net::Sizes<19>::forward_ws(n);
+    float *logits = reinterpret_cast<float *>(static_cast<char *>(ws) + f);
+    float *value = reinterpret_cast<float *>(static_cast<char *>(ws) + f + net::align256(n * N * N * 4));
+    hipError_t e = net_forward(N, params, packed, st.board, st.to_move, n, logits, value, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(net::k_estimate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, st.status, st.winner,
+                       st.to_move, value, n, estimate);
+    return hipGetLastError();
+}
+
+hipError_t net_adam(float *params, const float *grads, float *m, float *v, int step, float lr, float b1, float b2,
+                    float eps, void *packed, hipStream_t s)
+{
+    const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+    hipLaunchKernelGGL(net::k_adam, dim3((unsigned)((net::N_PARAMS + 255) / 256)), dim3(256), 0, s, params, grads,
+                       m, v, net::N_PARAMS, lr, b1, b2, eps, c1, c2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || packed == nullptr) return e;
+    return net_pack(params, packed, s);
+}
+
+} // namespace lx

@@ -1,0 +1,122 @@
+"""Training data, training loop and value-cutoff evaluation of the
+policy/value network, driven through the C ABI (every step of the game and
+of the network runs in the library's kernels; PyTorch holds the buffers and
+does the index bookkeeping).
+
+Samples come from seeded uniform-random playouts (the paper's benchmark
+policy, Sec. 6): every ply of every game gives one sample (position, the
+move played there, the final outcome for the player who moved).  The
+network learns the value (expected outcome under random play) and a policy
+weighted towards moves after which the mover did better than predicted.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import torch
+
+from . import ludax
+
+RUNNING, TERMINAL = 0, 1
+
+
+@dataclass
+class Samples:
+    board: torch.Tensor    # [m][cells] int8
+    to_move: torch.Tensor  # [m] int8
+    action: torch.Tensor   # [m] int16, the cell played
+    z: torch.Tensor        # [m] float32, final outcome for the mover
+
+    def __len__(self):
+        return self.board.shape[0]
+
+    def take(self, idx):
+        return Samples(self.board[idx], self.to_move[idx], self.action[idx], self.z[idx])
+
+
+def collect(game: ludax.Game, n_games: int, seed: int, id_base: int, batch: int = 65536) -> Samples:
+    """Play n_games uniform-random games (ids id_base + i) ply by ply with
+    ludax_random_step and keep every position before a move."""
+    boards, tms, acts, zs = [], [], [], []
+    for g0 in range(0, n_games, batch):
+        n = min(batch, n_games - g0)
+        s = ludax.State(game, n)
+        ludax.init(game, s)
+        r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
+        t = torch.empty(n, dtype=torch.uint8, device="cuda")
+        rec = []
+        for _ in range(game.max_plies):
+            live = (s.status == RUNNING).nonzero().squeeze(1)
+            if live.numel() == 0:
+                break
+            b, m = s.board[live].clone(), s.to_move[live].clone()
+            ludax.random_step(game, s, seed, id_base + g0, reward=r, terminal=t)
+            rec.append((live, b, m, s.last_action[live].clone()))
+        w = s.winner.to(torch.float32)
+        for live, b, m, a in rec:
+            wl = w[live]
+            mf = m.to(torch.float32)
+            z = torch.where(wl == mf, 1.0, torch.where(wl == 3.0 - mf, -1.0, 0.0))
+            boards.append(b)
+            tms.append(m)
+            acts.append(a)
+            zs.append(z)
+    return Samples(torch.cat(boards), torch.cat(tms), torch.cat(acts), torch.cat(zs))
+
+
+def train(net: ludax.Net, data: Samples, steps: int, batch: int = 4096, lr: float = 1e-3, beta: float = 1.0,
+          seed: int = 0, log_every: int = 0):
+    """Adam on shuffled minibatches (the paper's training batch size 4096
+    and learning rate 0.001).  Returns the per-step losses [steps][2]."""
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    m = len(data)
+    perm = torch.randperm(m, generator=gen).cuda()
+    losses = torch.empty((steps, 2), dtype=torch.float32, device="cuda")
+    grads = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    pos = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        if pos + batch > m:
+            perm = torch.randperm(m, generator=gen).cuda()
+            pos = 0
+        idx = perm[pos:pos + batch]
+        pos += batch
+        b = data.take(idx)
+        net.loss_grad(b.board, b.to_move, b.action, b.z, beta=beta, grads=grads, loss=losses[k])
+        net.adam(grads, lr=lr)
+        if log_every and (k + 1) % log_every == 0:
+            lv = losses[k - log_every + 1:k + 1].mean(0).tolist()
+            print(f"step {k + 1}: value loss {lv[0]:.4f} policy term {lv[1]:.4f} "
+                  f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    return losses
+
+
+def replicate(game: ludax.Game, s: ludax.State, reps: int) -> ludax.State:
+    """reps copies of every env (env i's copies are rows i*reps .. i*reps+reps-1)."""
+    t = {f: getattr(s, f).repeat_interleave(reps, dim=0).contiguous() for f in ludax.State.FIELDS}
+    return ludax.State.from_tensors(game, **t)
+
+
+def outcome_p1(s: ludax.State) -> torch.Tensor:
+    w = s.winner.to(torch.float32)
+    return torch.where(s.status == TERMINAL, torch.where(w == 1, 1.0, torch.where(w == 2, -1.0, 0.0)),
+                       torch.zeros_like(w))
+
+
+def truth(game: ludax.Game, s: ludax.State, reps: int, seed: int, id_base: int) -> torch.Tensor:
+    """Mean outcome for player 1 of `reps` full random playouts from each
+    state (distinct game ids), the reference the estimates are judged by."""
+    r = replicate(game, s, reps)
+    ludax.playout(game, r, seed, id_base, stats=None)
+    return outcome_p1(r).view(s.n, reps).mean(1)
+
+
+def cutoff_estimate(game: ludax.Game, net: ludax.Net, s: ludax.State, k: int, seed: int, id_base: int):
+    """k uniform-random plies (ludax_random_step), then the value cutoff
+    (ludax_net_estimate).  Modifies s."""
+    r = torch.empty((s.n, 2), dtype=torch.int8, device="cuda")
+    t = torch.empty(s.n, dtype=torch.uint8, device="cuda")
+    for _ in range(k):
+        ludax.random_step(game, s, seed, id_base, reward=r, terminal=t)
+    return net.estimate(s)

@@ -24,8 +24,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
            "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_playout",
            "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy", "ludax_mixed_set_slots",
-           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune", "ludax_strerror",
-           "ludax_last_device_error")
+           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune",
+           "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
+           "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
+           "ludax_net_estimate", "ludax_strerror", "ludax_last_device_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -80,6 +82,16 @@ def _load():
             L.ludax_mixed_playout.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp, vp]
             L.ludax_mixed_autotune.argtypes = [vp, ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp,
                                                P(ctypes.c_float)]
+            f32 = ctypes.c_float
+            L.ludax_net_create.argtypes = [i32, i32, P(vp)]
+            L.ludax_net_destroy.argtypes = [vp]
+            L.ludax_net_info.argtypes = [vp, P(i64), P(i64)]
+            L.ludax_net_workspace_bytes.argtypes = [vp, i64, i32, P(i64)]
+            L.ludax_net_pack.argtypes = [vp, vp, vp, vp]
+            L.ludax_net_forward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp]
+            L.ludax_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, f32, vp, vp, vp, vp]
+            L.ludax_net_adam.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
+            L.ludax_net_estimate.argtypes = [vp, vp, vp, P(_State), i64, vp, vp, vp]
             L.ludax_strerror.argtypes = [ctypes.c_int]
             L.ludax_strerror.restype = ctypes.c_char_p
             L.ludax_last_device_error.argtypes = []
@@ -89,7 +101,10 @@ def _load():
                          "ludax_playout",
                          "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy",
                          "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
-                         "ludax_mixed_autotune"):
+                         "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy",
+                         "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_pack",
+                         "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
+                         "ludax_net_estimate"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -363,4 +378,112 @@ class Mixed:
         h = getattr(self, "_h", None)
         if h is not None and _lib is not None:
             _lib.ludax_mixed_destroy(h)
+            self._h = None
+
+
+class Net:
+    """The policy/value network of an N x N board (N = 11 or 19); see
+    ludax_net_* in include/ludax.h.  Holds the parameters (float32), the
+    packed bfloat16 copy and the Adam moments as device tensors."""
+
+    def __init__(self, rows: int, cols: int, params=None, device="cuda"):
+        L = _load()
+        h = ctypes.c_void_p()
+        _check(L.ludax_net_create(rows, cols, ctypes.byref(h)), "ludax_net_create")
+        self._h = h
+        self.rows, self.cols = rows, cols
+        npar, pb = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.ludax_net_info(h, ctypes.byref(npar), ctypes.byref(pb)), "ludax_net_info")
+        self.n_params, self.packed_bytes = npar.value, pb.value
+        self.params = torch.zeros(self.n_params, dtype=torch.float32, device=device)
+        self.packed = torch.zeros(self.packed_bytes, dtype=torch.uint8, device=device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = {}
+        if params is not None:
+            self.load(params)
+
+    def load(self, params):
+        p = torch.as_tensor(params, dtype=torch.float32).reshape(-1)
+        if p.numel() != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {p.numel()}")
+        self.params.copy_(p)
+        self.pack()
+
+    def pack(self, stream=None):
+        _check(_load().ludax_net_pack(self._h, _ptr(self.params), _ptr(self.packed), _stream(stream)),
+               "ludax_net_pack")
+
+    def workspace(self, n: int, training: bool = False):
+        b = ctypes.c_int64()
+        _check(_load().ludax_net_workspace_bytes(self._h, n, int(training), ctypes.byref(b)),
+               "ludax_net_workspace_bytes")
+        key = (training, self.params.device)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < b.value:
+            ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=self.params.device)
+            self._ws[key] = ws
+        return ws
+
+    def forward(self, board, to_move, logits=None, value=None, stream=None):
+        n = board.shape[0]
+        dev = board.device
+        if logits is None:
+            logits = torch.empty((n, self.rows * self.cols), dtype=torch.float32, device=dev)
+        if value is None:
+            value = torch.empty(n, dtype=torch.float32, device=dev)
+        _need(board, torch.int8, (n, self.rows * self.cols), "board")
+        _need(to_move, torch.int8, (n,), "to_move")
+        _need(logits, torch.float32, (n, self.rows * self.cols), "logits")
+        _need(value, torch.float32, (n,), "value")
+        ws = self.workspace(n)
+        _check(_load().ludax_net_forward(self._h, _ptr(self.params), _ptr(self.packed), _ptr(board),
+                                         _ptr(to_move), n, _ptr(logits), _ptr(value), _ptr(ws),
+                                         _stream(stream)), "ludax_net_forward")
+        return logits, value
+
+    def loss_grad(self, board, to_move, action, z, beta: float = 1.0, grads=None, loss=None, stream=None):
+        n = board.shape[0]
+        dev = board.device
+        if grads is None:
+            grads = torch.empty(self.n_params, dtype=torch.float32, device=dev)
+        if loss is None:
+            loss = torch.empty(2, dtype=torch.float32, device=dev)
+        _need(board, torch.int8, (n, self.rows * self.cols), "board")
+        _need(to_move, torch.int8, (n,), "to_move")
+        _need(action, torch.int16, (n,), "action")
+        _need(z, torch.float32, (n,), "z")
+        _need(grads, torch.float32, (self.n_params,), "grads")
+        _need(loss, torch.float32, (2,), "loss")
+        ws = self.workspace(n, training=True)
+        _check(_load().ludax_net_loss_grad(self._h, _ptr(self.params), _ptr(self.packed), _ptr(board),
+                                           _ptr(to_move), _ptr(action), _ptr(z), n, ctypes.c_float(beta),
+                                           _ptr(loss), _ptr(grads), _ptr(ws), _stream(stream)),
+               "ludax_net_loss_grad")
+        return loss, grads
+
+    def adam(self, grads, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.step += 1
+        _need(grads, torch.float32, (self.n_params,), "grads")
+        _check(_load().ludax_net_adam(self._h, _ptr(self.params), _ptr(grads), _ptr(self.m), _ptr(self.v),
+                                      self.step, ctypes.c_float(lr), ctypes.c_float(beta1),
+                                      ctypes.c_float(beta2), ctypes.c_float(eps), _ptr(self.packed),
+                                      _stream(stream)), "ludax_net_adam")
+
+    def estimate(self, state: "State", out=None, stream=None):
+        n = state.n
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=state.board.device)
+        _need(out, torch.float32, (n,), "estimate")
+        ws = self.workspace(n)
+        _check(_load().ludax_net_estimate(self._h, _ptr(self.params), _ptr(self.packed),
+                                          ctypes.byref(state._c()), n, _ptr(out), _ptr(ws),
+                                          _stream(stream)), "ludax_net_estimate")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.ludax_net_destroy(h)
             self._h = None

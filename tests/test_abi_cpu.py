@@ -142,3 +142,31 @@ def test_mixed_argument_checks_need_no_gpu():
     assert L.ludax_mixed_get_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_playout(None, 1, 0, 10, 16, 16, 16, None, 16, None) == ludax.E_INVALID
     L.ludax_game_destroy(h)
+
+
+def test_net_argument_checks_need_no_gpu():
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.ludax_net_create(11, 12, ctypes.byref(h)) == ludax.E_UNSUPPORTED
+    assert L.ludax_net_create(13, 13, ctypes.byref(h)) == ludax.E_UNSUPPORTED
+    assert L.ludax_net_create(11, 11, None) == ludax.E_INVALID
+    assert L.ludax_net_create(11, 11, ctypes.byref(h)) == 0
+    npar, pb, ws, ws2 = (ctypes.c_int64() for _ in range(4))
+    assert L.ludax_net_info(h, ctypes.byref(npar), ctypes.byref(pb)) == 0
+    assert npar.value == 112706 and pb.value == 2 * (64 * 64 + 6 * 64 * 576)
+    assert L.ludax_net_workspace_bytes(h, 1000, 0, ctypes.byref(ws)) == 0
+    assert L.ludax_net_workspace_bytes(h, 1000, 1, ctypes.byref(ws2)) == 0
+    assert 0 < ws.value < ws2.value
+    assert L.ludax_net_workspace_bytes(h, -1, 0, ctypes.byref(ws)) == ludax.E_INVALID
+    s = ctypes.c_void_p(0)
+    # NULL or misaligned buffers, bad counts: rejected before any launch
+    assert L.ludax_net_forward(h, None, 256, 16, 16, 4, 16, 16, 256, s) == ludax.E_INVALID
+    assert L.ludax_net_forward(h, 16, 256, 16, 16, 4, 16, 16, 257, s) == ludax.E_INVALID
+    assert L.ludax_net_forward(h, 16, 256, 16, 16, 0, None, None, None, s) == 0
+    assert L.ludax_net_loss_grad(h, 16, 256, 16, 16, 16, 16, 0, 1.0, 16, 16, 256, s) == ludax.E_INVALID
+    assert L.ludax_net_loss_grad(h, 16, 256, 16, 16, None, 16, 4, 1.0, 16, 16, 256, s) == ludax.E_INVALID
+    assert L.ludax_net_adam(h, 16, 16, 16, 16, 0, 1e-3, 0.9, 0.999, 1e-8, None, s) == ludax.E_INVALID
+    assert L.ludax_net_adam(h, 16, 16, 16, 16, 1, 1e-3, 1.0, 0.999, 1e-8, None, s) == ludax.E_INVALID
+    assert L.ludax_net_estimate(h, 16, 256, None, 4, 16, 256, s) == ludax.E_INVALID
+    assert L.ludax_net_pack(h, None, 256, s) == ludax.E_INVALID
+    assert L.ludax_net_destroy(h) == 0

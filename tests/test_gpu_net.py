@@ -1,0 +1,127 @@
+"""GPU parity of the policy/value network (ludax_net_*) against the float64
+oracle with the same bfloat16 rounding points (oracle/net_ref.py).
+
+Tolerance: the GPU sums in float32 where the oracle sums in float64, so a
+value that the oracle rounds to bfloat16 can land one bfloat16 step (2^-8
+relative) away on the GPU when it lies within float32 rounding noise of a
+rounding boundary (a fraction of about 1e-4 of the values); everything else
+agrees to float32 accuracy.  Both effects stay far below a relative L2 error
+of 1e-3 over a whole output, which is the bound used here (and 1e-2 of the
+largest magnitude for any single element)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import net_ref as R
+from oracle import ref
+from paper_2506_22609_amd.workloads import init_net_params
+from tests.gpu_util import to_device
+from tests.oracle_util import random_states
+
+pytestmark = pytest.mark.gpu
+
+ludax = pytest.importorskip("paper_2506_22609_amd.ludax")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def close(got, exp, rel=1e-3, elem=1e-2):
+    got, exp = np.asarray(got, np.float64), np.asarray(exp, np.float64)
+    scale = max(np.abs(exp).max(), 1e-30)
+    err = np.linalg.norm(got - exp) / max(np.linalg.norm(exp), 1e-30)
+    worst = np.abs(got - exp).max() / scale
+    assert err <= rel and worst <= elem, f"relative L2 error {err:.3g}, worst element {worst:.3g}"
+
+
+def _states(kind, N, n, seed):
+    g = ref.Game(kind, N, N)
+    s = random_states(g, n, N * N // 2, np.random.default_rng(seed))
+    return g, s
+
+
+def _net(N, seed):
+    p = init_net_params(seed)
+    net = ludax.Net(N, N, params=torch.from_numpy(p).cuda())
+    return net, p.astype(np.float64)
+
+
+@pytest.mark.parametrize("N,n", [(11, 70), (11, 1), (19, 21)])
+def test_forward_matches_oracle(N, n):
+    g, s = _states(ref.HEX, N, n, 1 + N)
+    net, p = _net(N, 2)
+    logits, value = net.forward(torch.from_numpy(s.board).cuda(), torch.from_numpy(s.to_move).cuda())
+    f = R.forward(p, s.board, s.to_move, N, bf16=True)
+    close(logits.cpu().numpy(), f["logits"])
+    close(value.cpu().numpy(), f["value"])
+
+
+@pytest.mark.parametrize("kind", [ref.HEX, ref.GOMOKU], ids=["hex", "gomoku"])
+@pytest.mark.parametrize("N,n", [(11, 67), (19, 9)])
+def test_loss_and_gradient_match_oracle(kind, N, n):
+    g, s = _states(kind, N, n, 3 + N)
+    keep = s.status == ref.RUNNING
+    s = s.subset(np.flatnonzero(keep))
+    n = s.n
+    rng = np.random.default_rng(4)
+    act = np.array([rng.choice(np.flatnonzero(s.board[i] == 0)) for i in range(n)], np.int16)
+    z = rng.choice([-1.0, 0.0, 1.0], size=n).astype(np.float32)
+    net, p = _net(N, 5)
+    loss, grads = net.loss_grad(torch.from_numpy(s.board).cuda(), torch.from_numpy(s.to_move).cuda(),
+                                torch.from_numpy(act).cuda(), torch.from_numpy(z).cuda(), beta=0.7)
+    (lv, lp), eg = R.loss_and_grads(p, s.board, s.to_move, act.astype(np.int64), z.astype(np.float64), N,
+                                    beta=0.7, bf16=True)
+    close(loss.cpu().numpy(), [lv, lp])
+    gg = grads.cpu().numpy()
+    o = 0
+    for name, shape in R.param_shapes():
+        k = int(np.prod(shape))
+        if name == "bp":
+            # exactly zero: a shift of every logit leaves the softmax unchanged,
+            # so only float32 noise of a sum of n * cells terms below 2 is allowed
+            assert abs(eg[o]) < 1e-12 and abs(gg[o]) < 1e-5, (eg[o], gg[o])
+            o += k
+            continue
+        try:
+            close(gg[o:o + k], eg[o:o + k])
+        except AssertionError as e:
+            raise AssertionError(f"{name}: {e}")
+        o += k
+
+
+def test_adam_step_matches_oracle():
+    N = 11
+    net, p = _net(N, 6)
+    rng = np.random.default_rng(7)
+    gr = [rng.standard_normal(p.size).astype(np.float32) * 0.01 for _ in range(3)]
+    m = np.zeros(p.size)
+    v = np.zeros(p.size)
+    q = p.copy()
+    for k, gk in enumerate(gr):
+        net.adam(torch.from_numpy(gk).cuda(), lr=1e-3)
+        q, m, v = R.adam(q, gk.astype(np.float64), m, v, k + 1, lr=1e-3)
+    got = net.params.cpu().numpy()
+    assert np.abs(got - q).max() <= 1e-6 * max(1.0, np.abs(q).max())
+    # the packed copy follows the parameters: the forward equals the oracle's at q
+    _, s = _states(ref.HEX, N, 8, 8)
+    _, value = net.forward(torch.from_numpy(s.board).cuda(), torch.from_numpy(s.to_move).cuda())
+    close(value.cpu().numpy(), R.forward(q, s.board, s.to_move, N)["value"])
+
+
+def test_estimate_of_running_and_ended_states():
+    N = 11
+    og, s = _states(ref.HEX, N, 150, 9)
+    s.status[::11] = ref.ILLEGAL
+    dg = ludax.Game(ref.HEX, N, N)
+    d = to_device(dg, s)
+    net, p = _net(N, 10)
+    est = net.estimate(d).cpu().numpy()
+    v = R.forward(p, s.board, s.to_move, N)["value"]
+    exp = np.where(s.status == ref.TERMINAL, np.where(s.winner == 1, 1.0, np.where(s.winner == 2, -1.0, 0.0)),
+                   np.where(s.status == ref.RUNNING, np.where(s.to_move == 1, v, -v), 0.0))
+    ended = s.status != ref.RUNNING
+    assert np.array_equal(est[ended], exp[ended])
+    close(est[~ended], exp[~ended])
