@@ -276,9 +276,9 @@ int ludax_net_forward(const ludax_net *net, const float *params, const void *pac
 /* Loss and gradient of a batch of n samples (position, action[i] = the cell
  * played in it, which must be empty, z[i] = the final outcome for the mover,
  * +1 / 0 / -1):
- *   L = (1/n) sum_i (v_i - z_i)^2 + beta (z_i - v_i) (-log pi_i[action_i])
+ *   L = (1/n) sum_i (v_i - z_i)^2 + beta max(z_i - v_i, 0) (-log pi_i[action_i])
  * where pi_i is the softmax of the logits over the empty cells and the
- * factor (z_i - v_i) of the second term is held constant.  loss [2] float32
+ * weight max(z_i - v_i, 0) of the second term is held constant.  loss [2] float32
  * receives the two parts; grads [n_params] float32 is overwritten with dL /
  * d(params).  Gradients of the trunk flow through bfloat16: each layer's
  * pre-activation gradient is rounded to bfloat16 before it multiplies

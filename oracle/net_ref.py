@@ -25,12 +25,14 @@ one of its own benchmark configuration, written out here step by step:
 Loss of a batch of n samples (state s_i, action a_i played in s_i, final
 outcome z_i for the mover of s_i) with policy weight beta:
 
-  L = (1/n) sum_i [ (v_i - z_i)^2 + beta (z_i - sg(v_i)) (-log pi_i[a_i]) ]
+  L = (1/n) sum_i [ (v_i - z_i)^2 + beta max(z_i - sg(v_i), 0) (-log pi_i[a_i]) ]
 
 (sg = value held constant): value regression to the outcome, and the
-outcome-minus-value weighted log-likelihood of the move that was played,
-which raises the probability of moves after which the mover did better than
-the value predicted.
+log-likelihood of the move that was played, weighted by how much better
+than predicted the mover did (clipped at zero: with negative weights the
+objective has no lower bound, since it is minimised by driving the
+probability of a losing move to zero), which raises the probability of
+moves after which the mover did better than the value predicted.
 
 bf16=True rounds, to bfloat16 (round to nearest, ties to even), exactly the
 quantities the GPU kernels keep in bfloat16: the conv weights, each Y_l, and
@@ -183,7 +185,7 @@ def loss_and_grads(params, board, to_move, action, z, N, beta=1.0, bf16=True, fw
     v = f["value"]
     pi = masked_softmax(f["logits_frame"], f["legal_frame"])
     a = frame_index(action, to_move, N)
-    adv = z - v  # held constant
+    adv = np.maximum(z - v, 0.0)  # held constant
     logp = np.log(pi[np.arange(n), a])
     loss_v = np.mean((v - z) ** 2)
     loss_p = np.mean(beta * adv * (-logp))

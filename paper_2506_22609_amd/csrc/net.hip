@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ 
     }
 #pragma unroll
     for (int s = 32; s >= 1; s >>= 1) se += __shfl_xor(se, s);
-    const float adv = zb - v;
+    const float adv = fmaxf(zb - v, 0.f); // weight of the move's log-likelihood, clipped at zero
     const float du = 2.f * (v - zb) * inv_n * (1.f - v * v);
     if (lane == 0) {
         du_out[b] = du;

@@ -139,7 +139,7 @@ def test_backward_matches_finite_differences():
     board, tm, act, z = _batch(N, 6, 7)
     p = _params(8)
     f0 = R.forward(p, board, tm, N, bf16=False)
-    adv = z - f0["value"]
+    adv = np.maximum(z - f0["value"], 0.0)
 
     def loss(q):
         f = R.forward(q, board, tm, N, bf16=False)
@@ -199,7 +199,7 @@ def test_backward_matches_torch_autograd_with_bf16_rounding_points():
     logp = torch.log_softmax(lf.masked_fill(~legal, -np.inf), dim=1)
     a = torch.from_numpy(R.frame_index(act, tm, N))
     zt = torch.from_numpy(z)
-    adv = (zt - v).detach()
+    adv = torch.clamp(zt - v, min=0.0).detach()
     L = torch.mean((v - zt) ** 2) + torch.mean(adv * -logp[torch.arange(n), a])
     L.backward()
     tg = np.concatenate([P[name].grad.numpy().ravel() for name, _ in R.param_shapes()])
