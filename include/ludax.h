@@ -177,6 +177,18 @@ int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed,
                       int64_t game_id_base, const int64_t *game_id, int8_t *reward,
                       uint8_t *terminal, int64_t n, hipStream_t stream);
 
+/* One ply drawn from a policy instead of uniformly (the move proposal of
+ * a learned policy, Sec. 7): exactly ludax_random_step, except that a
+ * RUNNING env with legal placements plays the first legal action a (in
+ * increasing order) at which the running float32 sum of exp(logits[a] -
+ * max) over the legal placements exceeds u * (their total), u = (w >> 8) /
+ * 2^24 for the ply's Philox word w (the last legal placement if rounding
+ * leaves none); with no legal placement (Reversi) it passes.  logits:
+ * [n][A] float32 in action order (a PASS entry is ignored). */
+int ludax_policy_step(const ludax_game *game, ludax_state *state, const float *logits, uint64_t seed,
+                      int64_t game_id_base, const int64_t *game_id, int8_t *reward, uint8_t *terminal,
+                      int64_t n, hipStream_t stream);
+
 /* Counter reduction used by ludax_playout's stats, exposed on its own:
  * stats[0..3] += sign * (sum of ply, number of TERMINAL envs won by player
  * 1, won by player 2, drawn) over the n envs; sign is +1 or -1.  Calling

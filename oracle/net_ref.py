@@ -219,3 +219,26 @@ def adam(params, grads, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return params - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def policy_action(logits, legal, w):
+    """The move a policy step draws: over the legal actions in increasing
+    order, the running float32 sum of exp(logit - max) is compared with
+    u * total, u = (w >> 8) / 2^24 (w = the ply's 32-bit Philox word); the
+    first action whose running sum exceeds it is played (the last legal one
+    if none does).  Returns (action, margin): margin is the smallest distance
+    between the threshold and a running sum, relative to the total, which
+    says how close the draw was to picking a neighbour (an exp that differs
+    in the last bit can move a running sum across the threshold only when
+    the margin is of the order of float32 rounding)."""
+    idx = np.flatnonzero(legal)
+    lg = np.asarray(logits, np.float32)[idx]
+    mx = lg.max()
+    e = np.exp((lg - mx).astype(np.float32)).astype(np.float32)
+    run = np.cumsum(e, dtype=np.float32)  # sequential float32 sums
+    tot = run[-1]
+    thr = np.float32(np.float32(w >> 8) * np.float32(2.0 ** -24)) * tot
+    hit = np.flatnonzero(run > thr)
+    a = int(idx[hit[0]]) if hit.size else int(idx[-1])
+    margin = float(np.min(np.abs(run.astype(np.float64) - float(thr))) / float(tot))
+    return a, margin

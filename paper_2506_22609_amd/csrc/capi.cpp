@@ -207,6 +207,20 @@ int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed,
                                                terminal, stream));
 }
 
+int ludax_policy_step(const ludax_game *game, ludax_state *state, const float *logits, uint64_t seed,
+                      int64_t game_id_base, const int64_t *game_id, int8_t *reward, uint8_t *terminal,
+                      int64_t n, hipStream_t stream)
+{
+    if (game == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (n == 0) return LUDAX_OK;
+    if (logits == nullptr || reward == nullptr || terminal == nullptr) return LUDAX_E_INVALID;
+    lx::DevState d;
+    int rc = check_state(state, &d);
+    if (rc) return rc;
+    return device_error(game->ops->policy_step(d, n, game->max_plies, logits, seed, game_id_base, game_id, reward,
+                                               terminal, stream));
+}
+
 int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t sign, int64_t *stats,
                       int64_t n, hipStream_t stream)
 {

@@ -168,16 +168,19 @@ __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t 
 }
 
 // ---------------------------------------------------------------------------
-// a4-a6 for one ply: ludax_step (caller-chosen action, RANDOM = false) and
-// ludax_random_step (the uniform-random action of a3, RANDOM = true).  The
+// a4-a6 for one ply: ludax_step (caller-chosen action, MODE 0),
+// ludax_random_step (the uniform-random action of a3, MODE 1) and
+// ludax_policy_step (an action drawn from the softmax of given logits over
+// the legal actions with the same Philox word, MODE 2).  The
 // state stays in HBM between launches, so this kernel is bound by its bytes:
 // the block's statuses are read first and a block with no RUNNING env reads
 // no board; only envs that were RUNNING write their scalars back, and a
 // placement writes the one cell it changed (Reversi: the whole 64-cell board).
 // ---------------------------------------------------------------------------
-template <class G, bool RANDOM>
+template <class G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_plies,
-                                                const int32_t *__restrict__ action, uint32_t key0,
+                                                const int32_t *__restrict__ action,
+                                                const float *__restrict__ logits, uint32_t key0,
                                                 uint32_t key1, int64_t gid_base,
                                                 const int64_t *__restrict__ gid,
                                                 int8_t *__restrict__ reward,
@@ -223,8 +226,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
     if (was_running) {
         const typename G::M m = g.placements(me);
         bool legal, is_pass;
-        if constexpr (RANDOM) {
-            // the ply's word of the game's Philox stream, k-th legal action
+        if constexpr (MODE >= 1) {
+            // the ply's word of the game's Philox stream
             const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
             const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
             const int r = ply & 3;
@@ -232,7 +235,31 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
             const int np = popcount(m);
             is_pass = G::HAS_PASS && np == 0;
             legal = np > 0 || is_pass; // a hand-edited board may leave no action
-            if (np > 0) a = G::action_of(select_bit(m, (int)__umulhi(w, (uint32_t)np)));
+            if constexpr (MODE == 1) {
+                // uniform: the k-th legal action, k = (w * n_legal) >> 32
+                if (np > 0) a = G::action_of(select_bit(m, (int)__umulhi(w, (uint32_t)np)));
+            } else {
+                // softmax of the logits over the legal placements (float32,
+                // in increasing action order): the first action whose running
+                // sum of exp(logit - max) exceeds u * total, u = (w >> 8) / 2^24
+                const float *lg = logits + ec * G::A;
+                float mx = -3.0e38f;
+                for (int c = 0; c < G::CELLS; ++c)
+                    if (test_bit(m, G::bit_of(c))) mx = fmaxf(mx, lg[c]);
+                float tot = 0.f;
+                for (int c = 0; c < G::CELLS; ++c)
+                    if (test_bit(m, G::bit_of(c))) tot += expf(lg[c] - mx);
+                const float thr = (float)(w >> 8) * 0x1p-24f * tot;
+                float run = 0.f;
+                int pick = -1, lastc = -1;
+                for (int c = 0; c < G::CELLS; ++c)
+                    if (test_bit(m, G::bit_of(c))) {
+                        run += expf(lg[c] - mx);
+                        lastc = c;
+                        if (pick < 0 && run > thr) pick = c;
+                    }
+                if (np > 0) a = pick >= 0 ? pick : lastc;
+            }
             if (is_pass) a = G::A - 1;
         } else {
             a = action[ec];
@@ -859,8 +886,9 @@ struct Launch {
                            int8_t *reward, uint8_t *terminal, uint8_t *next_mask, hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL((k_step<G, false>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
-                           action, 0u, 0u, (int64_t)0, (const int64_t *)nullptr, reward, terminal, next_mask);
+        hipLaunchKernelGGL((k_step<G, 0>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                           action, (const float *)nullptr, 0u, 0u, (int64_t)0, (const int64_t *)nullptr, reward,
+                           terminal, next_mask);
         return hipGetLastError();
     }
     static hipError_t random_step(const DevState &st, int64_t n, int max_plies, uint64_t seed,
@@ -868,8 +896,18 @@ struct Launch {
                                   hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL((k_step<G, true>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
-                           (const int32_t *)nullptr, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid,
+        hipLaunchKernelGGL((k_step<G, 1>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                           (const int32_t *)nullptr, (const float *)nullptr, (uint32_t)seed, (uint32_t)(seed >> 32),
+                           gid_base, gid, reward, terminal, (uint8_t *)nullptr);
+        return hipGetLastError();
+    }
+    static hipError_t policy_step(const DevState &st, int64_t n, int max_plies, const float *logits,
+                                  uint64_t seed, int64_t gid_base, const int64_t *gid, int8_t *reward,
+                                  uint8_t *terminal, hipStream_t s)
+    {
+        const int64_t blocks = (n + BLOCK - 1) / BLOCK;
+        hipLaunchKernelGGL((k_step<G, 2>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+                           (const int32_t *)nullptr, logits, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid,
                            reward, terminal, (uint8_t *)nullptr);
         return hipGetLastError();
     }
@@ -904,7 +942,8 @@ struct Launch {
     }
     static constexpr GameOps ops()
     {
-        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &playout, &persist};
+        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step, &playout,
+                       &persist};
     }
 };
 

@@ -39,6 +39,8 @@ struct GameOps {
                        hipStream_t);
     hipError_t (*random_step)(const DevState &, int64_t, int, uint64_t, int64_t, const int64_t *, int8_t *,
                               uint8_t *, hipStream_t);
+    hipError_t (*policy_step)(const DevState &, int64_t, int, const float *, uint64_t, int64_t, const int64_t *,
+                              int8_t *, uint8_t *, hipStream_t);
     hipError_t (*playout)(const DevState &, int64_t, int, uint64_t, int64_t, const int64_t *, int8_t *,
                           uint8_t *, int64_t *, hipStream_t);
     hipError_t (*persist)(const MixedArgs &, int, hipStream_t);

@@ -155,7 +155,7 @@ __device__ __forceinline__ void zero_ring(uint16_t *act_b, int lane)
 // (board, group of up to 8 cell tiles).
 // ---------------------------------------------------------------------------
 template <int N, int CIN, int MODE>
-__global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
+__global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x, const uint16_t *__restrict__ w,
                                               const float *__restrict__ bias,
                                               const uint16_t *__restrict__ mask, uint16_t *__restrict__ out,
                                               int64_t n)
@@ -197,12 +197,9 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int ks = 0; ks < K / 32; ++ks) {
-        const int k0 = ks * 32 + quad * 8; // this lane's 8 consecutive k
-        bf16x8 bfr[4];
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-            bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * KS + k0));
+    // A fragments of K-step ks: this lane's 8 consecutive k of each tile row
+    auto load_a = [&](int ks, bf16x8 (&a)[8]) {
+        const int k0 = ks * 32 + quad * 8;
         int off0, off1;
         if constexpr (CIN == 4) {
             // k = tap * 4 + channel: two taps per lane; taps >= 9 read tap 0
@@ -219,18 +216,36 @@ __global__ __launch_bounds__(256) void k_conv(const uint16_t *__restrict__ x, co
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             if (g * 8 + mt >= MT) break;
-            bf16x8 a;
             if constexpr (CIN == 4) {
                 const uint2 lo = *reinterpret_cast<const uint2 *>(xb + cell_off[mt] + off0);
                 const uint2 hi = *reinterpret_cast<const uint2 *>(xb + cell_off[mt] + off1);
-                a = as_bf16x8(uint4{lo.x, lo.y, hi.x, hi.y});
+                a[mt] = as_bf16x8(uint4{lo.x, lo.y, hi.x, hi.y});
             } else {
-                a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + cell_off[mt] + off0));
+                a[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + cell_off[mt] + off0));
             }
+        }
+    };
+    // software pipeline: the next K-step's A fragments load while this
+    // step's MFMAs run
+    constexpr int KSTEPS = K / 32;
+    bf16x8 a_cur[8], a_nxt[8];
+    load_a(0, a_cur);
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int k0 = ks * 32 + quad * 8;
+        bf16x8 bfr[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * KS + k0));
+        if (ks + 1 < KSTEPS) load_a(ks + 1, a_nxt);
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            if (g * 8 + mt >= MT) break;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
         }
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) a_cur[mt] = a_nxt[mt];
     }
 
     // epilogue: lane holds rows 4 * quad + i (cells) of column row (channel)
@@ -417,34 +432,38 @@ __global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ 
 constexpr int HEAD_PART = 2 * C + 2;
 
 template <int N>
-__global__ __launch_bounds__(64) void k_head_wgrad(const uint16_t *__restrict__ y4, const float *__restrict__ dlog,
-                                                   const float *__restrict__ du, int64_t n,
-                                                   float *__restrict__ part)
+__global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t *__restrict__ y4, const float *__restrict__ dlog,
+                                                    const float *__restrict__ du, int64_t n,
+                                                    float *__restrict__ part)
 {
+    // one wave per board, lane = channel; the block's four waves add up in LDS
     constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
-    const int c = threadIdx.x;
+    __shared__ float red[4][HEAD_PART];
+    const int c = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float ap = 0.f, av = 0.f, sp = 0.f, sv = 0.f;
-    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+    for (int64_t b = (int64_t)blockIdx.x * 4 + wave; b < n; b += (int64_t)gridDim.x * 4) {
         const uint16_t *yb = y4 + b * (int64_t)PP * C;
-        const float dub = du[b];
+        const float *db = dlog + b * PIX;
         float mv = 0.f;
         for (int q = 0; q < PIX; ++q) {
             const float y = bf2f(yb[(int64_t)((q / N + 1) * NP + (q % N) + 1) * C + c]);
-            const float d = dlog[b * PIX + q];
+            const float d = db[q];
             ap += d * y;
             mv += y;
-            if (c == 0) sp += d;
+            sp += d; // every lane adds the same sum; lane 0's is kept
         }
-        av += dub * mv / (float)PIX;
-        if (c == 0) sv += dub;
+        av += du[b] * mv / (float)PIX;
+        sv += du[b];
     }
-    float *o = part + (int64_t)blockIdx.x * HEAD_PART;
-    o[c] = ap;
-    o[C + 1 + c] = av;
+    red[wave][c] = ap;
+    red[wave][C + 1 + c] = av;
     if (c == 0) {
-        o[C] = sp;
-        o[2 * C + 1] = sv;
+        red[wave][C] = sp;
+        red[wave][2 * C + 1] = sv;
     }
+    __syncthreads();
+    for (int j = threadIdx.x; j < HEAD_PART; j += 256)
+        part[(int64_t)blockIdx.x * HEAD_PART + j] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
 }
 
 // ---------------------------------------------------------------------------
@@ -574,15 +593,25 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     if (threadIdx.x < C) o[C * CR * 9 + threadIdx.x] = dbias;
 }
 
-// out[j] (+)= sum over rows r < rows of part[r * stride + j], j < cols
-__global__ void k_sum_rows(const float *__restrict__ part, int64_t rows, int stride, int cols,
-                           float *__restrict__ out)
+// out[j] = sum over rows r < rows of part[r * stride + j], j < cols: a block
+// takes 32 columns, its 8 waves' worth of row groups add up in LDS
+__global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part, int64_t rows, int stride, int cols,
+                                                  float *__restrict__ out)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cols) return;
+    __shared__ float red[8][32];
+    const int cl = threadIdx.x & 31, grp = threadIdx.x >> 5;
+    const int j = blockIdx.x * 32 + cl;
     float s = 0.f;
-    for (int64_t r = 0; r < rows; ++r) s += part[r * stride + j];
-    out[j] = s;
+    if (j < cols)
+        for (int64_t r = grp; r < rows; r += 8) s += part[r * stride + j];
+    red[grp][cl] = s;
+    __syncthreads();
+    if (grp == 0 && j < cols) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t += red[k][cl];
+        out[j] = t;
+    }
 }
 
 // value cutoff estimate for player 1
@@ -620,7 +649,8 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 namespace {
 
 constexpr int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
-constexpr int WG_BLOCKS = 256; // blocks of the weight-gradient reductions
+constexpr int WG_BLOCKS = 256;  // blocks of the conv weight-gradient reductions
+constexpr int HW_BLOCKS = 1024; // blocks of the head weight-gradient reduction
 
 int64_t blocks_min(int64_t n, int64_t cap) { return n < cap ? n : cap; }
 
@@ -646,7 +676,7 @@ struct Sizes {
     {
         return align256(a0(n)) + 6 * align256(act(n)) + 3 * align256(n * PIX * 4) + 3 * align256(n * 4) +
                align256(n * 8) + align256((int64_t)WG_BLOCKS * (C * C * 9 + C) * 4) +
-               align256((int64_t)WG_BLOCKS * HEAD_PART * 4);
+               align256((int64_t)HW_BLOCKS * HEAD_PART * 4);
     }
 };
 
@@ -699,7 +729,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     cv.take<float>(n * 4);
     float *lterms = cv.take<float>(n * 8);
     float *part = cv.take<float>((int64_t)WG_BLOCKS * (C * C * 9 + C) * 4);
-    float *hpart = cv.take<float>((int64_t)WG_BLOCKS * HEAD_PART * 4);
+    float *hpart = cv.take<float>((int64_t)HW_BLOCKS * HEAD_PART * 4);
 
     const unsigned eb = (unsigned)((n * S::PP + 255) / 256), cb = (unsigned)((n * NG + 3) / 4),
                    hb = (unsigned)((n + 3) / 4);
@@ -713,13 +743,14 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
                        action, z, n, beta, 1.f / (float)n, dlog, du, lterms, ga);
-    hipLaunchKernelGGL(k_head_wgrad<N>, dim3(wb), dim3(64), 0, s, y[4], dlog, du, n, hpart);
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, hpart, (int64_t)wb, HEAD_PART, HEAD_PART,
-                       grads + WP_OFF);
+    const unsigned hwb = (unsigned)blocks_min((n + 3) / 4, HW_BLOCKS);
+    hipLaunchKernelGGL(k_head_wgrad<N>, dim3(hwb), dim3(256), 0, s, y[4], dlog, du, n, hpart);
+    hipLaunchKernelGGL(k_sum_rows, dim3((HEAD_PART + 31) / 32), dim3(256), 0, s, hpart, (int64_t)hwb, HEAD_PART,
+                       HEAD_PART, grads + WP_OFF);
     constexpr int PART64 = C * C * 9 + C, PART4 = C * 27 + C;
     for (int l = 4; l >= 2; --l) {
         hipLaunchKernelGGL((k_conv_wgrad<N, 64>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
-        hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 255) / 256), dim3(256), 0, s, part, (int64_t)wb, PART64,
+        hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
         hipLaunchKernelGGL((k_conv<N, 64, 1>), dim3(cb), dim3(256), 0, s, ga, packed + pb_off(l),
                            (const float *)nullptr, y[l - 1], gb, n);
@@ -728,9 +759,9 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         gb = t;
     }
     hipLaunchKernelGGL((k_conv_wgrad<N, 4>), dim3(wb), dim3(256), 0, s, ga, y[0], n, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 255) / 256), dim3(256), 0, s, part, (int64_t)wb, PART4, PART4,
+    hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART4, PART4,
                        grads + w_off(1));
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, s, lterms, n, 2, 2, loss);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, lterms, n, 2, 2, loss);
     return hipGetLastError();
 }
 

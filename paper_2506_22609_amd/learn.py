@@ -120,3 +120,23 @@ def cutoff_estimate(game: ludax.Game, net: ludax.Net, s: ludax.State, k: int, se
     for _ in range(k):
         ludax.random_step(game, s, seed, id_base, reward=r, terminal=t)
     return net.estimate(s)
+
+
+def play_vs_random(game: ludax.Game, net: ludax.Net, n: int, net_player: int, seed: int, id_base: int):
+    """n games of the network's policy (ludax_policy_step on the logits of
+    ludax_net_forward) against the uniform-random policy, the network moving
+    for net_player (1 or 2).  All games start together and the mover of
+    every running game at ply t is the same, so each ply is one call of one
+    of the two steps.  Returns (net wins, opponent wins, draws)."""
+    s = ludax.State(game, n)
+    ludax.init(game, s)
+    r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
+    t = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for ply in range(game.max_plies):
+        if ply % 2 == net_player - 1:
+            logits, _ = net.forward(s.board, s.to_move)
+            ludax.policy_step(game, s, logits, seed, id_base, reward=r, terminal=t)
+        else:
+            ludax.random_step(game, s, seed, id_base, reward=r, terminal=t)
+    w = s.winner
+    return (int((w == net_player).sum()), int((w == 3 - net_player).sum()), int((w == 0).sum()))

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 
 # every symbol the public header declares
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
-           "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_playout",
+           "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_policy_step", "ludax_playout",
            "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy", "ludax_mixed_set_slots",
            "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune",
            "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
@@ -72,6 +72,7 @@ def _load():
             L.ludax_legal_mask.argtypes = [vp, P(_State), vp, i64, vp]
             L.ludax_step.argtypes = [vp, P(_State), vp, vp, vp, vp, i64, vp]
             L.ludax_random_step.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, i64, vp]
+            L.ludax_policy_step.argtypes = [vp, P(_State), vp, ctypes.c_uint64, i64, vp, vp, vp, i64, vp]
             L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
                                         vp]
             L.ludax_state_stats.argtypes = [vp, P(_State), ctypes.c_int32, vp, i64, vp]
@@ -98,7 +99,7 @@ def _load():
             L.ludax_last_device_error.restype = ctypes.c_char_p
             for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
                          "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_random_step",
-                         "ludax_playout",
+                         "ludax_policy_step", "ludax_playout",
                          "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy",
                          "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
                          "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy",
@@ -269,6 +270,27 @@ def random_step(game: Game, state: State, seed: int, game_id_base: int = 0, game
                                      ctypes.c_uint64(seed & (2**64 - 1)), game_id_base, _ptr(game_id),
                                      _ptr(reward), _ptr(terminal), state.n, _stream(stream)),
            "ludax_random_step")
+    return reward, terminal
+
+
+def policy_step(game: Game, state: State, logits: torch.Tensor, seed: int, game_id_base: int = 0,
+                game_id=None, reward=None, terminal=None, stream=None):
+    """One ply drawn from softmax(logits) over the legal actions (see
+    ludax_policy_step)."""
+    dev = state.board.device
+    _need(logits, torch.float32, (state.n, game.num_actions), "logits")
+    if reward is None:
+        reward = torch.empty((state.n, 2), dtype=torch.int8, device=dev)
+    if terminal is None:
+        terminal = torch.empty(state.n, dtype=torch.uint8, device=dev)
+    _need(reward, torch.int8, (state.n, 2), "reward")
+    _need(terminal, torch.uint8, (state.n,), "terminal")
+    if game_id is not None:
+        _need(game_id, torch.int64, (state.n,), "game_id")
+    _check(_load().ludax_policy_step(game.handle, ctypes.byref(state._c()), _ptr(logits),
+                                     ctypes.c_uint64(seed & (2**64 - 1)), game_id_base, _ptr(game_id),
+                                     _ptr(reward), _ptr(terminal), state.n, _stream(stream)),
+           "ludax_policy_step")
     return reward, terminal
 
 

@@ -289,3 +289,56 @@ def test_step_blocks_without_running_env(g):
     assert np.array_equal(rew, grew.cpu().numpy()) and np.array_equal(term, gterm.cpu().numpy())
     assert np.array_equal(nm, gnm.cpu().numpy())
     assert_same_state(s, from_device(d))
+
+
+@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4]], ids=["hex11", "reversi", "gomoku15"])
+def test_policy_step_sequences(g):
+    """ludax_policy_step ply by ply against the oracle's draw + step, with
+    random logits: every action equals the oracle's, except where the
+    oracle's threshold lies within float32 rounding of a running sum (then
+    the GPU's action must be one of the two legal actions at that boundary)."""
+    from oracle import net_ref as R
+    og, dg = pair(*g)
+    rng = np.random.default_rng(51 + g[0])
+    n = 150
+    s = random_states(og, n, min(og.cells, 20), rng)
+    s.status[:64] = ref.ILLEGAL
+    gid = rng.integers(0, 2**62, size=n, dtype=np.int64)
+    d = to_device(dg, s)
+    dgid = torch.from_numpy(gid).cuda()
+    seed = 77
+    close_calls = 0
+    for p in range(og.cells + 130):
+        lg = (rng.standard_normal((n, og.num_actions)) * 2.0).astype(np.float32)
+        m = ref.legal_mask(og, s)
+        a = np.full(n, -1, np.int32)
+        near = np.zeros(n, bool)
+        for i in np.flatnonzero(s.status == ref.RUNNING):
+            legal = m[i, :og.cells].astype(bool)
+            if legal.any():
+                a[i], margin = R.policy_action(lg[i, :og.cells], legal, ref.draw(seed, int(gid[i]), int(s.ply[i])))
+                near[i] = margin < 1e-5
+            elif m[i].any():
+                a[i] = og.num_actions - 1  # forced pass
+        s_before = s.copy()
+        rew, term, _ = ref.step(og, s, a, want_mask=False)
+        grew, gterm = ludax.policy_step(dg, d, torch.from_numpy(lg).cuda(), seed, game_id=dgid)
+        got = from_device(d)
+        ga = got.last_action
+        for i in np.flatnonzero(near & (ga != s.last_action)):
+            # a draw at a boundary: accept the neighbouring legal action, replay it on the oracle
+            close_calls += 1
+            legal = np.flatnonzero(m[i, :og.cells])
+            k = np.searchsorted(legal, s.last_action[i])
+            assert ga[i] in legal[max(0, k - 1):k + 2]
+            one = s_before.subset([i])
+            r1, t1, _ = ref.step(og, one, np.array([ga[i]], np.int32), want_mask=False)
+            for f in ref.State.FIELDS:
+                getattr(s, f)[i] = getattr(one, f)[0]
+            rew[i], term[i] = r1[0], t1[0]
+        assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
+        assert np.array_equal(term, gterm.cpu().numpy()), f"terminal at ply {p}"
+        assert_same_state(s, got, f"policy step {p}")
+        if (s.status != ref.RUNNING).all():
+            break
+    assert close_calls <= 2
