@@ -247,6 +247,110 @@ def _large_section(batches, seed: int, reps: int):
     return out
 
 
+def _learned_section(seed: int, train_games: int, steps: int):
+    """The learned policy/value network on Hex 11x11: samples from random
+    playouts, training by the library's own forward/backward/Adam kernels,
+    then 65536 held-out positions estimated four ways (one full random
+    playout; the value alone; 20 random plies + value cutoff; 20 plies
+    proposed by the policy for both sides + value cutoff), each timed and
+    judged against the mean of 256 full random playouts (on 4096 of the
+    positions); and the policy against the uniform-random mover."""
+    import torch
+    from paper_2506_22609_amd import learn, ludax
+    from paper_2506_22609_amd.workloads import init_net_params
+
+    g = ludax.Game(3, 11, 11)
+    t0 = time.perf_counter()
+    data = learn.collect(g, train_games, seed=seed + 100, id_base=0)
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    net = ludax.Net(11, 11, params=torch.from_numpy(init_net_params(seed)).cuda())
+    t0 = time.perf_counter()
+    losses = learn.train(net, data, steps, batch=4096, lr=1e-3, seed=seed)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    flops_fwd = (27 * 64 * 2 + 3 * 576 * 64 * 2) * 121  # per board, the four convolutions
+    lv = losses.cpu()
+    del data
+
+    ev = learn.collect(g, 12000, seed=seed + 200, id_base=10**9)
+    idx = torch.randperm(len(ev), generator=torch.Generator().manual_seed(seed))[:65536].cuda()
+    e = ev.take(idx)
+    n = e.board.shape[0]
+    base = ludax.State(g, n)
+    ludax.init(g, base)
+    base.board.copy_(e.board)
+    base.to_move.copy_(e.to_move)
+    base.ply.copy_((e.board != 0).sum(1).to(torch.int16))
+    sub = 4096
+    judge = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
+    tr = learn.truth(g, judge, 256, seed=seed + 300, id_base=2 * 10**9)
+
+    r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
+    t = torch.empty(n, dtype=torch.uint8, device="cuda")
+
+    def plain(s):
+        ludax.playout(g, s, seed + 400, 3 * 10**9, stats=None)
+        return learn.outcome_p1(s)
+
+    def value_only(s):
+        return net.estimate(s)
+
+    def cutoff(s):
+        return learn.cutoff_estimate(g, net, s, 20, seed + 500, 4 * 10**9)
+
+    def guided(s):
+        for _ in range(20):
+            logits, _ = net.forward(s.board, s.to_move)
+            ludax.policy_step(g, s, logits, seed + 600, 5 * 10**9, reward=r, terminal=t)
+        return net.estimate(s)
+
+    out = {"workload": f"hex11x11: training on {train_games} random games, {steps} Adam steps of 4096; "
+                       f"{n} held-out positions (error judged on {sub} of them against 256 full random "
+                       f"playouts each)",
+           "collect_s": t_collect, "train_s": t_train, "train_ms_per_step": t_train / steps * 1e3,
+           "train_tflops": 3 * 4096 * flops_fwd / (t_train / steps) / 1e12,
+           "value_loss_first_last": [float(lv[:50, 0].mean()), float(lv[-50:, 0].mean())],
+           "methods": {}}
+    for name, fn in (("plain_full_playout", plain), ("value_only", value_only),
+                     ("random20_value_cutoff", cutoff), ("policy20_value_cutoff", guided)):
+        s = base.clone()
+        fn(s)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            s = base.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            est = fn(s)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        el = min(ts)
+        mse = ((est[:sub] - tr) ** 2).mean().item()
+        out["methods"][name] = {"playouts_per_s": n / el, "ms_per_65536": el * 1e3 * 65536 / n,
+                                "mse_vs_256_playout_mean": mse}
+    # the value forward alone, as a fraction of the bf16 MFMA peak
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        net.forward(base.board, base.to_move)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_s = e0.elapsed_time(e1) / 5 / 1e3
+    out["forward_roofline"] = {"bound": "mfma", "achieved": n * flops_fwd / fwd_s / 1e12, "peak": 2500.0,
+                               "unit": "TFLOP/s", "frac": n * flops_fwd / fwd_s / 1e12 / 2500.0,
+                               "ms_per_65536": fwd_s * 1e3,
+                               "note": "useful conv flops (121 cells, no padding) of the whole forward "
+                                       "(encode, 4 conv layers, heads) over its event-timed duration"}
+    out["policy_vs_random"] = {}
+    for seat in (1, 2):
+        w, l, d = learn.play_vs_random(g, net, 4096, seat, seed + 700, 6 * 10**9)
+        out["policy_vs_random"][f"net_as_player{seat}"] = {"wins": w, "losses": l, "draws": d,
+                                                           "win_rate": w / 4096}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,6 +367,10 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 19x19 large-board section")
     ap.add_argument("--section-reps", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned policy/value network section")
+    ap.add_argument("--train-games", type=int, default=96000)
+    ap.add_argument("--train-steps", type=int, default=2400)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB "
                          "(a known-size reference for HBM byte counters under a profiler)")
@@ -373,6 +481,8 @@ def main():
             tuple(batches) + (() if args.no_large else W.LARGE_BATCHES), args.seed, args.section_reps)
     if not args.no_large:
         out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
+    if not args.no_learned:
+        out["learned"] = _learned_section(args.seed, args.train_games, args.train_steps)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = _cpu_baseline(batches, args.cpu_seconds)
     print(json.dumps(out), flush=True)
