@@ -247,6 +247,93 @@ def _large_section(batches, seed: int, reps: int):
     return out
 
 
+def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: float):
+    """Large boards, mixed: 1,048,576 game ids, kind = id mod 2 (Hex 19x19,
+    Gomoku 19x19), through the mixed persistent batch (slots autotuned) and
+    as the two plain single-kind batches; then per game a network trained
+    on its own random games, and 524288 held-out positions per game
+    estimated by one full random playout and by the network's value with
+    the network's workspace held to an HBM budget (positions admitted in
+    chunks of ludax_net_max_batch), judged against the mean of 256 full
+    random playouts on 2048 of them."""
+    import torch
+    from paper_2506_22609_amd import learn, ludax
+    from paper_2506_22609_amd import workloads as W
+    from paper_2506_22609_amd.workloads import init_net_params
+
+    kinds = W.LARGE_BATCHES
+    games = [ludax.Game(b.kind, b.rows, b.cols) for b in kinds]
+    n_games = sum(b.n for b in kinds)
+    m = ludax.Mixed(games)
+    out = ludax.MixedResult(n_games, len(games))
+    tune_ms = m.autotune(seed, 0, n_games, 262144, out=out)
+    stats = torch.zeros((len(games), 4), dtype=torch.int64, device="cuda")
+    m.playout(seed, 0, n_games, out=out, stats=stats)
+    torch.cuda.synchronize()
+    stats.zero_()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        m.playout(seed, (k + 1) * n_games, n_games, out=out, stats=stats)
+    torch.cuda.synchronize()
+    mixed_el = (time.perf_counter() - t0) / reps
+    res = {"workload": f"{n_games} game ids, kind = id mod 2 (hex19x19, gomoku19x19)",
+           "mixed": {"slots_per_kind": m.slots, "autotuned_ms": tune_ms, "ms_per_batch": mixed_el * 1e3,
+                     "env_steps_per_s": int(stats[:, 0].sum()) / reps / mixed_el,
+                     "playouts_per_s": n_games / mixed_el,
+                     "per_kind_env_steps_per_batch": [int(x) // reps for x in stats[:, 0].tolist()]},
+           "guided": {}}
+    del out
+    budget = int(budget_gb * 2**30)
+    for b, g in zip(kinds, games):
+        # about 10 M samples: Hex 19x19 games last ~332 plies, Gomoku 19x19 ~159
+        data = learn.collect(g, 30000 if b.kind == W.HEX else 60000, seed=seed + 800, id_base=0)
+        net = ludax.Net(b.rows, b.cols, params=torch.from_numpy(init_net_params(seed)).cuda())
+        t0 = time.perf_counter()
+        learn.train(net, data, train_steps, batch=4096, lr=1e-3, seed=seed)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        n_train = len(data)
+        del data
+        ev = learn.collect(g, 8000, seed=seed + 900, id_base=10**9)
+        idx = torch.randperm(len(ev), generator=torch.Generator().manual_seed(seed))[:b.n].cuda()
+        e = ev.take(idx)
+        del ev
+        n = e.board.shape[0]
+        base = ludax.State(g, n)
+        ludax.init(g, base)
+        base.board.copy_(e.board)
+        base.to_move.copy_(e.to_move)
+        base.ply.copy_((e.board != 0).sum(1).to(torch.int16))
+        sub = 2048
+        judge = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
+        tr = learn.truth(g, judge, 256, seed=seed + 950, id_base=2 * 10**9)
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+        timings = {}
+        for name in ("plain_full_playout", "value_budgeted"):
+            for rep in range(2):
+                s = base.clone()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if name == "plain_full_playout":
+                    ludax.playout(g, s, seed + 960, 3 * 10**9, stats=None)
+                    est = learn.outcome_p1(s)
+                else:
+                    learn.estimate_budgeted(g, net, s, budget, out=est)
+                torch.cuda.synchronize()
+                timings[name] = time.perf_counter() - t0
+            timings[name + "_mse"] = ((est[:sub] - tr) ** 2).mean().item()
+        res["guided"][b.name] = {
+            "positions": n, "train_samples": n_train, "train_steps": train_steps, "train_s": t_train,
+            "hbm_budget_bytes": budget, "admitted_chunk": net.max_batch(budget),
+            "plain_full_playout": {"playouts_per_s": n / timings["plain_full_playout"],
+                                   "mse_vs_256_playout_mean": timings["plain_full_playout_mse"]},
+            "value_budgeted": {"playouts_per_s": n / timings["value_budgeted"],
+                               "mse_vs_256_playout_mean": timings["value_budgeted_mse"]}}
+        del base, judge, net
+        torch.cuda.synchronize()
+    return res
+
+
 def _learned_section(seed: int, train_games: int, steps: int):
     """The learned policy/value network on Hex 11x11: samples from random
     playouts, training by the library's own forward/backward/Adam kernels,
@@ -371,6 +458,9 @@ def main():
                     help="skip the learned policy/value network section")
     ap.add_argument("--train-games", type=int, default=96000)
     ap.add_argument("--train-steps", type=int, default=2400)
+    ap.add_argument("--large-train-steps", type=int, default=1200)
+    ap.add_argument("--hbm-budget-gb", type=float, default=16.0,
+                    help="HBM held by the network's workspace in the large-board guided estimate")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB "
                          "(a known-size reference for HBM byte counters under a profiler)")
@@ -483,6 +573,9 @@ def main():
         out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
     if not args.no_learned:
         out["learned"] = _learned_section(args.seed, args.train_games, args.train_steps)
+    if not args.no_large and not args.no_learned:
+        out["large_mixed"] = _large_mixed_section(args.seed, args.section_reps, args.large_train_steps,
+                                                  args.hbm_budget_gb)
     if args.cpu_seconds > 0:
         out["cpu_baseline"] = _cpu_baseline(batches, args.cpu_seconds)
     print(json.dumps(out), flush=True)

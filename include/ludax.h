@@ -275,6 +275,10 @@ int ludax_net_create(int32_t rows, int32_t cols, ludax_net **out);
 int ludax_net_destroy(ludax_net *net);
 int ludax_net_info(const ludax_net *net, int64_t *n_params, int64_t *packed_bytes);
 int ludax_net_workspace_bytes(const ludax_net *net, int64_t n, int32_t training, int64_t *bytes);
+/* HBM-budget admission: *n = the largest batch whose workspace (training or
+ * inference) fits in budget_bytes (0 if none).  Large-board batches that do
+ * not fit are evaluated in chunks of this size. */
+int ludax_net_max_batch(const ludax_net *net, int64_t budget_bytes, int32_t training, int64_t *n);
 int ludax_net_pack(const ludax_net *net, const float *params, void *packed, hipStream_t stream);
 
 /* Forward pass of n positions (board [n][N*N] int8 and to_move [n] int8, as

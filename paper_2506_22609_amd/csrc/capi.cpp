@@ -506,6 +506,23 @@ int ludax_net_workspace_bytes(const ludax_net *net, int64_t n, int32_t training,
     return LUDAX_OK;
 }
 
+int ludax_net_max_batch(const ludax_net *net, int64_t budget_bytes, int32_t training, int64_t *n)
+{
+    if (net == nullptr || n == nullptr || budget_bytes < 0) return LUDAX_E_INVALID;
+    auto bytes = [&](int64_t k) {
+        return training ? lx::net_train_ws_bytes(net->n, k) : lx::net_forward_ws_bytes(net->n, k);
+    };
+    // the workspace grows with the batch: binary search of the largest fit
+    int64_t lo = 0, hi = MAX_ENVS;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (bytes(mid) <= budget_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    *n = lo > 0 && bytes(lo) <= budget_bytes ? lo : 0;
+    return LUDAX_OK;
+}
+
 namespace {
 bool aligned256(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
 } // namespace

@@ -140,3 +140,20 @@ def play_vs_random(game: ludax.Game, net: ludax.Net, n: int, net_player: int, se
             ludax.random_step(game, s, seed, id_base, reward=r, terminal=t)
     w = s.winner
     return (int((w == net_player).sum()), int((w == 3 - net_player).sum()), int((w == 0).sum()))
+
+
+def estimate_budgeted(game: ludax.Game, net: ludax.Net, s: ludax.State, budget_bytes: int,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+    """ludax_net_estimate over a batch of any size with the network's
+    workspace held to budget_bytes of HBM: the envs are admitted in chunks
+    of the largest batch whose workspace fits (ludax_net_max_batch)."""
+    chunk = net.max_batch(budget_bytes) // 64 * 64  # whole workgroups; keeps every chunk's boards 16-byte aligned
+    if chunk < 64:
+        raise ValueError("the HBM budget does not hold the workspace of 64 positions")
+    if out is None:
+        out = torch.empty(s.n, dtype=torch.float32, device=s.board.device)
+    for a in range(0, s.n, chunk):
+        b = min(s.n, a + chunk)
+        part = ludax.State.from_tensors(game, **{f: getattr(s, f)[a:b] for f in ludax.State.FIELDS})
+        net.estimate(part, out=out[a:b])
+    return out

@@ -26,6 +26,7 @@ EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_
            "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy", "ludax_mixed_set_slots",
            "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune",
            "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
+           "ludax_net_max_batch",
            "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
            "ludax_net_estimate", "ludax_strerror", "ludax_last_device_error")
 
@@ -88,6 +89,7 @@ def _load():
             L.ludax_net_destroy.argtypes = [vp]
             L.ludax_net_info.argtypes = [vp, P(i64), P(i64)]
             L.ludax_net_workspace_bytes.argtypes = [vp, i64, i32, P(i64)]
+            L.ludax_net_max_batch.argtypes = [vp, i64, i32, P(i64)]
             L.ludax_net_pack.argtypes = [vp, vp, vp, vp]
             L.ludax_net_forward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp, vp]
             L.ludax_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, f32, vp, vp, vp, vp]
@@ -103,7 +105,8 @@ def _load():
                          "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy",
                          "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
                          "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy",
-                         "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_pack",
+                         "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
+                         "ludax_net_pack",
                          "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
                          "ludax_net_estimate"):
                 getattr(L, name).restype = ctypes.c_int
@@ -447,6 +450,13 @@ class Net:
             ws = torch.empty(max(b.value, 256), dtype=torch.uint8, device=self.params.device)
             self._ws[key] = ws
         return ws
+
+    def max_batch(self, budget_bytes: int, training: bool = False) -> int:
+        """The largest batch whose workspace fits the HBM budget."""
+        k = ctypes.c_int64()
+        _check(_load().ludax_net_max_batch(self._h, budget_bytes, int(training), ctypes.byref(k)),
+               "ludax_net_max_batch")
+        return k.value
 
     def forward(self, board, to_move, logits=None, value=None, stream=None):
         n = board.shape[0]

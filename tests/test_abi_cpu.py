@@ -170,3 +170,21 @@ def test_net_argument_checks_need_no_gpu():
     assert L.ludax_net_estimate(h, 16, 256, None, 4, 16, 256, s) == ludax.E_INVALID
     assert L.ludax_net_pack(h, None, 256, s) == ludax.E_INVALID
     assert L.ludax_net_destroy(h) == 0
+
+
+def test_net_max_batch_is_the_largest_fit():
+    L = _lib()
+    h = ctypes.c_void_p()
+    assert L.ludax_net_create(19, 19, ctypes.byref(h)) == 0
+    for training in (0, 1):
+        for budget in (0, 10**5, 10**8, 16 * 2**30, 300 * 2**30):
+            k, b1, b2 = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+            assert L.ludax_net_max_batch(h, budget, training, ctypes.byref(k)) == 0
+            if k.value > 0:
+                assert L.ludax_net_workspace_bytes(h, k.value, training, ctypes.byref(b1)) == 0
+                assert b1.value <= budget
+            if k.value < 2**31 - 1:
+                assert L.ludax_net_workspace_bytes(h, k.value + 1, training, ctypes.byref(b2)) == 0
+                assert b2.value > budget
+    assert L.ludax_net_max_batch(h, -1, 0, ctypes.byref(k)) == ludax.E_INVALID
+    L.ludax_net_destroy(h)

@@ -136,3 +136,15 @@ def test_mixed_autotune_keeps_results():
     w, p, l, st = oracle_batch(MIX4, 5, 0, n)
     assert np.array_equal(out.winner.cpu().numpy(), w)
     assert np.array_equal(out.plies.cpu().numpy(), p)
+
+
+def test_mixed_large_boards_match_oracle():
+    """Hex 19x19 and Gomoku 19x19 in one mixed batch (the large-board
+    configuration at a size the oracle replays quickly)."""
+    kinds = [(ref.HEX, 19, 19), (ref.GOMOKU, 19, 19)]
+    out, stats, _ = run_mixed(kinds, 19, 3, 1200, [128, 192])
+    w, p, l, st = oracle_batch(kinds, 19, 3, 1200)
+    assert np.array_equal(out.winner.cpu().numpy(), w)
+    assert np.array_equal(out.plies.cpu().numpy(), p)
+    assert np.array_equal(out.last_action.cpu().numpy(), l)
+    assert np.array_equal(stats.cpu().numpy(), st)
