@@ -32,11 +32,11 @@ sys.path.insert(0, ROOT)
 # this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt).  Peak:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (the fp64
 # vector rate 78.6 TFLOP/s counts an FMA as two operations).
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 284, "hex11x11_n65536": 181}
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 284, "hex11x11_n65536": 184}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes of one Hex playout launch: FETCH_SIZE and WRITE_SIZE scaled by
 # a 256 MiB copy (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
-HEX_TRAFFIC_BYTES = 17.78e6
+HEX_TRAFFIC_BYTES = 19.95e6
 HBM_PEAK_GBS = 8000.0
 
 
@@ -446,6 +446,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
+    ap.add_argument("--sections", default="mixed,plain_step,large,learned,large_mixed",
+                    help="comma-separated extra sections to run after the headline steps")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed persistent batch section")
     ap.add_argument("--mixed-steps", type=int, default=5)
@@ -564,16 +566,25 @@ def main():
                    "envs_per_batch": batches[0].n, "seed": args.seed, "per_game": per},
         "roofline": roofline,
     }
-    if not args.no_mixed:
+    sec = set(x for x in args.sections.split(",") if x)
+    if args.no_mixed:
+        sec.discard("mixed")
+    if args.no_plain_step:
+        sec.discard("plain_step")
+    if args.no_large:
+        sec -= {"large", "large_mixed"}
+    if args.no_learned:
+        sec -= {"learned", "large_mixed"}
+    if "mixed" in sec:
         out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
-    if not args.no_plain_step:
+    if "plain_step" in sec:
         out["plain_step"] = _plain_step_section(
-            tuple(batches) + (() if args.no_large else W.LARGE_BATCHES), args.seed, args.section_reps)
-    if not args.no_large:
+            tuple(batches) + (W.LARGE_BATCHES if "large" in sec else ()), args.seed, args.section_reps)
+    if "large" in sec:
         out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
-    if not args.no_learned:
+    if "learned" in sec:
         out["learned"] = _learned_section(args.seed, args.train_games, args.train_steps)
-    if not args.no_large and not args.no_learned:
+    if "large_mixed" in sec:
         out["large_mixed"] = _large_mixed_section(args.seed, args.section_reps, args.large_train_steps,
                                                   args.hbm_budget_gb)
     if args.cpu_seconds > 0:
