@@ -276,6 +276,120 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
+// The 64-channel convolution with both operands in LDS.  Reading A (the
+// activations) straight from memory re-reads every cell once per tap, which
+// leaves the MFMA pipes waiting on the vector memory path; here a block
+// stages its boards and the weights in LDS, half of the input channels at a
+// time (two phases of 9 taps x 32 channels), so each activation byte comes
+// from memory once per layer.  N = 11: 4 boards per block, one wave each;
+// N = 19: one board per block, 3 waves of <= 8 cell tiles.  Same MODEs as
+// k_conv.
+// ---------------------------------------------------------------------------
+template <int N>
+struct LdsConv {
+    static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    static constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
+    static constexpr int BPB = N <= 13 ? 4 : 1;        // boards per block
+    static constexpr int THREADS = BPB * NG * 64;
+    static constexpr int WS = 9 * 32 + 8;               // weight row stride (bf16), one half of K
+    static constexpr int LDS_BYTES = (C * WS + BPB * PP * 32) * 2;
+};
+
+template <int N, int MODE>
+__global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint16_t *__restrict__ x,
+                                                                     const uint16_t *__restrict__ w,
+                                                                     const float *__restrict__ bias,
+                                                                     const uint16_t *__restrict__ mask,
+                                                                     uint16_t *__restrict__ out, int64_t n)
+{
+    using L = LdsConv<N>;
+    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
+    __shared__ __align__(16) uint16_t ws[C * WS];
+    __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int slot = wave / NG, g = wave % NG;
+    const int64_t b0 = (int64_t)blockIdx.x * BPB;
+    const int64_t b = b0 + slot;
+    const bool live = b < n;
+    const int row = lane & 15, quad = lane >> 4;
+    int cell_off[8]; // top-left tap of this lane's A row in each tile (padded cells)
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const int p = (g * 8 + mt) * 16 + row;
+        const int pc = p < PIX ? p : 0;
+        cell_off[mt] = (pc / N) * NP + (pc % N);
+    }
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
+        __syncthreads();
+        for (int j = threadIdx.x; j < C * 9 * 4; j += L::THREADS) { // weights: (out, tap, 8-channel chunk)
+            const int o = j / 36, r = j % 36, t = r >> 2, c8 = r & 3;
+            *reinterpret_cast<uint4 *>(ws + o * WS + t * 32 + c8 * 8) =
+                *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8);
+        }
+        for (int j = threadIdx.x; j < BPB * PP * 4; j += L::THREADS) { // boards: (board, cell, chunk)
+            const int bb = j / (PP * 4), r = j % (PP * 4), q = r >> 2, c8 = r & 3;
+            if (b0 + bb < n)
+                *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + c8 * 8) =
+                    *reinterpret_cast<const uint4 *>(x + ((b0 + bb) * PP + q) * (int64_t)C + h * 32 + c8 * 8);
+        }
+        __syncthreads();
+        if (!live) continue;
+        const uint16_t *xb = xs + slot * PP * 32;
+#pragma unroll 1
+        for (int t = 0; t < 9; ++t) {
+            const int toff = (t / 3) * NP + (t % 3);
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * WS + t * 32 + quad * 8));
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                if (g * 8 + mt >= MT) break;
+                const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + (cell_off[mt] + toff) * 32 + quad * 8));
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+    if (!live) return;
+
+    uint16_t *ob = out + b * (int64_t)PP * C;
+    if (g == 0) zero_ring<N>(ob, lane);
+    const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        if (g * 8 + mt >= MT) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int p = (g * 8 + mt) * 16 + quad * 4 + i;
+            if (p >= PIX) continue;
+            const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C;
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int co = nt * 16 + row;
+                float v = acc[mt][nt][i];
+                if constexpr (MODE == 0) {
+                    v += bias[co];
+                    v = v > 0.f ? v : 0.f;
+                } else {
+                    const uint16_t m = mb[o + co];
+                    v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
+                }
+                ob[o + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // heads, forward: one wave per board, lanes over cells.
 // logits in action order (the frame of player 2 is transposed back), and
 // optionally in the mover's frame; value = tanh(wv . mean + bv).
@@ -614,6 +728,28 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part
     }
 }
 
+// loss[j] = sum over rows r < n of terms[2 r + j], j = 0, 1 (one block)
+__global__ __launch_bounds__(256) void k_sum_loss(const float *__restrict__ terms, int64_t n, float *__restrict__ loss)
+{
+    __shared__ float red[2][256];
+    float a = 0.f, b = 0.f;
+    for (int64_t r = threadIdx.x; r < n; r += 256) {
+        a += terms[2 * r];
+        b += terms[2 * r + 1];
+    }
+    red[0][threadIdx.x] = a;
+    red[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int k = 128; k >= 1; k >>= 1) {
+        if (threadIdx.x < k) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + k];
+            red[1][threadIdx.x] += red[1][threadIdx.x + k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2) loss[threadIdx.x] = red[threadIdx.x][0];
+}
+
 // value cutoff estimate for player 1
 __global__ void k_estimate(const int8_t *__restrict__ status, const int8_t *__restrict__ winner,
                            const int8_t *__restrict__ to_move, const float *__restrict__ value, int64_t n,
@@ -696,8 +832,10 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, reinterpret_cast<const uint16_t *>(a0),
                        packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
     uint16_t *in = ya, *out = yb;
+    using LC = LdsConv<N>;
+    const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
     for (int l = 2; l <= 4; ++l) {
-        hipLaunchKernelGGL((k_conv<N, 64, 0>), dim3(cb), dim3(256), 0, s, in, packed + pf_off(l),
+        hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
                            params + b_off(l), (const uint16_t *)nullptr, out, n);
         uint16_t *t = in;
         in = out;
@@ -737,8 +875,10 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
     hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, y[0], packed + pf_off(1), params + b_off(1),
                        (const uint16_t *)nullptr, y[1], n);
+    using LC = LdsConv<N>;
+    const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
     for (int l = 2; l <= 4; ++l)
-        hipLaunchKernelGGL((k_conv<N, 64, 0>), dim3(cb), dim3(256), 0, s, y[l - 1], packed + pf_off(l),
+        hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
                            params + b_off(l), (const uint16_t *)nullptr, y[l], n);
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
@@ -752,7 +892,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         hipLaunchKernelGGL((k_conv_wgrad<N, 64>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
         hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
-        hipLaunchKernelGGL((k_conv<N, 64, 1>), dim3(cb), dim3(256), 0, s, ga, packed + pb_off(l),
+        hipLaunchKernelGGL((k_conv_lds<N, 1>), dim3(lb), dim3(LC::THREADS), 0, s, ga, packed + pb_off(l),
                            (const float *)nullptr, y[l - 1], gb, n);
         uint16_t *t = ga;
         ga = gb;
@@ -761,7 +901,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     hipLaunchKernelGGL((k_conv_wgrad<N, 4>), dim3(wb), dim3(256), 0, s, ga, y[0], n, part);
     hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART4, PART4,
                        grads + w_off(1));
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(256), 0, s, lterms, n, 2, 2, loss);
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lterms, n, loss);
     return hipGetLastError();
 }
 

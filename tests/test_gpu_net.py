@@ -4,10 +4,12 @@ oracle with the same bfloat16 rounding points (oracle/net_ref.py).
 Tolerance: the GPU sums in float32 where the oracle sums in float64, so a
 value that the oracle rounds to bfloat16 can land one bfloat16 step (2^-8
 relative) away on the GPU when it lies within float32 rounding noise of a
-rounding boundary (a fraction of about 1e-4 of the values); everything else
-agrees to float32 accuracy.  Both effects stay far below a relative L2 error
-of 1e-3 over a whole output, which is the bound used here (and 1e-2 of the
-largest magnitude for any single element)."""
+rounding boundary, and the backward pass carries such flips on.  The
+oracle's own arithmetic with float32 sums moves the forward outputs by far
+less than 1e-3 and the parameter gradients by up to 1.05e-3 relative L2
+(tests/test_oracle_net.py measures it); the bounds are 1e-3 for outputs and
+losses and 4e-3 for gradients (relative L2 over a whole output or parameter
+block), and 1e-2 of the largest magnitude for any single element."""
 import numpy as np
 import pytest
 import torch
@@ -86,7 +88,7 @@ def test_loss_and_gradient_match_oracle(kind, N, n):
             o += k
             continue
         try:
-            close(gg[o:o + k], eg[o:o + k])
+            close(gg[o:o + k], eg[o:o + k], rel=4e-3)
         except AssertionError as e:
             raise AssertionError(f"{name}: {e}")
         o += k
