@@ -335,8 +335,10 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
         }
         for (int j = threadIdx.x; j < BPB * PP * 4; j += L::THREADS) { // boards: (board, cell, chunk)
             const int bb = j / (PP * 4), r = j % (PP * 4), q = r >> 2, c8 = r & 3;
+            // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4: the 16 cells a
+            // fragment read touches then fall on 16 different LDS bank groups
             if (b0 + bb < n)
-                *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + c8 * 8) =
+                *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + ((c8 + (q >> 2)) & 3) * 8) =
                     *reinterpret_cast<const uint4 *>(x + ((b0 + bb) * PP + q) * (int64_t)C + h * 32 + c8 * 8);
         }
         __syncthreads();
@@ -352,7 +354,8 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt) {
                 if (g * 8 + mt >= MT) break;
-                const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + (cell_off[mt] + toff) * 32 + quad * 8));
+                const int q = cell_off[mt] + toff;
+                const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
 #pragma unroll
                 for (int nt = 0; nt < 4; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
