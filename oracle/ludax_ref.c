@@ -17,7 +17,8 @@
  *                 Sec. 3.3 (end rules checked in order, wins before draws).
  *   win rules     App. C: lines of 3 / 4 in Tic-Tac-Toe / Connect Four,
  *                 exactly five in Gomoku, Hex edge-to-edge connection,
- *                 Reversi disc count after both players pass.
+ *                 Reversi disc count after both players pass, Yavalath's
+ *                 four in a row wins / three in a row (without four) loses.
  *   playout       Sec. 6 (uniform-random action policy, full games).
  *   Philox        Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
  *                 Easy as 1, 2, 3", SC'11: Philox4x32 with 10 rounds.
@@ -33,6 +34,7 @@
 
 typedef struct {
     int kind, H, W, cells, A, max_plies;
+    int S; /* Yavalath: side of the hexagon */
 } game_t;
 
 typedef struct {
@@ -82,6 +84,7 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
     case LUDAX_REF_HEX:          ok = (H == W && H >= 1 && H <= 19); break;
     case LUDAX_REF_REVERSI:      ok = (H == 8 && W == 8); break;
     case LUDAX_REF_GOMOKU:       ok = (H == W && H >= 5 && H <= 19); break;
+    case LUDAX_REF_YAVALATH:     ok = (H == W && (H & 1) && H >= 3 && H <= 9); break;
     default: return LUDAX_REF_E_UNSUPPORTED;
     }
     if (!ok) return LUDAX_REF_E_UNSUPPORTED;
@@ -89,6 +92,11 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
     g->H = H;
     g->W = W;
     g->cells = H * W;
+    g->S = 0;
+    if (k == LUDAX_REF_YAVALATH) {
+        g->S = (H + 1) / 2;
+        g->cells = 3 * g->S * (g->S - 1) + 1;
+    }
     g->A = g->cells + (k == LUDAX_REF_REVERSI ? 1 : 0);
     g->max_plies = d->max_plies ? d->max_plies : natural_bound(k, g->cells);
     return LUDAX_REF_OK;
@@ -220,6 +228,7 @@ static void legal(const game_t *g, const env_t *e, uint8_t *m)
     case LUDAX_REF_TICTACTOE:
     case LUDAX_REF_HEX:
     case LUDAX_REF_GOMOKU:
+    case LUDAX_REF_YAVALATH:
         for (int i = 0; i < g->cells; i++) m[i] = (e->board[i] == 0);
         break;
     case LUDAX_REF_CONNECT_FOUR:
@@ -322,6 +331,52 @@ static int hex_connected(const game_t *g, const env_t *e, int who)
     return 0;
 }
 
+/* Yavalath geometry: row lengths, the first axial q of a row, and the cell
+ * at axial (r, q) (-1 off the board). */
+static int yav_len(const game_t *g, int r)
+{
+    int d = r - (g->S - 1);
+    return g->H - (d < 0 ? -d : d);
+}
+static int yav_q0(const game_t *g, int r) { return r < g->S - 1 ? g->S - 1 - r : 0; }
+static int yav_cell(const game_t *g, int r, int q)
+{
+    if (r < 0 || r >= g->H) return -1;
+    int i = q - yav_q0(g, r);
+    if (i < 0 || i >= yav_len(g, r)) return -1;
+    int base = 0;
+    for (int k = 0; k < r; k++) base += yav_len(g, k);
+    return base + i;
+}
+
+/* Longest and shortest maximal straight runs of `who`: *longest = the
+ * longest run, *has3 = some maximal run has exactly 3 stones.  Every cell
+ * is visited as a potential run start in each of the three directions. */
+static void yav_runs(const game_t *g, const env_t *e, int who, int *longest, int *has3)
+{
+    static const int DIR3[3][2] = {{0, 1}, {1, 0}, {1, -1}};
+    *longest = 0;
+    *has3 = 0;
+    for (int r = 0; r < g->H; r++)
+        for (int i = 0; i < yav_len(g, r); i++) {
+            int q = i + yav_q0(g, r);
+            if (e->board[yav_cell(g, r, q)] != who) continue;
+            for (int d = 0; d < 3; d++) {
+                int dr = DIR3[d][0], dq = DIR3[d][1];
+                int prev = yav_cell(g, r - dr, q - dq);
+                if (prev >= 0 && e->board[prev] == who) continue; /* not a run start */
+                int L = 0, rr = r, qq = q, c;
+                while ((c = yav_cell(g, rr, qq)) >= 0 && e->board[c] == who) {
+                    L++;
+                    rr += dr;
+                    qq += dq;
+                }
+                if (L > *longest) *longest = L;
+                if (L == 3) *has3 = 1;
+            }
+        }
+}
+
 static int board_full(const game_t *g, const env_t *e)
 {
     for (int i = 0; i < g->cells; i++)
@@ -349,6 +404,15 @@ static int end_rules(const game_t *g, const env_t *e, int me)
     case LUDAX_REF_HEX:
         if (hex_connected(g, e, me)) return me;
         return -1;
+    case LUDAX_REF_YAVALATH: {
+        /* four (or more) in a row wins; else three in a row loses */
+        int longest, has3;
+        yav_runs(g, e, me, &longest, &has3);
+        if (longest >= 4) return me;
+        if (has3) return 3 - me;
+        if (board_full(g, e)) return 0;
+        return -1;
+    }
     case LUDAX_REF_REVERSI:
         if (e->passes >= 2) {
             int n1 = 0, n2 = 0;
@@ -374,6 +438,12 @@ static void check_opponent(const game_t *g, const env_t *e, int me)
     case LUDAX_REF_CONNECT_FOUR: bad = has_line(g, e, opp, 4, 0); break;
     case LUDAX_REF_GOMOKU: bad = has_line(g, e, opp, 5, 1); break;
     case LUDAX_REF_HEX: bad = hex_connected(g, e, opp); break;
+    case LUDAX_REF_YAVALATH: {
+        int longest, has3;
+        yav_runs(g, e, opp, &longest, &has3);
+        bad = longest >= 3;
+        break;
+    }
     default: break;
     }
     if (bad) check_failed();
@@ -390,6 +460,11 @@ int ludax_ref_holds_win(const ludax_ref_desc *d, const int8_t *board, int who)
     case LUDAX_REF_CONNECT_FOUR: return has_line(&g, &e, who, 4, 0);
     case LUDAX_REF_GOMOKU: return has_line(&g, &e, who, 5, 1);
     case LUDAX_REF_HEX: return hex_connected(&g, &e, who);
+    case LUDAX_REF_YAVALATH: {
+        int longest, has3;
+        yav_runs(&g, &e, who, &longest, &has3);
+        return longest >= 4;
+    }
     default: return -1;
     }
 }

@@ -17,6 +17,13 @@
  *   - player 1 moves first; movers alternate strictly; a pass is a ply.
  *   - end rules are evaluated in order, wins before draws (Sec. 3.3).
  *   - random play draws one Philox4x32-10 word per ply (see ludax_ref_playout).
+ *   - Yavalath (App. C) is played on a regular hexagon whose diameter D
+ *     (rows = cols = D, odd) runs left to right: side S = (D + 1) / 2, rows
+ *     r = 0..D-1 from the top, row r holding D - |r - (S-1)| cells, numbered
+ *     row by row, left to right (61 cells for D = 9).  In axial coordinates
+ *     cell i of row r has q = i + max(0, S-1-r); (r, q) touches (r, q+-1),
+ *     (r-1, q), (r-1, q+1), (r+1, q-1), (r+1, q), and straight lines run
+ *     along (0, 1), (1, 0) and (1, -1).
  */
 #ifndef LUDAX_REF_H
 #define LUDAX_REF_H
@@ -33,6 +40,7 @@ extern "C" {
 #define LUDAX_REF_HEX          3
 #define LUDAX_REF_REVERSI      4
 #define LUDAX_REF_GOMOKU       5
+#define LUDAX_REF_YAVALATH     6
 
 /* env status */
 #define LUDAX_REF_RUNNING   0
