@@ -22,11 +22,18 @@
  *                      both players pass in a row, most discs wins
  *   LUDAX_GOMOKU       NxN, 5 <= N <= 19, a line of exactly five wins, full
  *                      board draws
+ *   LUDAX_YAVALATH     DxD, D = 3, 5, 7 or 9: a regular hexagon of diameter D
+ *                      (61 cells for D = 9), four in a row wins, else three
+ *                      in a row loses, full board draws.  Cells are numbered
+ *                      row by row from the top, row r holding
+ *                      D - |r - (D-1)/2| cells, left to right; lines run
+ *                      along the rows and the two other hexagon axes.
  * Anything else is LUDAX_E_UNSUPPORTED.
  *
  * Board and action conventions:
  *   cell (r, c) has index r*cols + c, r = 0 the top row, c = 0 the left
- *   column; a cell holds 0 (empty), 1 (player 1) or 2 (player 2).
+ *   column (Yavalath: the hexagon numbering above); a cell holds 0 (empty),
+ *   1 (player 1) or 2 (player 2).
  *   The action space is the set of cells (Sec. 3.4: its size depends only
  *   on the board and the play mechanic), plus one PASS action at index
  *   rows*cols for Reversi.  Player 1 moves first; movers alternate; a pass
@@ -64,6 +71,7 @@ extern "C" {
 #define LUDAX_HEX          3
 #define LUDAX_REVERSI      4
 #define LUDAX_GOMOKU       5
+#define LUDAX_YAVALATH     6
 
 /* per-environment status values (ludax_state.status) */
 #define LUDAX_RUNNING   0 /* the game goes on */
@@ -82,7 +90,7 @@ typedef struct ludax_game ludax_game; /* opaque, immutable after create */
 /* Static description of a game (Sec. 4: every shape is fixed when the
  * game is built). */
 typedef struct {
-    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_GOMOKU */
+    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_YAVALATH */
     int32_t rows;
     int32_t cols;
     int32_t max_plies; /* 0 = the natural bound: cells (Reversi: 121); at most 32767 */

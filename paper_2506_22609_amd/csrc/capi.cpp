@@ -110,6 +110,7 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out)
     case LUDAX_HEX: ops = lx::ops_hex(desc->rows, desc->cols); break;
     case LUDAX_REVERSI: ops = lx::ops_reversi(desc->rows, desc->cols); break;
     case LUDAX_GOMOKU: ops = lx::ops_gomoku(desc->rows, desc->cols); break;
+    case LUDAX_YAVALATH: ops = lx::ops_yavalath(desc->rows, desc->cols); break;
     default: return LUDAX_E_UNSUPPORTED;
     }
     if (ops == nullptr) return LUDAX_E_UNSUPPORTED;

@@ -8,6 +8,9 @@
 //   Reversi       bit = cell (64 bits); column masks stop wrapping
 //   Hex N         bit = cell (N*N bits); column masks stop wrapping
 //   Gomoku N      row stride N+1 (zero guard column), N*(N+1) bits
+//   Yavalath D    axial (r, q) at bit r*(D+1) + q inside a D x (D+1)
+//                 rhombus; the guard column and the corners outside the
+//                 hexagon stay zero
 // Every internal layout is increasing in the cell index, so "the k-th legal
 // cell in index order" is the k-th set bit of the internal legal mask.
 //
@@ -463,6 +466,104 @@ struct Gomoku {
         p2 = pick(me == 1, p2, own);
         if (five_along<1>(own) | five_along<S>(own) | five_along<S - 1>(own) | five_along<S + 1>(own))
             return me;
+        if (popcount(p1 | p2) == CELLS) return 0;
+        return -1;
+    }
+    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int pass(int &) { return -1; }
+};
+
+// ---------------------------------------------------------------------------
+// Yavalath (App. C) on a regular hexagon of diameter D (odd, side
+// SIDE = (D+1)/2): four or more in a row wins, else three in a row (no
+// four) loses, else a full board draws.  Cells are numbered row by row from
+// the top, row r holding D - |r - (SIDE-1)| cells; cell i of row r has axial
+// q = i + max(0, SIDE-1-r).  Straight lines run along (0, 1), (1, 0) and
+// (1, -1), which in the internal layout are the shifts 1, D + 1 and D.  Only
+// the mover's stones can form a new line, and a mover who already had a line
+// would have ended the game, so full-board tests of the mover's stones are
+// exact: some four -> win, else some three -> every run is at most three
+// long, so any three is an exact three -> loss.
+// ---------------------------------------------------------------------------
+template <int D>
+struct Yavalath {
+    static_assert(D % 2 == 1 && D >= 3, "odd diameter");
+    static constexpr int KIND = 6, H = D, W = D, SIDE = (D + 1) / 2;
+    static constexpr int CELLS = 3 * SIDE * (SIDE - 1) + 1, A = CELLS;
+    static constexpr int S = D + 1, NBITS = D * S;
+    static constexpr int NWC = (CELLS + 31) / 32, NWI = (NBITS + 31) / 32;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<NWI>;
+    M p1, p2;
+
+    __host__ __device__ static constexpr int rlen(int r) { return D - (r > SIDE - 1 ? r - (SIDE - 1) : SIDE - 1 - r); }
+    __host__ __device__ static constexpr int q0(int r) { return r < SIDE - 1 ? SIDE - 1 - r : 0; }
+    // first cell of row r (closed forms: rows grow by one to the middle row, then shrink)
+    __host__ __device__ static constexpr int rstart(int r)
+    {
+        if (r <= SIDE - 1) return r * SIDE + r * (r - 1) / 2;
+        const int mid = (SIDE - 1) * SIDE + (SIDE - 1) * (SIDE - 2) / 2, k = r - SIDE;
+        return mid + D + k * D - k * (k + 1) / 2;
+    }
+    static_assert(rstart(D) == CELLS, "row starts");
+
+    struct Valid {
+        constexpr bool operator()(int b) const
+        {
+            const int r = b / S, q = b % S;
+            return r < D && q >= q0(r) && q < q0(r) + rlen(r);
+        }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c)
+    {
+        M m = bb_zero<NWI>();
+        static_for<D>([&](auto R) {
+            constexpr int r = R;
+            or_field<r * S + q0(r), rlen(r)>(m, get_field<rstart(r), rlen(r)>(c));
+        });
+        return m;
+    }
+    __device__ static BB<NWC> to_canon(const M &m)
+    {
+        BB<NWC> c = bb_zero<NWC>();
+        static_for<D>([&](auto R) {
+            constexpr int r = R;
+            or_field<rstart(r), rlen(r)>(c, get_field<r * S + q0(r), rlen(r)>(m));
+        });
+        return c;
+    }
+    __device__ static int action_of(int b)
+    {
+        const int r = b / S;
+        return rstart(r) + (b % S) - q0(r);
+    }
+    __device__ static int bit_of(int a)
+    {
+        int r = 0;
+#pragma unroll
+        for (int k = 1; k < D; ++k) r += a >= rstart(k) ? 1 : 0;
+        return r * S + q0(r) + (a - rstart(r));
+    }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = from_canon(c1); p2 = from_canon(c2); }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = to_canon(p1); c2 = to_canon(p2); }
+    __device__ void prepare() {}
+
+    __device__ M placements(int) const { return and_mask<Valid, NBITS, NWI>(~(p1 | p2)); }
+
+    template <int K>
+    __device__ static M runs3(const M &x) { return x & shr<K>(x) & shr<2 * K>(x); }
+    template <int K>
+    __device__ static M runs4(const M &x) { const M a = x & shr<K>(x); return a & shr<2 * K>(a); }
+
+    __device__ int place(int b, int me)
+    {
+        M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
+        p1 = pick(me == 1, own, p1);
+        p2 = pick(me == 1, p2, own);
+        if (any(runs4<1>(own) | runs4<S>(own) | runs4<D>(own))) return me;
+        if (any(runs3<1>(own) | runs3<S>(own) | runs3<D>(own))) return 3 - me;
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;
     }

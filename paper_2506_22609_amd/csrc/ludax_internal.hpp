@@ -79,5 +79,6 @@ const GameOps *ops_connect_four(int rows, int cols);
 const GameOps *ops_hex(int rows, int cols);
 const GameOps *ops_reversi(int rows, int cols);
 const GameOps *ops_gomoku(int rows, int cols);
+const GameOps *ops_yavalath(int rows, int cols);
 
 } // namespace lx

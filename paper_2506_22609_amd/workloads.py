@@ -8,7 +8,7 @@ The paper benchmarks its own rule sets under a uniformly random policy
 """
 from dataclasses import dataclass
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU = 1, 2, 3, 4, 5
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH = 1, 2, 3, 4, 5, 6
 
 SEEDS = (1, 2, 3)
 
@@ -32,6 +32,8 @@ REVERSI_65536 = Batch("reversi8x8_n65536", REVERSI, 8, 8, 65536)
 GOMOKU15_65536 = Batch("gomoku15x15_n65536", GOMOKU, 15, 15, 65536)
 
 BENCH_BATCHES = (C4_65536, HEX11_65536)
+# Yavalath on the hexagon of diameter 9 (61 cells)
+YAVALATH9_65536 = Batch("yavalath9_n65536", YAVALATH, 9, 9, 65536)
 
 # large boards: Hex 19x19 and Gomoku 19x19, 524288 envs each (1,048,576
 # envs, 378.5 MB of int8 boards)

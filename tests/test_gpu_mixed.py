@@ -148,3 +148,13 @@ def test_mixed_large_boards_match_oracle():
     assert np.array_equal(out.plies.cpu().numpy(), p)
     assert np.array_equal(out.last_action.cpu().numpy(), l)
     assert np.array_equal(stats.cpu().numpy(), st)
+
+
+def test_mixed_with_yavalath_matches_oracle():
+    kinds = [(ref.YAVALATH, 9, 9), (ref.HEX, 11, 11), (ref.YAVALATH, 7, 7)]
+    out, stats, _ = run_mixed(kinds, 23, 11, 2500, [64, 128, 64])
+    w, p, l, st = oracle_batch(kinds, 23, 11, 2500)
+    assert np.array_equal(out.winner.cpu().numpy(), w)
+    assert np.array_equal(out.plies.cpu().numpy(), p)
+    assert np.array_equal(out.last_action.cpu().numpy(), l)
+    assert np.array_equal(stats.cpu().numpy(), st)

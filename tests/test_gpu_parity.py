@@ -24,8 +24,10 @@ GAMES = [
     (ref.GOMOKU, 15, 15),
     (ref.HEX, 19, 19),
     (ref.GOMOKU, 19, 19),
+    (ref.YAVALATH, 9, 9),
+    (ref.YAVALATH, 5, 5),
 ]
-IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19"]
+IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19", "yavalath9", "yavalath5"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -153,8 +155,9 @@ def test_truncation(g):
     assert np.array_equal(stats, gstats.cpu().numpy())
 
 
-@pytest.mark.parametrize("kind,sizes", [(ref.HEX, range(1, 20)), (ref.GOMOKU, range(5, 20))],
-                         ids=["hex", "gomoku"])
+@pytest.mark.parametrize("kind,sizes", [(ref.HEX, range(1, 20)), (ref.GOMOKU, range(5, 20)),
+                                        (ref.YAVALATH, (3, 5, 7, 9))],
+                         ids=["hex", "gomoku", "yavalath"])
 def test_every_board_size(kind, sizes):
     for N in sizes:
         og, dg = pair(kind, N, N)
@@ -291,7 +294,7 @@ def test_step_blocks_without_running_env(g):
     assert_same_state(s, from_device(d))
 
 
-@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4]], ids=["hex11", "reversi", "gomoku15"])
+@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7]], ids=["hex11", "reversi", "gomoku15", "yavalath9"])
 def test_policy_step_sequences(g):
     """ludax_policy_step ply by ply against the oracle's draw + step, with
     random logits: every action equals the oracle's, except where the
