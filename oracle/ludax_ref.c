@@ -18,7 +18,8 @@
  *   win rules     App. C: lines of 3 / 4 in Tic-Tac-Toe / Connect Four,
  *                 exactly five in Gomoku, Hex edge-to-edge connection,
  *                 Reversi disc count after both players pass, Yavalath's
- *                 four in a row wins / three in a row (without four) loses.
+ *                 four in a row wins / three in a row (without four) loses,
+ *                 Pente's five in a row or ten captured stones.
  *   playout       Sec. 6 (uniform-random action policy, full games).
  *   Philox        Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
  *                 Easy as 1, 2, 3", SC'11: Philox4x32 with 10 rounds.
@@ -67,6 +68,10 @@ static int natural_bound(int kind, int cells)
         /* 60 placements, at most 59 single passes between them, and the
          * final two passes. */
         return (cells - 4) + (cells - 4 - 1) + 2;
+    case LUDAX_REF_PENTE:
+        /* a capture frees two cells; after 16 removed stones somebody has
+         * captured 10 and won, so the board fills by then */
+        return cells + 16;
     default:
         return cells; /* one stone per ply, never removed */
     }
@@ -85,6 +90,7 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
     case LUDAX_REF_REVERSI:      ok = (H == 8 && W == 8); break;
     case LUDAX_REF_GOMOKU:       ok = (H == W && H >= 5 && H <= 19); break;
     case LUDAX_REF_YAVALATH:     ok = (H == W && (H & 1) && H >= 3 && H <= 9); break;
+    case LUDAX_REF_PENTE:        ok = (H == W && (H & 1) && H >= 5 && H <= 19); break;
     default: return LUDAX_REF_E_UNSUPPORTED;
     }
     if (!ok) return LUDAX_REF_E_UNSUPPORTED;
@@ -231,6 +237,16 @@ static void legal(const game_t *g, const env_t *e, uint8_t *m)
     case LUDAX_REF_YAVALATH:
         for (int i = 0; i < g->cells; i++) m[i] = (e->board[i] == 0);
         break;
+    case LUDAX_REF_PENTE: {
+        int empty = 1;
+        for (int i = 0; i < g->cells; i++) empty &= e->board[i] == 0;
+        if (empty) { /* the first move goes to the exact centre */
+            m[(g->H / 2) * g->W + g->W / 2] = 1;
+            break;
+        }
+        for (int i = 0; i < g->cells; i++) m[i] = (e->board[i] == 0);
+        break;
+    }
     case LUDAX_REF_CONNECT_FOUR:
         /* an empty cell resting on the floor (bottom row) or on a piece */
         for (int r = 0; r < g->H; r++)
@@ -413,6 +429,13 @@ static int end_rules(const game_t *g, const env_t *e, int me)
         if (board_full(g, e)) return 0;
         return -1;
     }
+    case LUDAX_REF_PENTE: {
+        /* five or more in a row, or 10 captured stones (5 pairs), wins */
+        int pairs = me == 1 ? (e->passes & 15) : ((e->passes >> 4) & 15);
+        if (has_line(g, e, me, 5, 0) || pairs >= 5) return me;
+        if (board_full(g, e)) return 0;
+        return -1;
+    }
     case LUDAX_REF_REVERSI:
         if (e->passes >= 2) {
             int n1 = 0, n2 = 0;
@@ -444,6 +467,7 @@ static void check_opponent(const game_t *g, const env_t *e, int me)
         bad = longest >= 3;
         break;
     }
+    case LUDAX_REF_PENTE: bad = has_line(g, e, opp, 5, 0); break;
     default: break;
     }
     if (bad) check_failed();
@@ -465,6 +489,7 @@ int ludax_ref_holds_win(const ludax_ref_desc *d, const int8_t *board, int who)
         yav_runs(&g, &e, who, &longest, &has3);
         return longest >= 4;
     }
+    case LUDAX_REF_PENTE: return has_line(&g, &e, who, 5, 0);
     default: return -1;
     }
 }
@@ -502,6 +527,25 @@ static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_
             e->passes = 0;
         }
         e->board[a] = (int8_t)me;
+        if (g->kind == LUDAX_REF_PENTE) {
+            /* custodial capture of exactly two: in each of the 8 directions,
+             * two opponent stones and then one of the mover's */
+            int opp = 3 - me, pairs = 0;
+            for (int d = 0; d < 8; d++) {
+                int dr = DIR8[d][0], dc = DIR8[d][1];
+                int r1 = r + dr, c1 = c + dc, r2 = r + 2 * dr, c2 = c + 2 * dc, r3 = r + 3 * dr, c3 = c + 3 * dc;
+                if (on_board(g, r3, c3) && at(g, e, r1, c1) == opp && at(g, e, r2, c2) == opp &&
+                    at(g, e, r3, c3) == me) {
+                    e->board[r1 * g->W + c1] = 0;
+                    e->board[r2 * g->W + c2] = 0;
+                    pairs++;
+                }
+            }
+            int lo = e->passes & 15, hi = (e->passes >> 4) & 15;
+            if (me == 1) lo += pairs;
+            else hi += pairs;
+            e->passes = (int8_t)(lo | (hi << 4));
+        }
     }
     e->ply += 1;
     e->last_action = a;

@@ -24,6 +24,14 @@
  *     cell i of row r has q = i + max(0, S-1-r); (r, q) touches (r, q+-1),
  *     (r-1, q), (r-1, q+1), (r+1, q-1), (r+1, q), and straight lines run
  *     along (0, 1), (1, 0) and (1, -1).
+ *   - Pente (App. C), N x N with N odd: while the board is empty the only
+ *     legal placement is the centre; a placement that brackets exactly two
+ *     opponent stones between itself and one of the mover's stones on a
+ *     straight line (any of 8 directions) removes them; five or more in a
+ *     row, or 10 captured stones, wins; a full board draws.  The state's
+ *     `passes` byte holds the captured PAIRS: player 1's in the low four
+ *     bits, player 2's in the high four bits.  Natural ply bound: cells + 16
+ *     (at most 16 stones are removed before somebody reaches 10).
  */
 #ifndef LUDAX_REF_H
 #define LUDAX_REF_H
@@ -41,6 +49,7 @@ extern "C" {
 #define LUDAX_REF_REVERSI      4
 #define LUDAX_REF_GOMOKU       5
 #define LUDAX_REF_YAVALATH     6
+#define LUDAX_REF_PENTE        7
 
 /* env status */
 #define LUDAX_REF_RUNNING   0

@@ -21,8 +21,10 @@
 //   load(c1, c2) / store(c1, c2): whole state from / to cell-indexed boards
 //   placements(me): internal mask of legal placements for player `me`
 //   action_of(bit) / bit_of(action)
-//   place(bit, me): apply a legal placement, return the end-rule outcome:
-//                   -1 the game goes on, 0 draw, 1 or 2 the winner
+//   place(bit, me, extra): apply a legal placement, return the end-rule
+//                   outcome: -1 the game goes on, 0 draw, 1 or 2 the winner;
+//                   extra is the state's per-game byte (Reversi: consecutive
+//                   passes, reset by a placement; Pente: captured pairs)
 //   pass(passes): Reversi's forced pass
 #pragma once
 
@@ -111,7 +113,7 @@ struct TicTacToe {
         return w;
     }
 
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         const uint32_t bit = 1u << b;
         uint32_t own = (me == 1 ? p1.w[0] : p2.w[0]) | bit;
@@ -121,7 +123,7 @@ struct TicTacToe {
         if ((p1.w[0] | p2.w[0]) == 0x1FFu) return 0;
         return -1;
     }
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };
 
@@ -176,7 +178,7 @@ struct ConnectFour {
         return any(a & shr<2 * D>(a));
     }
 
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
         p1 = pick(me == 1, own, p1);
@@ -186,7 +188,7 @@ struct ConnectFour {
         if (same(occ, const_mask<Valid, NBITS, NWI>())) return 0;
         return -1;
     }
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };
 
@@ -299,7 +301,7 @@ struct Hex {
     __device__ M placements(int) const { return open_cells(p1, p2); }
 
     // place and test the new stone's group against both sides
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         const M s = onehot<NWI>(b);
         const M own = pick(me == 1, p1, p2) | s;
@@ -309,7 +311,7 @@ struct Hex {
         const bool won = any(first_side(g, me)) && meets_far_side(g, me);
         return won ? me : -1;
     }
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };
 
@@ -391,7 +393,7 @@ struct Reversi {
         return any(step<D>(run) & own) ? run : bb_zero<2>();
     }
 
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         const M s = onehot<2>(b);
         M own = pick(me == 1, p1, p2);
@@ -405,10 +407,11 @@ struct Reversi {
         opp = andnot(opp, f);
         p1 = pick(me == 1, own, opp);
         p2 = pick(me == 1, opp, own);
+        extra = 0; // a placement ends a run of passes
         return -1;
     }
 
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
 
     __device__ int pass(int &passes)
     {
@@ -459,7 +462,7 @@ struct Gomoku {
         return any(e);
     }
 
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
         p1 = pick(me == 1, own, p1);
@@ -469,7 +472,7 @@ struct Gomoku {
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;
     }
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };
 
@@ -557,7 +560,7 @@ struct Yavalath {
     template <int K>
     __device__ static M runs4(const M &x) { const M a = x & shr<K>(x); return a & shr<2 * K>(a); }
 
-    __device__ int place(int b, int me)
+    __device__ int place(int b, int me, int &extra)
     {
         M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
         p1 = pick(me == 1, own, p1);
@@ -567,7 +570,7 @@ struct Yavalath {
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;
     }
-    __device__ int place_step(int b, int me) { return place(b, me); }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };
 

@@ -274,8 +274,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
             if (is_pass) {
                 outcome = g.pass(passes);
             } else {
-                outcome = g.place_step(G::bit_of(a), me);
-                passes = 0;
+                outcome = g.place_step(G::bit_of(a), me, passes);
                 changed = true;
             }
             ply += 1;
@@ -358,8 +357,7 @@ __device__ __forceinline__ bool random_ply(G &g, int &me, int &passes, int &ply,
     } else {
         const int b = select_bit(m, k);
         a = G::action_of(b);
-        outcome = g.place(b, me);
-        passes = 0;
+        outcome = g.place(b, me, passes);
     }
     ply += 1;
     last = a;
