@@ -28,6 +28,15 @@
  *                      row by row from the top, row r holding
  *                      D - |r - (D-1)/2| cells, left to right; lines run
  *                      along the rows and the two other hexagon axes.
+ *   LUDAX_PENTE        NxN, N = 7, 9 or 19: the first stone goes to the exact
+ *                      centre (the only legal placement on an empty board);
+ *                      a placement bracketing exactly two opponent stones
+ *                      against one of the mover's stones on a straight line
+ *                      removes them; five or more in a row, or 10 captured
+ *                      stones, wins; full board draws.  The state's `passes`
+ *                      byte holds the captured pairs (player 1: low four
+ *                      bits, player 2: high four bits); natural ply bound
+ *                      cells + 16.
  * Anything else is LUDAX_E_UNSUPPORTED.
  *
  * Board and action conventions:
@@ -72,6 +81,7 @@ extern "C" {
 #define LUDAX_REVERSI      4
 #define LUDAX_GOMOKU       5
 #define LUDAX_YAVALATH     6
+#define LUDAX_PENTE        7
 
 /* per-environment status values (ludax_state.status) */
 #define LUDAX_RUNNING   0 /* the game goes on */
@@ -90,7 +100,7 @@ typedef struct ludax_game ludax_game; /* opaque, immutable after create */
 /* Static description of a game (Sec. 4: every shape is fixed when the
  * game is built). */
 typedef struct {
-    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_YAVALATH */
+    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_PENTE */
     int32_t rows;
     int32_t cols;
     int32_t max_plies; /* 0 = the natural bound: cells (Reversi: 121); at most 32767 */
@@ -107,7 +117,8 @@ typedef struct {
     int8_t  *to_move;     /* [n] player to move, 1 or 2 */
     int8_t  *status;      /* [n] LUDAX_RUNNING ... LUDAX_ILLEGAL */
     int8_t  *winner;      /* [n] -1 none, 0 draw, 1, 2 */
-    int8_t  *passes;      /* [n] consecutive passes (Reversi; 0 otherwise) */
+    int8_t  *passes;      /* [n] the game's extra state byte: Reversi's consecutive passes,
+                             Pente's captured pairs (see above), 0 otherwise */
     int16_t *ply;         /* [n] plies applied since the start */
     int16_t *last_action; /* [n] last applied action, -1 before the first */
     void    *aux;         /* reserved; may be NULL (no game needs it: aux_bytes = 0) */

@@ -90,6 +90,9 @@ int natural_bound(int kind, int cells)
 {
     // Reversi: 60 placements, at most 59 single passes between them, and
     // the two final passes.  Other games: one stone per ply, never removed.
+    // Pente: a capture frees two cells, and after 16 removed stones somebody
+    // has captured 10 and won, so the board is full by cells + 16 plies.
+    if (kind == LUDAX_PENTE) return cells + 16;
     return kind == LUDAX_REVERSI ? (cells - 4) + (cells - 5) + 2 : cells;
 }
 
@@ -111,6 +114,7 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out)
     case LUDAX_REVERSI: ops = lx::ops_reversi(desc->rows, desc->cols); break;
     case LUDAX_GOMOKU: ops = lx::ops_gomoku(desc->rows, desc->cols); break;
     case LUDAX_YAVALATH: ops = lx::ops_yavalath(desc->rows, desc->cols); break;
+    case LUDAX_PENTE: ops = lx::ops_pente(desc->rows, desc->cols); break;
     default: return LUDAX_E_UNSUPPORTED;
     }
     if (ops == nullptr) return LUDAX_E_UNSUPPORTED;

@@ -8,6 +8,7 @@
 //   Reversi       bit = cell (64 bits); column masks stop wrapping
 //   Hex N         bit = cell (N*N bits); column masks stop wrapping
 //   Gomoku N      row stride N+1 (zero guard column), N*(N+1) bits
+//   Pente N       row stride N+1 (zero guard column), N*(N+1) bits
 //   Yavalath D    axial (r, q) at bit r*(D+1) + q inside a D x (D+1)
 //                 rhombus; the guard column and the corners outside the
 //                 hexagon stay zero
@@ -567,6 +568,97 @@ struct Yavalath {
         p2 = pick(me == 1, p2, own);
         if (any(runs4<1>(own) | runs4<S>(own) | runs4<D>(own))) return me;
         if (any(runs3<1>(own) | runs3<S>(own) | runs3<D>(own))) return 3 - me;
+        if (popcount(p1 | p2) == CELLS) return 0;
+        return -1;
+    }
+    __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
+    __device__ int pass(int &) { return -1; }
+};
+
+// ---------------------------------------------------------------------------
+// Pente (App. C) on N x N, N odd: while the board is empty the only legal
+// placement is the centre; a placement that brackets exactly two opponent
+// stones between itself and one of the mover's stones on a straight line
+// removes them (any of the 8 directions, several at once); five or more in
+// a row, or 5 captured pairs (10 stones), wins; a full board draws.  The
+// state's per-game byte holds the captured pairs (player 1 in the low four
+// bits, player 2 in the high four bits).  Layout as Gomoku (row stride
+// N + 1): walking from the new stone, the zero guard column ends every
+// horizontal or diagonal chain before it can wrap to the next row, so the
+// bracket test needs no bounds test.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Pente {
+    static_assert(N % 2 == 1, "odd side: the centre is a cell");
+    static constexpr int KIND = 7, H = N, W = N, CELLS = N * N, A = N * N;
+    static constexpr int S = N + 1, NBITS = N * S;
+    static constexpr int NWC = (CELLS + 31) / 32, NWI = (NBITS + 31) / 32;
+    static constexpr int CENTRE = (N / 2) * S + N / 2;
+    static constexpr bool HAS_PASS = false;
+    using M = BB<NWI>;
+    M p1, p2;
+
+    struct Valid {
+        constexpr bool operator()(int b) const { return (b % S) < N; }
+    };
+
+    __device__ static M from_canon(const BB<NWC> &c) { return restride<N, N, N, S, NWC, NWI>(c); }
+    __device__ static BB<NWC> to_canon(const M &m) { return restride<N, N, S, N, NWI, NWC>(m); }
+    __device__ static int action_of(int b) { return (b / S) * N + (b % S); }
+    __device__ static int bit_of(int a) { return (a / N) * S + (a % N); }
+
+    __device__ void load(const BB<NWC> &c1, const BB<NWC> &c2) { p1 = from_canon(c1); p2 = from_canon(c2); }
+    __device__ void store(BB<NWC> &c1, BB<NWC> &c2) const { c1 = to_canon(p1); c2 = to_canon(p2); }
+    __device__ void prepare() {}
+
+    __device__ M placements(int) const
+    {
+        const M occ = p1 | p2;
+        return pick(any(occ), and_mask<Valid, NBITS, NWI>(~occ), onehot<NWI>(CENTRE));
+    }
+
+    // the new stone s brackets two opponent stones along step D
+    template <int D>
+    __device__ static bool brackets(const M &s, const M &own, const M &opp, M &cap)
+    {
+        const M a = shift<D>(s) & opp, b = shift<2 * D>(s) & opp;
+        const bool hit = any(a) & any(b) & any(shift<3 * D>(s) & own);
+        cap = pick(hit, cap | a | b, cap);
+        return hit;
+    }
+    // starts of runs of five or more along step K
+    template <int K>
+    __device__ static M runs5(const M &x)
+    {
+        const M a = x & shr<K>(x);    // i, i+K
+        const M b = a & shr<2 * K>(a); // i .. i+3K
+        return b & shr<4 * K>(x);      // i .. i+4K
+    }
+
+    __device__ int place(int b, int me, int &extra)
+    {
+        const M s = onehot<NWI>(b);
+        const M own = pick(me == 1, p1, p2) | s;
+        M opp = pick(me == 1, p2, p1);
+        M cap = bb_zero<NWI>();
+        int pairs = 0;
+        pairs += brackets<1>(s, own, opp, cap);
+        pairs += brackets<-1>(s, own, opp, cap);
+        pairs += brackets<S>(s, own, opp, cap);
+        pairs += brackets<-S>(s, own, opp, cap);
+        pairs += brackets<S + 1>(s, own, opp, cap);
+        pairs += brackets<-(S + 1)>(s, own, opp, cap);
+        pairs += brackets<S - 1>(s, own, opp, cap);
+        pairs += brackets<-(S - 1)>(s, own, opp, cap);
+        opp = andnot(opp, cap);
+        p1 = pick(me == 1, own, opp);
+        p2 = pick(me == 1, opp, own);
+        int lo = extra & 15, hi = (extra >> 4) & 15;
+        lo += me == 1 ? pairs : 0;
+        hi += me == 1 ? 0 : pairs;
+        extra = lo | (hi << 4);
+        const int mine = me == 1 ? lo : hi;
+        if (any(runs5<1>(own) | runs5<S>(own) | runs5<S - 1>(own) | runs5<S + 1>(own)) || mine >= 5) return me;
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;
     }

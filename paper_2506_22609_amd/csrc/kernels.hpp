@@ -175,7 +175,8 @@ __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t 
 // state stays in HBM between launches, so this kernel is bound by its bytes:
 // the block's statuses are read first and a block with no RUNNING env reads
 // no board; only envs that were RUNNING write their scalars back, and a
-// placement writes the one cell it changed (Reversi: the whole 64-cell board).
+// placement writes the one cell it changed (Reversi and Pente: the whole
+// board, since flips and captures change other cells).
 // ---------------------------------------------------------------------------
 template <class G, int MODE>
 __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_plies,
@@ -306,8 +307,9 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
         reward[2 * e + 1] = (int8_t)r2;
         terminal[e] = status != RUNNING ? 1 : 0;
     }
-    if constexpr (G::KIND == 4) {
-        // flips can touch any cell: write whole boards (64 B per env) back
+    if constexpr (G::KIND == 4 || G::KIND == 7) {
+        // Reversi's flips and Pente's captures can touch any cell: write
+        // whole boards back
         __syncthreads();
         if (valid) {
             BB<G::NWC> c1, c2;

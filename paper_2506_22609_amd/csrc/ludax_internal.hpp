@@ -80,5 +80,6 @@ const GameOps *ops_hex(int rows, int cols);
 const GameOps *ops_reversi(int rows, int cols);
 const GameOps *ops_gomoku(int rows, int cols);
 const GameOps *ops_yavalath(int rows, int cols);
+const GameOps *ops_pente(int rows, int cols);
 
 } // namespace lx

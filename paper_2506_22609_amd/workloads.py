@@ -8,7 +8,7 @@ The paper benchmarks its own rule sets under a uniformly random policy
 """
 from dataclasses import dataclass
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH = 1, 2, 3, 4, 5, 6
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE = 1, 2, 3, 4, 5, 6, 7
 
 SEEDS = (1, 2, 3)
 

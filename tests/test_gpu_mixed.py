@@ -158,3 +158,13 @@ def test_mixed_with_yavalath_matches_oracle():
     assert np.array_equal(out.plies.cpu().numpy(), p)
     assert np.array_equal(out.last_action.cpu().numpy(), l)
     assert np.array_equal(stats.cpu().numpy(), st)
+
+
+def test_mixed_with_pente_matches_oracle():
+    kinds = [(ref.PENTE, 19, 19), (ref.GOMOKU, 19, 19), (ref.PENTE, 7, 7)]
+    out, stats, _ = run_mixed(kinds, 29, 5, 1500, [128, 64, 64])
+    w, p, l, st = oracle_batch(kinds, 29, 5, 1500)
+    assert np.array_equal(out.winner.cpu().numpy(), w)
+    assert np.array_equal(out.plies.cpu().numpy(), p)
+    assert np.array_equal(out.last_action.cpu().numpy(), l)
+    assert np.array_equal(stats.cpu().numpy(), st)

@@ -26,8 +26,11 @@ GAMES = [
     (ref.GOMOKU, 19, 19),
     (ref.YAVALATH, 9, 9),
     (ref.YAVALATH, 5, 5),
+    (ref.PENTE, 19, 19),
+    (ref.PENTE, 7, 7),
 ]
-IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19", "yavalath9", "yavalath5"]
+IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19", "yavalath9", "yavalath5", "pente19",
+       "pente7"]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -156,8 +159,8 @@ def test_truncation(g):
 
 
 @pytest.mark.parametrize("kind,sizes", [(ref.HEX, range(1, 20)), (ref.GOMOKU, range(5, 20)),
-                                        (ref.YAVALATH, (3, 5, 7, 9))],
-                         ids=["hex", "gomoku", "yavalath"])
+                                        (ref.YAVALATH, (3, 5, 7, 9)), (ref.PENTE, (7, 9, 19))],
+                         ids=["hex", "gomoku", "yavalath", "pente"])
 def test_every_board_size(kind, sizes):
     for N in sizes:
         og, dg = pair(kind, N, N)
@@ -294,7 +297,8 @@ def test_step_blocks_without_running_env(g):
     assert_same_state(s, from_device(d))
 
 
-@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7]], ids=["hex11", "reversi", "gomoku15", "yavalath9"])
+@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7], GAMES[9]],
+                         ids=["hex11", "reversi", "gomoku15", "yavalath9", "pente19"])
 def test_policy_step_sequences(g):
     """ludax_policy_step ply by ply against the oracle's draw + step, with
     random logits: every action equals the oracle's, except where the
