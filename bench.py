@@ -334,6 +334,39 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
     return res
 
 
+def _more_games_section(seed: int, reps: int):
+    """Plain fused playouts of the other placement games, 65536 envs each:
+    Yavalath on the diameter-9 hexagon, Pente 19x19."""
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    out = {}
+    for b in W.MORE_GAMES:
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        s = ludax.State(g, b.n)
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ludax.init(g, s)
+        ludax.playout(g, s, seed, 0, stats=None)
+        torch.cuda.synchronize()
+        ev = []
+        for k in range(reps):
+            ludax.init(g, s)
+            ludax.state_stats(g, s, -1, st)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ludax.playout(g, s, seed, (k + 1) * b.n, stats=None)
+            e1.record()
+            ev.append((e0, e1))
+            ludax.state_stats(g, s, +1, st)
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(c) for a, c in ev) / reps
+        v = st.cpu().tolist()
+        out[b.name] = {"playout_kernel_ms": ms, "env_steps_per_s": v[0] / reps / (ms / 1e3),
+                       "mean_plies": v[0] / reps / b.n, "p1_wins": v[1], "p2_wins": v[2], "draws": v[3]}
+    return out
+
+
 def _learned_section(seed: int, train_games: int, steps: int):
     """The learned policy/value network on Hex 11x11: samples from random
     playouts, training by the library's own forward/backward/Adam kernels,
@@ -446,7 +479,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
-    ap.add_argument("--sections", default="mixed,plain_step,large,learned,large_mixed",
+    ap.add_argument("--sections", default="mixed,plain_step,large,more_games,learned,large_mixed",
                     help="comma-separated extra sections to run after the headline steps")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed persistent batch section")
@@ -582,6 +615,8 @@ def main():
             tuple(batches) + (W.LARGE_BATCHES if "large" in sec else ()), args.seed, args.section_reps)
     if "large" in sec:
         out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
+    if "more_games" in sec:
+        out["more_games"] = _more_games_section(args.seed, args.section_reps)
     if "learned" in sec:
         out["learned"] = _learned_section(args.seed, args.train_games, args.train_steps)
     if "large_mixed" in sec:

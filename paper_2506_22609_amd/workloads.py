@@ -32,8 +32,11 @@ REVERSI_65536 = Batch("reversi8x8_n65536", REVERSI, 8, 8, 65536)
 GOMOKU15_65536 = Batch("gomoku15x15_n65536", GOMOKU, 15, 15, 65536)
 
 BENCH_BATCHES = (C4_65536, HEX11_65536)
-# Yavalath on the hexagon of diameter 9 (61 cells)
+# the other placement games of the paper's benchmark list: Yavalath on the
+# hexagon of diameter 9 (61 cells), Pente 19x19
 YAVALATH9_65536 = Batch("yavalath9_n65536", YAVALATH, 9, 9, 65536)
+PENTE19_65536 = Batch("pente19x19_n65536", PENTE, 19, 19, 65536)
+MORE_GAMES = (YAVALATH9_65536, PENTE19_65536)
 
 # large boards: Hex 19x19 and Gomoku 19x19, 524288 envs each (1,048,576
 # envs, 378.5 MB of int8 boards)
