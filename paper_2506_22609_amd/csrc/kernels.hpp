@@ -55,19 +55,35 @@ __device__ __forceinline__ void stage_out(int8_t *__restrict__ dst, int bytes, c
 }
 
 // One lane's board bytes (LDS) -> cell-indexed bitboards of both players.
+// The lane's row starts at any byte offset, so it is read as the aligned
+// dwords that cover it (one more than its length, hence the 16 bytes of
+// slack behind every staging array) and each 4-cell group is realigned with
+// v_alignbyte; a dot product of the group's low (high) bits with the byte
+// weights 1, 2, 4, 8 packs the four cells of player 1 (player 2) into one
+// nibble.
+constexpr int STAGE_SLACK = 16;
+
 template <int CELLS, int NWC>
 __device__ __forceinline__ void read_board(const int8_t *p, BB<NWC> &c1, BB<NWC> &c2)
 {
+    constexpr int G4 = (CELLS + 3) / 4;                                    // 4-cell groups
+    constexpr uint32_t LAST = CELLS % 4 == 0 ? 0xFFFFFFFFu : (1u << (8 * (CELLS % 4))) - 1u;
+    const uint32_t off = (uint32_t)(uintptr_t)p & 3u;
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p - off);
+    uint32_t lo = q[0];
     static_for<NWC>([&](auto I) {
         constexpr int i = I;
         uint32_t a = 0u, b = 0u;
 #pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const int c = 32 * i + j;
-            if (c < CELLS) {
-                const uint32_t v = (uint8_t)p[c];
-                a |= (v & 1u) << j;
-                b |= ((v >> 1) & 1u) << j;
+        for (int j = 0; j < 8; ++j) {
+            const int k = 8 * i + j;
+            if (k < G4) {
+                const uint32_t hi = q[k + 1];
+                uint32_t v = __builtin_amdgcn_alignbyte(hi, lo, off);
+                if (k == G4 - 1) v &= LAST;
+                lo = hi;
+                a |= __builtin_amdgcn_udot4(v & 0x01010101u, 0x08040201u, 0u, false) << (4 * j);
+                b |= (__builtin_amdgcn_udot4(v & 0x02020202u, 0x08040201u, 0u, false) >> 1) << (4 * j);
             }
         }
         c1.w[i] = a;
@@ -144,7 +160,7 @@ template <class G>
 __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t *__restrict__ mask)
 {
     constexpr int LB = (G::CELLS > G::A ? G::CELLS : G::A);
-    __shared__ __align__(16) int8_t lds[BLOCK * LB];
+    __shared__ __align__(16) int8_t lds[BLOCK * LB + STAGE_SLACK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     stage_in<G::CELLS>(st.board, e0, nb, lds);
@@ -189,7 +205,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
                                                 uint8_t *__restrict__ next_mask)
 {
     constexpr int LB = (G::CELLS > G::A ? G::CELLS : G::A);
-    __shared__ __align__(16) int8_t lds[BLOCK * LB];
+    __shared__ __align__(16) int8_t lds[BLOCK * LB + STAGE_SLACK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     const int t = threadIdx.x;
@@ -387,7 +403,7 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
                                                    int8_t *__restrict__ reward,
                                                    uint8_t *__restrict__ terminal)
 {
-    __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS];
+    __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS + STAGE_SLACK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     stage_in<G::CELLS>(st.board, e0, nb, lds);
@@ -679,7 +695,7 @@ __global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, 
     using E = MoveT<G>;
     constexpr int STAGE = BLOCK * G::CELLS;
     constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(E);
-    __shared__ __align__(16) int8_t lds[STAGE > LIST ? STAGE : LIST];
+    __shared__ __align__(16) int8_t lds[(STAGE > LIST ? STAGE : LIST) + STAGE_SLACK];
     E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: internal bit of window ply j
 
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
