@@ -290,7 +290,9 @@ struct LdsConv {
     static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
     static constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
     static constexpr int BPB = N <= 13 ? 4 : 1;        // boards per block
-    static constexpr int THREADS = BPB * NG * 64;
+    static constexpr int NSPLIT = 2;                    // waves sharing a board's 64 output channels
+    static constexpr int NTW = 4 / NSPLIT;              // output-channel tiles per wave
+    static constexpr int THREADS = BPB * NG * NSPLIT * 64;
     static constexpr int WS = 9 * 32 + 8;               // weight row stride (bf16), one half of K
     static constexpr int LDS_BYTES = (C * WS + BPB * PP * 32) * 2;
 };
@@ -304,10 +306,11 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 {
     using L = LdsConv<N>;
     constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
+    constexpr int NTW = L::NTW;
     __shared__ __align__(16) uint16_t ws[C * WS];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
     const int64_t b0 = (int64_t)blockIdx.x * BPB;
     const int64_t b = b0 + slot;
@@ -320,11 +323,11 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
         const int pc = p < PIX ? p : 0;
         cell_off[mt] = (pc / N) * NP + (pc % N);
     }
-    f32x4 acc[8][4];
+    f32x4 acc[8][NTW];
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
         __syncthreads();
@@ -347,17 +350,17 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int toff = (t / 3) * NP + (t % 3);
-            bf16x8 bfr[4];
+            bf16x8 bfr[NTW];
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt)
-                bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * WS + t * 32 + quad * 8));
+            for (int nt = 0; nt < NTW; ++nt)
+                bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + ((half * NTW + nt) * 16 + row) * WS + t * 32 + quad * 8));
 #pragma unroll
             for (int mt = 0; mt < 8; ++mt) {
                 if (g * 8 + mt >= MT) break;
                 const int q = cell_off[mt] + toff;
                 const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+                for (int nt = 0; nt < NTW; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
             }
         }
@@ -365,7 +368,7 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
     if (!live) return;
 
     uint16_t *ob = out + b * (int64_t)PP * C;
-    if (g == 0) zero_ring<N>(ob, lane);
+    if (g == 0 && half == 0) zero_ring<N>(ob, lane);
     const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
@@ -376,8 +379,8 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
             if (p >= PIX) continue;
             const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C;
 #pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int co = nt * 16 + row;
+            for (int nt = 0; nt < NTW; ++nt) {
+                const int co = (half * NTW + nt) * 16 + row;
                 float v = acc[mt][nt][i];
                 if constexpr (MODE == 0) {
                     v += bias[co];
