@@ -289,7 +289,7 @@ template <int N>
 struct LdsConv {
     static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
     static constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
-    static constexpr int BPB = N <= 13 ? 4 : 1;        // boards per block
+    static constexpr int BPB = N <= 13 ? 4 : 2;        // boards per block
     static constexpr int NSPLIT = 2;                    // waves sharing a board's 64 output channels
     static constexpr int NTW = 4 / NSPLIT;              // output-channel tiles per wave
     static constexpr int THREADS = BPB * NG * NSPLIT * 64;
