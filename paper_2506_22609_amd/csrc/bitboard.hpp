@@ -227,10 +227,12 @@ __device__ __forceinline__ BB<NW> onehot(int b)
 template <int NW>
 __device__ __forceinline__ uint32_t test_bit(const BB<NW> &x, int b)
 {
+    // OR of masked words: a select chain here is turned into a private-memory
+    // table lookup by the compiler
     const int q = b >> 5;
-    uint32_t w = x.w[0];
+    uint32_t w = 0u;
 #pragma unroll
-    for (int i = 1; i < NW; ++i) w = (q == i) ? x.w[i] : w;
+    for (int i = 0; i < NW; ++i) w |= x.w[i] & (0u - (uint32_t)(q == i));
     return (w >> (b & 31)) & 1u;
 }
 
