@@ -20,6 +20,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -322,7 +323,11 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
                 torch.cuda.synchronize()
                 timings[name] = time.perf_counter() - t0
             timings[name + "_mse"] = ((est[:sub] - tr) ** 2).mean().item()
+        k = max(1, math.ceil(timings["plain_full_playout_mse"] / timings["value_budgeted_mse"]))
         res["guided"][b.name] = {
+            "fixed_value_error": {"mse": timings["value_budgeted_mse"], "plain_playouts_averaged": k,
+                                  "plain_positions_per_s": n / timings["plain_full_playout"] / k,
+                                  "guided_positions_per_s": n / timings["value_budgeted"]},
             "positions": n, "train_samples": n_train, "train_steps": train_steps, "train_s": t_train,
             "hbm_budget_bytes": budget, "admitted_chunk": net.max_batch(budget),
             "plain_full_playout": {"playouts_per_s": n / timings["plain_full_playout"],
@@ -449,6 +454,14 @@ def _learned_section(seed: int, train_games: int, steps: int):
         mse = ((est[:sub] - tr) ** 2).mean().item()
         out["methods"][name] = {"playouts_per_s": n / el, "ms_per_65536": el * 1e3 * 65536 / n,
                                 "mse_vs_256_playout_mean": mse}
+    # at a fixed value error: how many full random playouts one position
+    # needs, averaged, to match the value's squared error (one playout's
+    # error is the outcome variance, an average of k divides it by k)
+    pm, vm = out["methods"]["plain_full_playout"], out["methods"]["value_only"]
+    k = max(1, math.ceil(pm["mse_vs_256_playout_mean"] / vm["mse_vs_256_playout_mean"]))
+    out["fixed_value_error"] = {"mse": vm["mse_vs_256_playout_mean"], "plain_playouts_averaged": k,
+                                "plain_positions_per_s": pm["playouts_per_s"] / k,
+                                "guided_positions_per_s": vm["playouts_per_s"]}
     # the value forward alone, as a fraction of the bf16 MFMA peak
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -72,3 +72,84 @@ def test_65536_sampled(b):
     assert gstats[1] + gstats[2] + gstats[3] == b.n
     if b.kind == ref.HEX:
         assert gstats[3] == 0
+
+
+def _sampled_check(b, g, grew, gstats, seed, base, samples=1024):
+    """Replay a sample of the batch's games one by one on the oracle (by
+    game id), and check whole-batch counter invariants."""
+    og, _ = pair(b.kind, b.rows, b.cols)
+    rng = np.random.default_rng(b.kind * 31 + b.rows)
+    idx = np.sort(rng.choice(b.n, size=samples, replace=False))
+    idx[0], idx[-1] = 0, b.n - 1
+    s = ref.init(og, len(idx))
+    rew, _, _ = ref.playout(og, s, seed, 0, game_id=base + idx, threads=16)
+    assert_same_state(s, g.subset(idx))
+    assert np.array_equal(rew, grew[idx])
+    assert (g.status == ref.TERMINAL).all()
+    assert gstats[0] == g.ply.astype(np.int64).sum()
+    assert gstats[1] + gstats[2] + gstats[3] == b.n
+
+
+@pytest.mark.parametrize("b", list(W.LARGE_BATCHES) + list(W.MORE_GAMES), ids=lambda b: b.name)
+def test_large_and_more_games_sampled(b):
+    """The 19x19 batches of 524288 envs and the Yavalath / Pente batches."""
+    seed, base = 3, W.game_id_base(2, b)
+    g, grew, gstats = _gpu_batch(b, seed, base)
+    _sampled_check(b, g, grew, gstats, seed, base)
+
+
+def test_per_ply_loop_at_full_size_sampled():
+    """ludax_random_step launched max_plies times over the Hex 19x19 batch of
+    524288 envs (the benchmark's per-ply loop) ends every game exactly where
+    the oracle's playout of the same game id ends."""
+    b = W.HEX19_524288
+    _, dg = pair(b.kind, b.rows, b.cols)
+    d = ludax.State(dg, b.n)
+    ludax.init(dg, d)
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ludax.state_stats(dg, d, -1, st)
+    r = torch.empty((b.n, 2), dtype=torch.int8, device="cuda")
+    t = torch.empty(b.n, dtype=torch.uint8, device="cuda")
+    for _ in range(dg.max_plies):
+        ludax.random_step(dg, d, 4, 7 * b.n, reward=r, terminal=t)
+    ludax.state_stats(dg, d, +1, st)
+    g = from_device(d)
+    og, _ = pair(b.kind, b.rows, b.cols)
+    rng = np.random.default_rng(17)
+    idx = np.sort(rng.choice(b.n, size=512, replace=False))
+    s = ref.init(og, len(idx))
+    ref.playout(og, s, 4, 0, game_id=7 * b.n + idx, threads=16)
+    assert_same_state(s, g.subset(idx))
+    assert (g.status == ref.TERMINAL).all()
+    assert st.cpu().numpy()[0] == g.ply.astype(np.int64).sum()
+
+
+@pytest.mark.parametrize("mb_name", ["MIXED4", "LARGE_MIXED"])
+def test_mixed_full_size_sampled(mb_name):
+    """The mixed persistent batches at their benchmark sizes: 4 x 262144
+    game ids through 262144 slots, and 1048576 Hex / Gomoku 19x19 ids."""
+    if mb_name == "MIXED4":
+        kinds = [(b.kind, b.rows, b.cols) for b in W.MIXED4.kinds]
+        n_games, total = W.MIXED4.n_games, W.MIXED4.slots
+    else:
+        kinds = [(b.kind, b.rows, b.cols) for b in W.LARGE_BATCHES]
+        n_games, total = sum(b.n for b in W.LARGE_BATCHES), 262144
+    games = [ludax.Game(k, r, c) for k, r, c in kinds]
+    m = ludax.Mixed(games)
+    m.slots = [total // len(games) // 64 * 64] * len(games)
+    seed, base = 6, 12345
+    out, stats = m.playout(seed, base, n_games)
+    torch.cuda.synchronize()
+    w, p, l = (x.cpu().numpy() for x in (out.winner, out.plies, out.last_action))
+    rng = np.random.default_rng(n_games)
+    js = np.sort(rng.choice(n_games, size=1200, replace=False))
+    for k, (kind, r, c) in enumerate(kinds):
+        sel = js[(base + js) % len(kinds) == k]
+        og = ref.Game(kind, r, c)
+        s = ref.init(og, len(sel))
+        ref.playout(og, s, seed, 0, game_id=base + sel, threads=16)
+        assert np.array_equal(w[sel], np.where(s.status == ref.TERMINAL, s.winner, -1))
+        assert np.array_equal(p[sel], s.ply) and np.array_equal(l[sel], s.last_action)
+    st = stats.cpu().numpy()
+    assert st[:, 0].sum() == p.astype(np.int64).sum()
+    assert st[:, 1:].sum() == n_games
