@@ -1,4 +1,4 @@
-// games.hpp -- the five rule sets as env-per-lane bitboard state machines.
+// games.hpp -- the rule sets as env-per-lane bitboard state machines.
 //
 // Every game keeps the two players' stones as bitboards in registers, in an
 // internal bit layout chosen so that line and neighbour tests are shifts:
@@ -203,7 +203,7 @@ struct ConnectFour {
 // The single-step kernel floods the new stone's group (6-neighbour
 // dilation by shifts, repeated until it stops growing) and checks both
 // sides.  The playout kernel does not test connection ply by ply at all:
-// see k_playout_hex in kernels.hpp.
+// see k_playout_fill in kernels.hpp.
 // ---------------------------------------------------------------------------
 template <int N>
 struct Hex {

@@ -10,12 +10,15 @@
 //
 //   k_init     start positions, 16-byte stores
 //   k_mask     legal mask [n][A], staged through LDS for coalesced stores
-//   k_step     one ply per env for a caller-chosen action (or the uniform
-//              random one); board delta written in place, optional next mask
+//   k_step     one ply per env for a caller-chosen action, the uniform
+//              random one, or one drawn from given logits; board delta
+//              written in place, optional next mask
 //   k_playout  the whole uniform-random game in registers: mask -> Philox
 //              -> k-th legal action -> apply -> end rules, until every lane
 //              of the wave has ended; final board written back through LDS
-//   k_playout_hex  the same result for Hex by fill-then-resolve
+//   k_playout_fill  the same result for Hex, Tic-Tac-Toe and Connect Four by
+//              fill-then-resolve (random fill, then a binary search of the end)
+//   k_persist_ply / k_persist_fill  the mixed persistent batch
 //   k_stats    step and outcome counters (a difference of two reductions)
 #pragma once
 

@@ -294,7 +294,6 @@ struct LdsConv {
     static constexpr int NTW = 4 / NSPLIT;              // output-channel tiles per wave
     static constexpr int THREADS = BPB * NG * NSPLIT * 64;
     static constexpr int WS = 9 * 32 + 8;               // weight row stride (bf16), one half of K
-    static constexpr int LDS_BYTES = (C * WS + BPB * PP * 32) * 2;
 };
 
 template <int N, int MODE>
