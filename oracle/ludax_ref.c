@@ -20,6 +20,11 @@
  *                 Reversi disc count after both players pass, Yavalath's
  *                 four in a row wins / three in a row (without four) loses,
  *                 Pente's five in a row or ten captured stones.
+ *   movement      Sec. 3.2 (move mechanic: step, hop; hop priority over
+ *                 step; capture, promotion and extra-turn effects), the App. B
+ *                 English Draughts listing (start cells, effect order, end
+ *                 rule) and the App. C rule texts of Wolf and Sheep and
+ *                 English Draughts.
  *   playout       Sec. 6 (uniform-random action policy, full games).
  *   Philox        Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As
  *                 Easy as 1, 2, 3", SC'11: Philox4x32 with 10 rounds.
@@ -31,7 +36,7 @@
 #include <string.h>
 
 #define MAX_CELLS 361
-#define MAX_ACTIONS (MAX_CELLS + 1)
+#define MAX_ACTIONS 4096 /* 64 x 64 ordered cell pairs of the 8 x 8 movement games */
 
 typedef struct {
     int kind, H, W, cells, A, max_plies;
@@ -72,6 +77,12 @@ static int natural_bound(int kind, int cells)
         /* a capture frees two cells; after 16 removed stones somebody has
          * captured 10 and won, so the board fills by then */
         return cells + 16;
+    case LUDAX_REF_WOLF_SHEEP:
+        /* every other ply moves a sheep one row up, at most 7 rows each */
+        return 2 * 4 * 7;
+    case LUDAX_REF_DRAUGHTS:
+        /* kings can move back and forth forever: the paper's 200-turn cap */
+        return 200;
     default:
         return cells; /* one stone per ply, never removed */
     }
@@ -91,6 +102,8 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
     case LUDAX_REF_GOMOKU:       ok = (H == W && H >= 5 && H <= 19); break;
     case LUDAX_REF_YAVALATH:     ok = (H == W && (H & 1) && H >= 3 && H <= 9); break;
     case LUDAX_REF_PENTE:        ok = (H == W && (H & 1) && H >= 5 && H <= 19); break;
+    case LUDAX_REF_WOLF_SHEEP:
+    case LUDAX_REF_DRAUGHTS:     ok = (H == 8 && W == 8); break;
     default: return LUDAX_REF_E_UNSUPPORTED;
     }
     if (!ok) return LUDAX_REF_E_UNSUPPORTED;
@@ -104,6 +117,7 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
         g->cells = 3 * g->S * (g->S - 1) + 1;
     }
     g->A = g->cells + (k == LUDAX_REF_REVERSI ? 1 : 0);
+    if (k == LUDAX_REF_WOLF_SHEEP || k == LUDAX_REF_DRAUGHTS) g->A = g->cells * g->cells;
     g->max_plies = d->max_plies ? d->max_plies : natural_bound(k, g->cells);
     return LUDAX_REF_OK;
 }
@@ -173,6 +187,22 @@ static void init_env(const game_t *g, env_t *e)
         e->board[row5 * 8 + D] = 1; /* D5 black */
         e->board[row4 * 8 + E] = 1; /* E4 black */
     }
+    if (g->kind == LUDAX_REF_WOLF_SHEEP) {
+        /* App. C: the sheep on the dark cells of the bottom row, the wolf on
+         * a central dark cell of the top row (the left one of the two) */
+        for (int c = 0; c < 8; c += 2) e->board[7 * 8 + c] = 1;
+        e->board[3] = 2;
+    }
+    if (g->kind == LUDAX_REF_DRAUGHTS) {
+        /* the start cells of the App. B listing: the dark cells of rows 5-7
+         * for player 1 and of rows 0-2 for player 2 */
+        static const int P1[12] = {40, 42, 44, 46, 49, 51, 53, 55, 56, 58, 60, 62};
+        static const int P2[12] = {1, 3, 5, 7, 8, 10, 12, 14, 17, 19, 21, 23};
+        for (int k = 0; k < 12; k++) {
+            e->board[P1[k]] = 1;
+            e->board[P2[k]] = 2;
+        }
+    }
     e->to_move = 1;
     e->status = LUDAX_REF_RUNNING;
     e->winner = -1;
@@ -225,6 +255,73 @@ static int reversi_placement_legal(const game_t *g, const env_t *e, int r, int c
     return 0;
 }
 
+/* ---- movement games (Wolf and Sheep, English Draughts) ---- */
+
+static int is_move_game(const game_t *g)
+{
+    return g->kind == LUDAX_REF_WOLF_SHEEP || g->kind == LUDAX_REF_DRAUGHTS;
+}
+
+/* May the piece with cell value v go in row direction dr (-1 up, +1 down)?
+ * A Draughts king (bit 4) and the wolf go both ways; a pawn or a sheep only
+ * forward: up for player 1, down for player 2. */
+static int goes_both_ways(const game_t *g, int v)
+{
+    return g->kind == LUDAX_REF_DRAUGHTS ? (v & 4) != 0 : v == 2;
+}
+
+static int may_go(const game_t *g, int v, int dr)
+{
+    if (goes_both_ways(g, v)) return 1;
+    return (v & 3) == 1 ? dr < 0 : dr > 0;
+}
+
+/* Destination of the move of the piece on `src` by `dist` (1 = step, 2 =
+ * hop) cells in diagonal direction (dr, dc), or -1 if that move is not
+ * allowed: the direction must suit the piece, the destination must be on
+ * the board and empty, and a hop must pass over an opponent piece. */
+static int move_dst(const game_t *g, const env_t *e, int src, int dr, int dc, int dist)
+{
+    int v = e->board[src], me = v & 3;
+    if (!may_go(g, v, dr)) return -1;
+    int r = src / g->W + dist * dr, c = src % g->W + dist * dc;
+    if (!on_board(g, r, c) || at(g, e, r, c) != 0) return -1;
+    if (dist == 2) {
+        int over = at(g, e, src / g->W + dr, src % g->W + dc);
+        if (over == 0 || (over & 3) != 3 - me) return -1;
+    }
+    return r * g->W + c;
+}
+
+static const int DIAG4[4][2] = {{-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+
+/* Legal moves of the player to move: pieces of `me` (only the piece on
+ * passes - 1 during a Draughts extra turn); the hops if there is any hop
+ * (hop priority 0 over step priority 1, App. B listing), else the steps.
+ * Marks m[src * cells + dst] and returns the number of moves. */
+static int move_legal(const game_t *g, const env_t *e, uint8_t *m)
+{
+    int me = e->to_move;
+    int only = (g->kind == LUDAX_REF_DRAUGHTS && e->passes > 0) ? e->passes - 1 : -1;
+    int first = g->kind == LUDAX_REF_DRAUGHTS ? 2 : 1; /* Wolf and Sheep has no hops */
+    for (int dist = first; dist >= 1; dist--) {
+        int count = 0;
+        for (int src = 0; src < g->cells; src++) {
+            if (e->board[src] == 0 || (e->board[src] & 3) != me) continue;
+            if (only >= 0 && src != only) continue;
+            for (int d = 0; d < 4; d++) {
+                int dst = move_dst(g, e, src, DIAG4[d][0], DIAG4[d][1], dist);
+                if (dst >= 0) {
+                    m[src * g->cells + dst] = 1;
+                    count++;
+                }
+            }
+        }
+        if (count) return count;
+    }
+    return 0;
+}
+
 static void legal(const game_t *g, const env_t *e, uint8_t *m)
 {
     memset(m, 0, (size_t)g->A);
@@ -264,6 +361,10 @@ static void legal(const game_t *g, const env_t *e, uint8_t *m)
         m[g->cells] = (uint8_t)!any; /* forced pass, and only then */
         break;
     }
+    case LUDAX_REF_WOLF_SHEEP:
+    case LUDAX_REF_DRAUGHTS:
+        move_legal(g, e, m);
+        break;
     }
 }
 
@@ -498,6 +599,46 @@ int ludax_ref_holds_win(const ludax_ref_desc *d, const int8_t *board, int who)
 /* step                                                                */
 /* ------------------------------------------------------------------ */
 
+/* A legal move of a movement game and its effects (Sec. 3.2; the order of
+ * the App. B Draughts listing: move and capture, then promotion, then the
+ * extra-turn test).  Returns the player who moves next. */
+static int apply_move(const game_t *g, env_t *e, int a, int me)
+{
+    int src = a / g->cells, dst = a % g->cells;
+    int v = e->board[src];
+    int rs = src / g->W, cs = src % g->W, rd = dst / g->W, cd = dst % g->W;
+    int hop = rd - rs == 2 || rs - rd == 2;
+    e->board[src] = 0;
+    e->board[dst] = (int8_t)v;
+    if (hop) e->board[((rs + rd) / 2) * g->W + (cs + cd) / 2] = 0; /* the hopped piece is captured */
+    e->passes = 0;
+    if (g->kind != LUDAX_REF_DRAUGHTS) return 3 - me;
+    if (!(v & 4) && rd == (me == 1 ? 0 : g->H - 1)) e->board[dst] = (int8_t)(v | 4); /* promotion */
+    if (hop)
+        for (int d = 0; d < 4; d++)
+            if (move_dst(g, e, dst, DIAG4[d][0], DIAG4[d][1], 2) >= 0) {
+                e->passes = (int8_t)(dst + 1); /* extra turn for the same piece */
+                return me;
+            }
+    return 3 - me;
+}
+
+/* End rules of a movement game after the mover's ply, `next` being the
+ * player to move next: the wolf on the bottom row wins (Wolf and Sheep),
+ * then the mover wins if `next` has no legal action. */
+static int move_end_rules(const game_t *g, const env_t *e, int me, int next)
+{
+    if (g->kind == LUDAX_REF_WOLF_SHEEP && me == 2)
+        for (int c = 0; c < g->W; c++)
+            if (at(g, e, g->H - 1, c) == 2) return 2;
+    env_t t = *e;
+    t.to_move = next;
+    uint8_t m[MAX_ACTIONS];
+    memset(m, 0, (size_t)g->A);
+    if (move_legal(g, &t, m) == 0) return me;
+    return -1;
+}
+
 static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_t *term)
 {
     rew[0] = rew[1] = 0;
@@ -512,8 +653,10 @@ static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_
         *term = 1;
         return;
     }
-    int me = e->to_move;
-    if (g->kind == LUDAX_REF_REVERSI && a == g->cells) {
+    int me = e->to_move, next = 3 - me;
+    if (is_move_game(g)) {
+        next = apply_move(g, e, a, me);
+    } else if (g->kind == LUDAX_REF_REVERSI && a == g->cells) {
         e->passes += 1;
     } else {
         int r = a / g->W, c = a % g->W;
@@ -550,7 +693,7 @@ static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_
     e->ply += 1;
     e->last_action = a;
 
-    int w = end_rules(g, e, me);
+    int w = is_move_game(g) ? move_end_rules(g, e, me, next) : end_rules(g, e, me);
     if (g_checks) check_opponent(g, e, me);
     if (w >= 0) {
         e->status = LUDAX_REF_TERMINAL;
@@ -558,7 +701,7 @@ static void step_env(const game_t *g, env_t *e, int32_t a, int8_t rew[2], uint8_
         if (w == 1) { rew[0] = 1; rew[1] = -1; }
         if (w == 2) { rew[0] = -1; rew[1] = 1; }
     } else {
-        e->to_move = 3 - me;
+        e->to_move = next;
         if (e->ply >= g->max_plies) {
             e->status = LUDAX_REF_TRUNCATED;
             e->winner = -1;
@@ -778,6 +921,36 @@ int64_t ludax_ref_perft(const ludax_ref_desc *d, const ludax_ref_state *s, int d
     env_t e;
     load_env(&g, s, 0, &e);
     return perft_rec(&g, &e, depth);
+}
+
+/* As perft_rec, but a ply after which the same player moves again (an
+ * extra turn) does not use up a level. */
+static int64_t perft_turns_rec(const game_t *g, const env_t *e, int depth)
+{
+    if (depth == 0) return 1;
+    if (e->status != LUDAX_REF_RUNNING) return 0;
+    uint8_t m[MAX_ACTIONS];
+    legal(g, e, m);
+    int64_t total = 0;
+    for (int a = 0; a < g->A; a++) {
+        if (!m[a]) continue;
+        env_t c = *e;
+        int8_t rew[2];
+        uint8_t t;
+        step_env(g, &c, a, rew, &t);
+        int again = c.status == LUDAX_REF_RUNNING && c.to_move == e->to_move;
+        total += perft_turns_rec(g, &c, again ? depth : depth - 1);
+    }
+    return total;
+}
+
+int64_t ludax_ref_perft_turns(const ludax_ref_desc *d, const ludax_ref_state *s, int depth)
+{
+    game_t g;
+    if (resolve(d, &g) || !state_ok(s) || depth < 0) return -1;
+    env_t e;
+    load_env(&g, s, 0, &e);
+    return perft_turns_rec(&g, &e, depth);
 }
 
 static int64_t games_rec(const game_t *g, const env_t *e, int64_t *tab, int max_len,

@@ -32,6 +32,29 @@
  *     `passes` byte holds the captured PAIRS: player 1's in the low four
  *     bits, player 2's in the high four bits.  Natural ply bound: cells + 16
  *     (at most 16 stones are removed before somebody reaches 10).
+ *   - Movement games (Sec. 3.2 move mechanic: step and hop), both 8 x 8
+ *     with the dark squares at (r + c) odd:
+ *     the action space is every ordered pair of cells, action
+ *     src * cells + dst (4096 actions), a move of the piece on src to dst.
+ *     A piece may step to an empty diagonal neighbour, or (Draughts) hop
+ *     over a diagonally adjacent opponent piece to the empty cell beyond,
+ *     removing it.  Pawns (and sheep) go forward only: up (towards row 0)
+ *     for player 1, down for player 2; kings (and the wolf) go any diagonal
+ *     way.  Hops have priority: while any hop is legal, no step is.
+ *     After a ply the mover wins if the player to move next has no legal
+ *     action (Draughts' end rule; the sheep's win by blocking the wolf).
+ *   - Wolf and Sheep (App. C): player 1's four sheep (cell value 1) start
+ *     on 56, 58, 60, 62, player 2's wolf (value 2) on 3; the wolf wins on
+ *     reaching the bottom row (checked before the blocking rule).  A sheep
+ *     moves at most 7 times, so a game has at most 56 plies.
+ *   - English Draughts (App. B listing, App. C): cell value = owner | 4 for
+ *     a king (1, 2 pawns; 5, 6 kings); pawns start on the cells the listing
+ *     gives.  After a ply, a pawn on the far row becomes a king; then, if
+ *     the ply was a hop and the same piece can hop again, the mover takes an
+ *     extra turn in which only that piece moves: `passes` holds its cell + 1
+ *     (0 when no extra turn is pending) and to_move does not change.  The
+ *     game has no natural end, so plies are capped at 200 (the paper's cap
+ *     for unbounded games, Sec. 6).
  */
 #ifndef LUDAX_REF_H
 #define LUDAX_REF_H
@@ -50,6 +73,8 @@ extern "C" {
 #define LUDAX_REF_GOMOKU       5
 #define LUDAX_REF_YAVALATH     6
 #define LUDAX_REF_PENTE        7
+#define LUDAX_REF_WOLF_SHEEP   8
+#define LUDAX_REF_DRAUGHTS     9
 
 /* env status */
 #define LUDAX_REF_RUNNING   0
@@ -75,7 +100,9 @@ typedef struct {
     int8_t  *to_move;      /* [n] 1 or 2 */
     int8_t  *status;       /* [n] RUNNING/TERMINAL/TRUNCATED/ILLEGAL */
     int8_t  *winner;       /* [n] -1 none, 0 draw, 1, 2 */
-    int8_t  *passes;       /* [n] consecutive passes (Reversi) */
+    int8_t  *passes;       /* [n] per game: Reversi's consecutive passes,
+                              Pente's captured pairs, Draughts' extra-turn
+                              piece + 1 */
     int16_t *ply;          /* [n] plies applied so far */
     int16_t *last_action;  /* [n] -1 before the first ply */
 } ludax_ref_state;
@@ -120,6 +147,9 @@ uint32_t ludax_ref_draw(uint64_t seed, int64_t game_id, int32_t ply);
  * their number is returned through *truncated.  Returns the number of
  * games. */
 int64_t ludax_ref_perft(const ludax_ref_desc *d, const ludax_ref_state *s, int depth);
+/* The same count over TURNS: the plies of an extra turn (Draughts) belong
+ * to the turn they continue, so a multi-hop capture is one turn. */
+int64_t ludax_ref_perft_turns(const ludax_ref_desc *d, const ludax_ref_state *s, int depth);
 int64_t ludax_ref_count_games(const ludax_ref_desc *d, const ludax_ref_state *s,
                               int64_t *by_len_winner, int max_len, int64_t *truncated);
 

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ludax_ref.c")
 LIB = os.path.join(HERE, "libludax_ref.so")
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE = 1, 2, 3, 4, 5, 6, 7
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS = 1, 2, 3, 4, 5, 6, 7, 8, 9
 RUNNING, TERMINAL, TRUNCATED, ILLEGAL = 0, 1, 2, 3
 
 _lock = threading.Lock()
@@ -76,6 +76,8 @@ def lib():
             L.ludax_ref_draw.restype = ctypes.c_uint32
             L.ludax_ref_perft.argtypes = [P(_Desc), P(_State), ctypes.c_int]
             L.ludax_ref_perft.restype = ctypes.c_int64
+            L.ludax_ref_perft_turns.argtypes = [P(_Desc), P(_State), ctypes.c_int]
+            L.ludax_ref_perft_turns.restype = ctypes.c_int64
             L.ludax_ref_count_games.argtypes = [P(_Desc), P(_State), ctypes.c_void_p, ctypes.c_int,
                                                 ctypes.c_void_p]
             L.ludax_ref_count_games.restype = ctypes.c_int64
@@ -217,6 +219,10 @@ def draw(seed: int, game_id: int, ply: int) -> int:
 
 def perft(game: Game, s: State, depth: int) -> int:
     return lib().ludax_ref_perft(ctypes.byref(game.desc()), ctypes.byref(s.c()), depth)
+
+
+def perft_turns(game: Game, s: State, depth: int) -> int:
+    return lib().ludax_ref_perft_turns(ctypes.byref(game.desc()), ctypes.byref(s.c()), depth)
 
 
 def count_games(game: Game, s: State, max_len: int):
