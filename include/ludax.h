@@ -37,6 +37,25 @@
  *                      byte holds the captured pairs (player 1: low four
  *                      bits, player 2: high four bits); natural ply bound
  *                      cells + 16.
+ *   LUDAX_WOLF_SHEEP   8x8 movement game (Sec. 3.2 step mechanic): player 1's
+ *                      four sheep (cell value 1) start on cells 56, 58, 60,
+ *                      62 and step diagonally up into an empty cell; player
+ *                      2's wolf (value 2) starts on cell 3 and steps to any
+ *                      empty diagonal neighbour.  The wolf wins on reaching
+ *                      the bottom row; a player left without a legal move
+ *                      after the opponent's ply loses.  Natural ply bound 56.
+ *   LUDAX_DRAUGHTS     8x8 English Draughts (App. B listing): pawns (1, 2)
+ *                      step diagonally forward (player 1 up, player 2 down)
+ *                      or hop over an adjacent opponent piece into the empty
+ *                      cell beyond and capture it; kings (cell value owner |
+ *                      4: 5, 6) do both in all four diagonal directions.
+ *                      While any hop is legal no step is.  After a ply a pawn
+ *                      on its far row becomes a king; then, after a hop, if
+ *                      the same piece can hop again the mover plays again
+ *                      with that piece only: `passes` holds its cell + 1 (0
+ *                      otherwise) and to_move stays.  A player left without
+ *                      a legal move loses.  Natural ply bound: 200 (the
+ *                      game itself is unbounded).
  * Anything else is LUDAX_E_UNSUPPORTED.
  *
  * Board and action conventions:
@@ -45,7 +64,9 @@
  *   1 (player 1) or 2 (player 2).
  *   The action space is the set of cells (Sec. 3.4: its size depends only
  *   on the board and the play mechanic), plus one PASS action at index
- *   rows*cols for Reversi.  Player 1 moves first; movers alternate; a pass
+ *   rows*cols for Reversi.  For the movement games it is the set of
+ *   ordered cell pairs: action src * cells + dst moves the piece on src to
+ *   dst (4096 actions).  Player 1 moves first; movers alternate; a pass
  *   is a ply.  Reversi: player 1 is black; discs start on D5, E4 (player 1)
  *   and D4, E5 (player 2) with letters naming columns left to right and
  *   digits rows top to bottom.
@@ -82,6 +103,8 @@ extern "C" {
 #define LUDAX_GOMOKU       5
 #define LUDAX_YAVALATH     6
 #define LUDAX_PENTE        7
+#define LUDAX_WOLF_SHEEP   8
+#define LUDAX_DRAUGHTS     9
 
 /* per-environment status values (ludax_state.status) */
 #define LUDAX_RUNNING   0 /* the game goes on */
@@ -100,10 +123,11 @@ typedef struct ludax_game ludax_game; /* opaque, immutable after create */
 /* Static description of a game (Sec. 4: every shape is fixed when the
  * game is built). */
 typedef struct {
-    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_PENTE */
+    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_DRAUGHTS */
     int32_t rows;
     int32_t cols;
-    int32_t max_plies; /* 0 = the natural bound: cells (Reversi: 121); at most 32767 */
+    int32_t max_plies; /* 0 = the natural bound: cells (Reversi 121, Pente cells + 16,
+                          Wolf and Sheep 56, Draughts 200); at most 32767 */
 } ludax_game_desc;
 
 /* Structure-of-arrays batch state for n environments (Sec. 4, dynamic
@@ -113,12 +137,13 @@ typedef struct {
  * playouts; on hand-edited boards results are defined only as "no memory
  * access outside the buffers" (see ludax_playout for the one safeguard). */
 typedef struct {
-    int8_t  *board;       /* [n][rows*cols], 0 empty, 1, 2 */
+    int8_t  *board;       /* [n][rows*cols], 0 empty, 1, 2 (Draughts kings: 5, 6) */
     int8_t  *to_move;     /* [n] player to move, 1 or 2 */
     int8_t  *status;      /* [n] LUDAX_RUNNING ... LUDAX_ILLEGAL */
     int8_t  *winner;      /* [n] -1 none, 0 draw, 1, 2 */
     int8_t  *passes;      /* [n] the game's extra state byte: Reversi's consecutive passes,
-                             Pente's captured pairs (see above), 0 otherwise */
+                             Pente's captured pairs, Draughts' extra-turn piece + 1
+                             (see above), 0 otherwise */
     int16_t *ply;         /* [n] plies applied since the start */
     int16_t *last_action; /* [n] last applied action, -1 before the first */
     void    *aux;         /* reserved; may be NULL (no game needs it: aux_bytes = 0) */
@@ -136,8 +161,8 @@ int ludax_game_info(const ludax_game *game, int32_t *cells, int32_t *num_actions
                     int32_t *aux_bytes, int32_t *max_plies);
 
 /* Start position (Sec. 3.1 start rules) for all n environments: empty
- * board (Reversi: the four start discs), to_move 1, RUNNING, winner -1,
- * passes 0, ply 0, last_action -1. */
+ * board (Reversi: the four start discs; the movement games: their start
+ * pieces), to_move 1, RUNNING, winner -1, passes 0, ply 0, last_action -1. */
 int ludax_init(const ludax_game *game, ludax_state *state, int64_t n, hipStream_t stream);
 
 /* Legal-action mask (Sec. 3.2: each play mechanic defines one of fixed
@@ -203,7 +228,8 @@ int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed,
  * max) over the legal placements exceeds u * (their total), u = (w >> 8) /
  * 2^24 for the ply's Philox word w (the last legal placement if rounding
  * leaves none); with no legal placement (Reversi) it passes.  logits:
- * [n][A] float32 in action order (a PASS entry is ignored). */
+ * [n][A] float32 in action order (a PASS entry is ignored).  Movement
+ * games: the same rule over their legal moves in increasing action order. */
 int ludax_policy_step(const ludax_game *game, ludax_state *state, const float *logits, uint64_t seed,
                       int64_t game_id_base, const int64_t *game_id, int8_t *reward, uint8_t *terminal,
                       int64_t n, hipStream_t stream);
@@ -232,7 +258,8 @@ int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t 
  * ------------------------------------------------------------------------ */
 typedef struct ludax_mixed ludax_mixed;
 
-/* 1 <= n_kinds <= 8 game handles (they must outlive the mixed handle).
+/* 1 <= n_kinds <= 8 game handles (they must outlive the mixed handle);
+ * the movement games have no mixed batch (LUDAX_E_UNSUPPORTED).
  * Creates the internal streams and events; the default plan gives every
  * kind 65536 slots.  A mixed handle serves one host thread at a time. */
 int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mixed **out);

@@ -92,7 +92,12 @@ int natural_bound(int kind, int cells)
     // the two final passes.  Other games: one stone per ply, never removed.
     // Pente: a capture frees two cells, and after 16 removed stones somebody
     // has captured 10 and won, so the board is full by cells + 16 plies.
+    // Wolf and Sheep: every other ply moves one of the four sheep a row up,
+    // at most 7 rows each.  Draughts has no natural end (kings can move back
+    // and forth): the 200-ply cap for unbounded games.
     if (kind == LUDAX_PENTE) return cells + 16;
+    if (kind == LUDAX_WOLF_SHEEP) return 2 * 4 * 7;
+    if (kind == LUDAX_DRAUGHTS) return 200;
     return kind == LUDAX_REVERSI ? (cells - 4) + (cells - 5) + 2 : cells;
 }
 
@@ -115,6 +120,8 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out)
     case LUDAX_GOMOKU: ops = lx::ops_gomoku(desc->rows, desc->cols); break;
     case LUDAX_YAVALATH: ops = lx::ops_yavalath(desc->rows, desc->cols); break;
     case LUDAX_PENTE: ops = lx::ops_pente(desc->rows, desc->cols); break;
+    case LUDAX_WOLF_SHEEP: ops = lx::ops_wolf_sheep(desc->rows, desc->cols); break;
+    case LUDAX_DRAUGHTS: ops = lx::ops_draughts(desc->rows, desc->cols); break;
     default: return LUDAX_E_UNSUPPORTED;
     }
     if (ops == nullptr) return LUDAX_E_UNSUPPORTED;
@@ -353,6 +360,8 @@ int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mi
     *out = nullptr;
     for (int k = 0; k < n_kinds; ++k)
         if (games[k] == nullptr) return LUDAX_E_INVALID;
+    for (int k = 0; k < n_kinds; ++k)
+        if (games[k]->ops->persist == nullptr) return LUDAX_E_UNSUPPORTED;
     ludax_mixed *m = new (std::nothrow) ludax_mixed;
     if (m == nullptr) return LUDAX_E_INVALID;
     m->n = n_kinds;

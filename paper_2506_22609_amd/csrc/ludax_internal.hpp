@@ -43,7 +43,7 @@ struct GameOps {
                               int8_t *, uint8_t *, hipStream_t);
     hipError_t (*playout)(const DevState &, int64_t, int, uint64_t, int64_t, const int64_t *, int8_t *,
                           uint8_t *, int64_t *, hipStream_t);
-    hipError_t (*persist)(const MixedArgs &, int, hipStream_t);
+    hipError_t (*persist)(const MixedArgs &, int, hipStream_t); // NULL: no mixed batches of this game
 };
 
 hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s);
@@ -81,5 +81,7 @@ const GameOps *ops_reversi(int rows, int cols);
 const GameOps *ops_gomoku(int rows, int cols);
 const GameOps *ops_yavalath(int rows, int cols);
 const GameOps *ops_pente(int rows, int cols);
+const GameOps *ops_wolf_sheep(int rows, int cols);
+const GameOps *ops_draughts(int rows, int cols);
 
 } // namespace lx

@@ -46,7 +46,8 @@ def test_game_create_and_info():
     L = _lib()
     cases = {(1, 3, 3): (9, 9, 9), (2, 6, 7): (42, 42, 42), (3, 11, 11): (121, 121, 121),
              (4, 8, 8): (64, 65, 121), (5, 15, 15): (225, 225, 225), (3, 1, 1): (1, 1, 1),
-             (3, 19, 19): (361, 361, 361), (5, 5, 5): (25, 25, 25)}
+             (3, 19, 19): (361, 361, 361), (5, 5, 5): (25, 25, 25), (8, 8, 8): (64, 4096, 56),
+             (9, 8, 8): (64, 4096, 200)}
     for (k, r, c), exp in cases.items():
         rc, h = _create(k, r, c)
         assert rc == 0
@@ -64,7 +65,7 @@ def test_game_create_and_info():
 
 def test_unsupported_and_invalid_descs():
     for k, r, c in [(2, 7, 6), (1, 4, 4), (3, 20, 20), (3, 5, 6), (5, 4, 4), (5, 20, 20), (4, 6, 6),
-                    (9, 3, 3), (0, 3, 3)]:
+                    (9, 3, 3), (0, 3, 3), (8, 9, 9), (9, 10, 10), (8, 8, 7), (10, 8, 8)]:
         assert _create(k, r, c)[0] == ludax.E_UNSUPPORTED, (k, r, c)
     for k, r, c, m in [(1, 0, 3, 0), (1, 3, -1, 0), (1, 3, 3, -1), (1, 3, 3, 40000)]:
         assert _create(k, r, c, m)[0] == ludax.E_INVALID
@@ -141,6 +142,11 @@ def test_mixed_argument_checks_need_no_gpu():
     assert L.ludax_mixed_set_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_get_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_playout(None, 1, 0, 10, 16, 16, 16, None, 16, None) == ludax.E_INVALID
+    # the movement games have no mixed persistent batch
+    rc, hd = _create(9, 8, 8)
+    both = (ctypes.c_void_p * 2)(h.value, hd.value)
+    assert L.ludax_mixed_create(both, 2, ctypes.byref(out)) == ludax.E_UNSUPPORTED
+    L.ludax_game_destroy(hd)
     L.ludax_game_destroy(h)
 
 

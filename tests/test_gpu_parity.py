@@ -28,9 +28,12 @@ GAMES = [
     (ref.YAVALATH, 5, 5),
     (ref.PENTE, 19, 19),
     (ref.PENTE, 7, 7),
+    (ref.WOLF_SHEEP, 8, 8),
+    (ref.DRAUGHTS, 8, 8),
 ]
 IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19", "yavalath9", "yavalath5", "pente19",
-       "pente7"]
+       "pente7", "wolf_sheep", "draughts"]
+MOVES = [GAMES[-2], GAMES[-1]]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -244,7 +247,7 @@ def test_random_step_sequences(g):
     d = to_device(dg, s)
     dgid = torch.from_numpy(gid).cuda()
     seed = 0x1234_5678_9ABC_DEF0 + g[0]
-    for p in range(og.cells + 130):
+    for p in range(og.info()[2] + 5):
         rew, term = _oracle_random_step(og, s, seed, gid)
         grew, gterm = ludax.random_step(dg, d, seed, game_id=dgid)
         assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
@@ -267,7 +270,7 @@ def test_random_step_loop_equals_playout(g):
     ludax.init(dg, d)
     st = torch.zeros(4, dtype=torch.int64, device="cuda")
     ludax.state_stats(dg, d, -1, st)
-    for _ in range(og.cells + 130):
+    for _ in range(og.info()[2] + 5):
         _, term = ludax.random_step(dg, d, 5, 1000)
         if bool(term.all()):
             break
@@ -297,8 +300,8 @@ def test_step_blocks_without_running_env(g):
     assert_same_state(s, from_device(d))
 
 
-@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7], GAMES[9]],
-                         ids=["hex11", "reversi", "gomoku15", "yavalath9", "pente19"])
+@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7], GAMES[9], GAMES[12]],
+                         ids=["hex11", "reversi", "gomoku15", "yavalath9", "pente19", "draughts"])
 def test_policy_step_sequences(g):
     """ludax_policy_step ply by ply against the oracle's draw + step, with
     random logits: every action equals the oracle's, except where the
@@ -315,15 +318,16 @@ def test_policy_step_sequences(g):
     dgid = torch.from_numpy(gid).cuda()
     seed = 77
     close_calls = 0
-    for p in range(og.cells + 130):
+    P = og.num_actions - (1 if g[0] == ref.REVERSI else 0)  # the actions that are not PASS
+    for p in range(og.info()[2] + 5):
         lg = (rng.standard_normal((n, og.num_actions)) * 2.0).astype(np.float32)
         m = ref.legal_mask(og, s)
         a = np.full(n, -1, np.int32)
         near = np.zeros(n, bool)
         for i in np.flatnonzero(s.status == ref.RUNNING):
-            legal = m[i, :og.cells].astype(bool)
+            legal = m[i, :P].astype(bool)
             if legal.any():
-                a[i], margin = R.policy_action(lg[i, :og.cells], legal, ref.draw(seed, int(gid[i]), int(s.ply[i])))
+                a[i], margin = R.policy_action(lg[i, :P], legal, ref.draw(seed, int(gid[i]), int(s.ply[i])))
                 near[i] = margin < 1e-5
             elif m[i].any():
                 a[i] = og.num_actions - 1  # forced pass
@@ -335,7 +339,7 @@ def test_policy_step_sequences(g):
         for i in np.flatnonzero(near & (ga != s.last_action)):
             # a draw at a boundary: accept the neighbouring legal action, replay it on the oracle
             close_calls += 1
-            legal = np.flatnonzero(m[i, :og.cells])
+            legal = np.flatnonzero(m[i, :P])
             k = np.searchsorted(legal, s.last_action[i])
             assert ga[i] in legal[max(0, k - 1):k + 2]
             one = s_before.subset([i])
@@ -349,3 +353,30 @@ def test_policy_step_sequences(g):
         if (s.status != ref.RUNNING).all():
             break
     assert close_calls <= 2
+
+
+@pytest.mark.parametrize("g", MOVES, ids=["wolf_sheep", "draughts"])
+def test_moves_deep_positions(g):
+    """Movement games from positions deep into the game (Draughts: kings,
+    pending extra turns): mask, stepped plies with next masks, then the
+    playout to the end."""
+    og, dg = pair(*g)
+    rng = np.random.default_rng(61)
+    n = 300
+    s = random_states(og, n, 150 if g[0] == ref.DRAUGHTS else 50, rng)
+    if g[0] == ref.DRAUGHTS:
+        assert (s.board >= 5).any() and ((s.passes > 0) & (s.status == ref.RUNNING)).any()
+    d = to_device(dg, s)
+    assert np.array_equal(ludax.legal_mask(dg, d).cpu().numpy(), ref.legal_mask(og, s))
+    for p in range(40):
+        m = ref.legal_mask(og, s)
+        a = np.array([np.flatnonzero(r)[rng.integers(0, r.sum())] if r.any() else 0 for r in m], np.int32)
+        rew, term, nm = ref.step(og, s, a)
+        grew, gterm, gnm = ludax.step(dg, d, torch.from_numpy(a).cuda())
+        assert np.array_equal(rew, grew.cpu().numpy()) and np.array_equal(term, gterm.cpu().numpy()), p
+        assert np.array_equal(nm, gnm.cpu().numpy()), f"next mask at ply {p}"
+        assert_same_state(s, from_device(d), f"ply {p}")
+    rew, term, stats = ref.playout(og, s, 3, 70, threads=8)
+    grew, gterm, gstats = ludax.playout(dg, d, 3, 70)
+    assert_same_state(s, from_device(d), "playout")
+    assert np.array_equal(rew, grew.cpu().numpy()) and np.array_equal(stats, gstats.cpu().numpy())
