@@ -340,8 +340,9 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
 
 
 def _more_games_section(seed: int, reps: int):
-    """Plain fused playouts of the other placement games, 65536 envs each:
-    Yavalath on the diameter-9 hexagon, Pente 19x19."""
+    """Plain fused playouts of the paper's other games, 65536 envs each:
+    Yavalath on the diameter-9 hexagon, Pente 19x19, and the movement games
+    Wolf and Sheep and English Draughts (8x8)."""
     import torch
     from paper_2506_22609_amd import ludax
     from paper_2506_22609_amd import workloads as W
