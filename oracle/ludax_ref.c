@@ -36,7 +36,7 @@
 #include <string.h>
 
 #define MAX_CELLS 361
-#define MAX_ACTIONS 4096 /* 64 x 64 ordered cell pairs of the 8 x 8 movement games */
+#define MAX_ACTIONS 6561 /* 81 x 81 ordered cell pairs of Dai Hasami Shogi */
 
 typedef struct {
     int kind, H, W, cells, A, max_plies;
@@ -81,7 +81,8 @@ static int natural_bound(int kind, int cells)
         /* every other ply moves a sheep one row up, at most 7 rows each */
         return 2 * 4 * 7;
     case LUDAX_REF_DRAUGHTS:
-        /* kings can move back and forth forever: the paper's 200-turn cap */
+    case LUDAX_REF_HASAMI_SHOGI:
+        /* pieces can move back and forth forever: the paper's 200-turn cap */
         return 200;
     default:
         return cells; /* one stone per ply, never removed */
@@ -104,6 +105,7 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
     case LUDAX_REF_PENTE:        ok = (H == W && (H & 1) && H >= 5 && H <= 19); break;
     case LUDAX_REF_WOLF_SHEEP:
     case LUDAX_REF_DRAUGHTS:     ok = (H == 8 && W == 8); break;
+    case LUDAX_REF_HASAMI_SHOGI: ok = (H == 9 && W == 9); break;
     default: return LUDAX_REF_E_UNSUPPORTED;
     }
     if (!ok) return LUDAX_REF_E_UNSUPPORTED;
@@ -117,7 +119,8 @@ static int resolve(const ludax_ref_desc *d, game_t *g)
         g->cells = 3 * g->S * (g->S - 1) + 1;
     }
     g->A = g->cells + (k == LUDAX_REF_REVERSI ? 1 : 0);
-    if (k == LUDAX_REF_WOLF_SHEEP || k == LUDAX_REF_DRAUGHTS) g->A = g->cells * g->cells;
+    if (k == LUDAX_REF_WOLF_SHEEP || k == LUDAX_REF_DRAUGHTS || k == LUDAX_REF_HASAMI_SHOGI)
+        g->A = g->cells * g->cells;
     g->max_plies = d->max_plies ? d->max_plies : natural_bound(k, g->cells);
     return LUDAX_REF_OK;
 }
@@ -203,6 +206,13 @@ static void init_env(const game_t *g, env_t *e)
             e->board[P2[k]] = 2;
         }
     }
+    if (g->kind == LUDAX_REF_HASAMI_SHOGI) {
+        /* App. C: each player fills the two rows on its side */
+        for (int c = 0; c < 9; c++) {
+            e->board[0 * 9 + c] = e->board[1 * 9 + c] = 2;
+            e->board[7 * 9 + c] = e->board[8 * 9 + c] = 1;
+        }
+    }
     e->to_move = 1;
     e->status = LUDAX_REF_RUNNING;
     e->winner = -1;
@@ -259,7 +269,36 @@ static int reversi_placement_legal(const game_t *g, const env_t *e, int r, int c
 
 static int is_move_game(const game_t *g)
 {
-    return g->kind == LUDAX_REF_WOLF_SHEEP || g->kind == LUDAX_REF_DRAUGHTS;
+    return g->kind == LUDAX_REF_WOLF_SHEEP || g->kind == LUDAX_REF_DRAUGHTS || g->kind == LUDAX_REF_HASAMI_SHOGI;
+}
+
+static const int ORTH4[4][2] = {{-1, 0}, {0, -1}, {0, 1}, {1, 0}};
+
+/* Dai Hasami Shogi moves of the player to move: from each of its pieces,
+ * along each row / column direction, a slide to every cell of the run of
+ * empty cells next to it, or, if the neighbour is a piece (either
+ * player's), a hop to the cell beyond it when that cell is empty. */
+static int shogi_legal(const game_t *g, const env_t *e, uint8_t *m)
+{
+    int me = e->to_move, count = 0;
+    for (int src = 0; src < g->cells; src++) {
+        if (e->board[src] != me) continue;
+        int r = src / g->W, c = src % g->W;
+        for (int d = 0; d < 4; d++) {
+            int dr = ORTH4[d][0], dc = ORTH4[d][1], k = 1;
+            while (on_board(g, r + k * dr, c + k * dc) && at(g, e, r + k * dr, c + k * dc) == 0) {
+                m[src * g->cells + (r + k * dr) * g->W + (c + k * dc)] = 1;
+                count++;
+                k++;
+            }
+            if (k == 1 && on_board(g, r + dr, c + dc) && on_board(g, r + 2 * dr, c + 2 * dc) &&
+                at(g, e, r + 2 * dr, c + 2 * dc) == 0) {
+                m[src * g->cells + (r + 2 * dr) * g->W + (c + 2 * dc)] = 1;
+                count++;
+            }
+        }
+    }
+    return count;
 }
 
 /* May the piece with cell value v go in row direction dr (-1 up, +1 down)?
@@ -301,6 +340,7 @@ static const int DIAG4[4][2] = {{-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
  * Marks m[src * cells + dst] and returns the number of moves. */
 static int move_legal(const game_t *g, const env_t *e, uint8_t *m)
 {
+    if (g->kind == LUDAX_REF_HASAMI_SHOGI) return shogi_legal(g, e, m);
     int me = e->to_move;
     int only = (g->kind == LUDAX_REF_DRAUGHTS && e->passes > 0) ? e->passes - 1 : -1;
     int first = g->kind == LUDAX_REF_DRAUGHTS ? 2 : 1; /* Wolf and Sheep has no hops */
@@ -363,6 +403,7 @@ static void legal(const game_t *g, const env_t *e, uint8_t *m)
     }
     case LUDAX_REF_WOLF_SHEEP:
     case LUDAX_REF_DRAUGHTS:
+    case LUDAX_REF_HASAMI_SHOGI:
         move_legal(g, e, m);
         break;
     }
@@ -599,6 +640,30 @@ int ludax_ref_holds_win(const ludax_ref_desc *d, const int8_t *board, int who)
 /* step                                                                */
 /* ------------------------------------------------------------------ */
 
+/* Dai Hasami Shogi captures after `me` moved a piece to dst: along each row
+ * and column direction from dst, a run of one or more opponent pieces
+ * closed by another piece of the mover's is removed; an opponent piece on
+ * a corner is removed when both its neighbours are the mover's and one of
+ * them is dst. */
+static void shogi_captures(const game_t *g, env_t *e, int dst, int me)
+{
+    int opp = 3 - me, r = dst / g->W, c = dst % g->W;
+    for (int d = 0; d < 4; d++) {
+        int dr = ORTH4[d][0], dc = ORTH4[d][1], k = 1;
+        while (on_board(g, r + k * dr, c + k * dc) && at(g, e, r + k * dr, c + k * dc) == opp) k++;
+        if (k > 1 && on_board(g, r + k * dr, c + k * dc) && at(g, e, r + k * dr, c + k * dc) == me)
+            for (int j = 1; j < k; j++) e->board[(r + j * dr) * g->W + (c + j * dc)] = 0;
+    }
+    static const int CORNER[4][2] = {{0, 0}, {0, 8}, {8, 0}, {8, 8}};
+    for (int q = 0; q < 4; q++) {
+        int cr = CORNER[q][0], cc = CORNER[q][1];
+        int vr = cr == 0 ? 1 : cr - 1, hc = cc == 0 ? 1 : cc - 1; /* its column and row neighbours */
+        int v = vr * g->W + cc, h = cr * g->W + hc;
+        if (at(g, e, cr, cc) == opp && e->board[v] == me && e->board[h] == me && (dst == v || dst == h))
+            e->board[cr * g->W + cc] = 0;
+    }
+}
+
 /* A legal move of a movement game and its effects (Sec. 3.2; the order of
  * the App. B Draughts listing: move and capture, then promotion, then the
  * extra-turn test).  Returns the player who moves next. */
@@ -607,11 +672,15 @@ static int apply_move(const game_t *g, env_t *e, int a, int me)
     int src = a / g->cells, dst = a % g->cells;
     int v = e->board[src];
     int rs = src / g->W, cs = src % g->W, rd = dst / g->W, cd = dst % g->W;
-    int hop = rd - rs == 2 || rs - rd == 2;
     e->board[src] = 0;
     e->board[dst] = (int8_t)v;
-    if (hop) e->board[((rs + rd) / 2) * g->W + (cs + cd) / 2] = 0; /* the hopped piece is captured */
     e->passes = 0;
+    if (g->kind == LUDAX_REF_HASAMI_SHOGI) { /* slides and hops only move the piece */
+        shogi_captures(g, e, dst, me);
+        return 3 - me;
+    }
+    int hop = rd - rs == 2 || rs - rd == 2;
+    if (hop) e->board[((rs + rd) / 2) * g->W + (cs + cd) / 2] = 0; /* the hopped piece is captured */
     if (g->kind != LUDAX_REF_DRAUGHTS) return 3 - me;
     if (!(v & 4) && rd == (me == 1 ? 0 : g->H - 1)) e->board[dst] = (int8_t)(v | 4); /* promotion */
     if (hop)
@@ -623,6 +692,23 @@ static int apply_move(const game_t *g, env_t *e, int a, int me)
     return 3 - me;
 }
 
+/* Dai Hasami Shogi's win: five of `me`'s pieces in a row or a column, none
+ * of them on me's two start rows. */
+static int shogi_five(const game_t *g, const env_t *e, int me)
+{
+    int lo = me == 1 ? 0 : 2, hi = me == 1 ? 6 : 8; /* rows outside the start rows */
+    for (int r = lo; r <= hi; r++)
+        for (int c = 0; c < g->W; c++) {
+            int row = c + 5 <= g->W, col = r + 4 <= hi;
+            for (int k = 0; k < 5 && (row || col); k++) {
+                if (row && !(on_board(g, r, c + k) && at(g, e, r, c + k) == me)) row = 0;
+                if (col && at(g, e, r + k, c) != me) col = 0;
+            }
+            if (row || col) return 1;
+        }
+    return 0;
+}
+
 /* End rules of a movement game after the mover's ply, `next` being the
  * player to move next: the wolf on the bottom row wins (Wolf and Sheep),
  * then the mover wins if `next` has no legal action. */
@@ -631,6 +717,7 @@ static int move_end_rules(const game_t *g, const env_t *e, int me, int next)
     if (g->kind == LUDAX_REF_WOLF_SHEEP && me == 2)
         for (int c = 0; c < g->W; c++)
             if (at(g, e, g->H - 1, c) == 2) return 2;
+    if (g->kind == LUDAX_REF_HASAMI_SHOGI && shogi_five(g, e, me)) return me;
     env_t t = *e;
     t.to_move = next;
     uint8_t m[MAX_ACTIONS];

@@ -55,6 +55,17 @@
  *     (0 when no extra turn is pending) and to_move does not change.  The
  *     game has no natural end, so plies are capped at 200 (the paper's cap
  *     for unbounded games, Sec. 6).
+ *   - Dai Hasami Shogi (App. C), 9 x 9, action src * 81 + dst: player 1's
+ *     18 pieces start on rows 7-8, player 2's on rows 0-1.  A piece slides
+ *     any number of empty cells along its row or column, or hops over one
+ *     adjacent piece of either player (no capture) to the empty cell beyond.
+ *     After the move, every straight row or column run of opponent pieces
+ *     enclosed between the moved piece and another of the mover's pieces is
+ *     captured, and so is an opponent piece on a corner whose two neighbours
+ *     are then both the mover's (the moved piece being one of them).  Five
+ *     of the mover's pieces in a row or column, none on the mover's start
+ *     rows, win; then a next player without a legal move loses.  No natural
+ *     end: 200 plies.
  */
 #ifndef LUDAX_REF_H
 #define LUDAX_REF_H
@@ -75,6 +86,7 @@ extern "C" {
 #define LUDAX_REF_PENTE        7
 #define LUDAX_REF_WOLF_SHEEP   8
 #define LUDAX_REF_DRAUGHTS     9
+#define LUDAX_REF_HASAMI_SHOGI 10
 
 /* env status */
 #define LUDAX_REF_RUNNING   0

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ludax_ref.c")
 LIB = os.path.join(HERE, "libludax_ref.so")
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS = 1, 2, 3, 4, 5, 6, 7, 8, 9
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS, HASAMI_SHOGI = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 RUNNING, TERMINAL, TRUNCATED, ILLEGAL = 0, 1, 2, 3
 
 _lock = threading.Lock()
