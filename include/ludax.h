@@ -56,6 +56,18 @@
  *                      otherwise) and to_move stays.  A player left without
  *                      a legal move loses.  Natural ply bound: 200 (the
  *                      game itself is unbounded).
+ *   LUDAX_HASAMI_SHOGI 9x9 Dai Hasami Shogi (Sec. 3.2 slide and hop): player
+ *                      1's 18 pieces start on rows 7-8, player 2's on rows
+ *                      0-1.  A piece slides any number of empty cells along
+ *                      its row or column, or hops over an adjacent piece of
+ *                      either player (no capture) to the empty cell beyond.
+ *                      Every row or column run of opponent pieces enclosed
+ *                      between the moved piece and another of the mover's
+ *                      is captured, as is an opponent corner piece whose two
+ *                      neighbours become the mover's.  Five of the mover's
+ *                      pieces in a row or column, none on its two start
+ *                      rows, win; a player left without a legal move loses.
+ *                      Natural ply bound: 200 (unbounded game).
  * Anything else is LUDAX_E_UNSUPPORTED.
  *
  * Board and action conventions:
@@ -66,7 +78,7 @@
  *   on the board and the play mechanic), plus one PASS action at index
  *   rows*cols for Reversi.  For the movement games it is the set of
  *   ordered cell pairs: action src * cells + dst moves the piece on src to
- *   dst (4096 actions).  Player 1 moves first; movers alternate; a pass
+ *   dst (4096 actions on 8x8, 6561 on 9x9).  Player 1 moves first; movers alternate; a pass
  *   is a ply.  Reversi: player 1 is black; discs start on D5, E4 (player 1)
  *   and D4, E5 (player 2) with letters naming columns left to right and
  *   digits rows top to bottom.
@@ -105,6 +117,7 @@ extern "C" {
 #define LUDAX_PENTE        7
 #define LUDAX_WOLF_SHEEP   8
 #define LUDAX_DRAUGHTS     9
+#define LUDAX_HASAMI_SHOGI 10
 
 /* per-environment status values (ludax_state.status) */
 #define LUDAX_RUNNING   0 /* the game goes on */
@@ -123,11 +136,12 @@ typedef struct ludax_game ludax_game; /* opaque, immutable after create */
 /* Static description of a game (Sec. 4: every shape is fixed when the
  * game is built). */
 typedef struct {
-    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_DRAUGHTS */
+    int32_t kind;      /* LUDAX_TICTACTOE ... LUDAX_HASAMI_SHOGI */
     int32_t rows;
     int32_t cols;
     int32_t max_plies; /* 0 = the natural bound: cells (Reversi 121, Pente cells + 16,
-                          Wolf and Sheep 56, Draughts 200); at most 32767 */
+                          Wolf and Sheep 56, Draughts and Dai Hasami Shogi 200);
+                          at most 32767 */
 } ludax_game_desc;
 
 /* Structure-of-arrays batch state for n environments (Sec. 4, dynamic

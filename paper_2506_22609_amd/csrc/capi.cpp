@@ -93,11 +93,12 @@ int natural_bound(int kind, int cells)
     // Pente: a capture frees two cells, and after 16 removed stones somebody
     // has captured 10 and won, so the board is full by cells + 16 plies.
     // Wolf and Sheep: every other ply moves one of the four sheep a row up,
-    // at most 7 rows each.  Draughts has no natural end (kings can move back
-    // and forth): the 200-ply cap for unbounded games.
+    // at most 7 rows each.  Draughts and Dai Hasami Shogi have no natural
+    // end (pieces can move back and forth): the 200-ply cap for unbounded
+    // games.
     if (kind == LUDAX_PENTE) return cells + 16;
     if (kind == LUDAX_WOLF_SHEEP) return 2 * 4 * 7;
-    if (kind == LUDAX_DRAUGHTS) return 200;
+    if (kind == LUDAX_DRAUGHTS || kind == LUDAX_HASAMI_SHOGI) return 200;
     return kind == LUDAX_REVERSI ? (cells - 4) + (cells - 5) + 2 : cells;
 }
 
@@ -122,6 +123,7 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out)
     case LUDAX_PENTE: ops = lx::ops_pente(desc->rows, desc->cols); break;
     case LUDAX_WOLF_SHEEP: ops = lx::ops_wolf_sheep(desc->rows, desc->cols); break;
     case LUDAX_DRAUGHTS: ops = lx::ops_draughts(desc->rows, desc->cols); break;
+    case LUDAX_HASAMI_SHOGI: ops = lx::ops_hasami_shogi(desc->rows, desc->cols); break;
     default: return LUDAX_E_UNSUPPORTED;
     }
     if (ops == nullptr) return LUDAX_E_UNSUPPORTED;

@@ -83,5 +83,6 @@ const GameOps *ops_yavalath(int rows, int cols);
 const GameOps *ops_pente(int rows, int cols);
 const GameOps *ops_wolf_sheep(int rows, int cols);
 const GameOps *ops_draughts(int rows, int cols);
+const GameOps *ops_hasami_shogi(int rows, int cols);
 
 } // namespace lx

@@ -14,7 +14,7 @@ import threading
 
 import torch
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS = 1, 2, 3, 4, 5, 6, 7, 8, 9
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS, HASAMI_SHOGI = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 RUNNING, TERMINAL, TRUNCATED, ILLEGAL = 0, 1, 2, 3
 OK, E_INVALID, E_UNSUPPORTED, E_DEVICE = 0, -1, -2, -3
 

@@ -8,7 +8,7 @@ The paper benchmarks its own rule sets under a uniformly random policy
 """
 from dataclasses import dataclass
 
-TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS = 1, 2, 3, 4, 5, 6, 7, 8, 9
+TICTACTOE, CONNECT_FOUR, HEX, REVERSI, GOMOKU, YAVALATH, PENTE, WOLF_SHEEP, DRAUGHTS, HASAMI_SHOGI = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 
 SEEDS = (1, 2, 3)
 
@@ -36,10 +36,11 @@ BENCH_BATCHES = (C4_65536, HEX11_65536)
 # hexagon of diameter 9 (61 cells), Pente 19x19
 YAVALATH9_65536 = Batch("yavalath9_n65536", YAVALATH, 9, 9, 65536)
 PENTE19_65536 = Batch("pente19x19_n65536", PENTE, 19, 19, 65536)
-# and the movement games (step and hop mechanics) on the 8x8 board
+# and the movement games: step and hop on the 8x8 board, slide and hop on 9x9
 WOLF_SHEEP_65536 = Batch("wolf_sheep8x8_n65536", WOLF_SHEEP, 8, 8, 65536)
 DRAUGHTS_65536 = Batch("draughts8x8_n65536", DRAUGHTS, 8, 8, 65536)
-MORE_GAMES = (YAVALATH9_65536, PENTE19_65536, WOLF_SHEEP_65536, DRAUGHTS_65536)
+HASAMI_SHOGI_65536 = Batch("hasami_shogi9x9_n65536", HASAMI_SHOGI, 9, 9, 65536)
+MORE_GAMES = (YAVALATH9_65536, PENTE19_65536, WOLF_SHEEP_65536, DRAUGHTS_65536, HASAMI_SHOGI_65536)
 
 # large boards: Hex 19x19 and Gomoku 19x19, 524288 envs each (1,048,576
 # envs, 378.5 MB of int8 boards)

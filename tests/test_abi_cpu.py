@@ -47,7 +47,7 @@ def test_game_create_and_info():
     cases = {(1, 3, 3): (9, 9, 9), (2, 6, 7): (42, 42, 42), (3, 11, 11): (121, 121, 121),
              (4, 8, 8): (64, 65, 121), (5, 15, 15): (225, 225, 225), (3, 1, 1): (1, 1, 1),
              (3, 19, 19): (361, 361, 361), (5, 5, 5): (25, 25, 25), (8, 8, 8): (64, 4096, 56),
-             (9, 8, 8): (64, 4096, 200)}
+             (9, 8, 8): (64, 4096, 200), (10, 9, 9): (81, 6561, 200)}
     for (k, r, c), exp in cases.items():
         rc, h = _create(k, r, c)
         assert rc == 0
@@ -65,7 +65,7 @@ def test_game_create_and_info():
 
 def test_unsupported_and_invalid_descs():
     for k, r, c in [(2, 7, 6), (1, 4, 4), (3, 20, 20), (3, 5, 6), (5, 4, 4), (5, 20, 20), (4, 6, 6),
-                    (9, 3, 3), (0, 3, 3), (8, 9, 9), (9, 10, 10), (8, 8, 7), (10, 8, 8)]:
+                    (9, 3, 3), (0, 3, 3), (8, 9, 9), (9, 10, 10), (8, 8, 7), (10, 8, 8), (11, 9, 9)]:
         assert _create(k, r, c)[0] == ludax.E_UNSUPPORTED, (k, r, c)
     for k, r, c, m in [(1, 0, 3, 0), (1, 3, -1, 0), (1, 3, 3, -1), (1, 3, 3, 40000)]:
         assert _create(k, r, c, m)[0] == ludax.E_INVALID

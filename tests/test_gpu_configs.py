@@ -85,10 +85,10 @@ def _sampled_check(b, g, grew, gstats, seed, base, samples=1024):
     rew, _, _ = ref.playout(og, s, seed, 0, game_id=base + idx, threads=16)
     assert_same_state(s, g.subset(idx))
     assert np.array_equal(rew, grew[idx])
-    # every game ended; only Draughts (no natural end) is ever cut at max_plies
+    # every game ended; only the unbounded Draughts and Dai Hasami Shogi are ever cut at max_plies
     cut = g.status == ref.TRUNCATED
     assert ((g.status == ref.TERMINAL) | cut).all()
-    assert (g.ply[cut] == og.info()[2]).all() and (b.kind == ref.DRAUGHTS or not cut.any())
+    assert (g.ply[cut] == og.info()[2]).all() and (b.kind in (ref.DRAUGHTS, ref.HASAMI_SHOGI) or not cut.any())
     assert gstats[0] == g.ply.astype(np.int64).sum()
     assert gstats[1] + gstats[2] + gstats[3] == b.n - int(cut.sum())
 
@@ -96,7 +96,7 @@ def _sampled_check(b, g, grew, gstats, seed, base, samples=1024):
 @pytest.mark.parametrize("b", list(W.LARGE_BATCHES) + list(W.MORE_GAMES), ids=lambda b: b.name)
 def test_large_and_more_games_sampled(b):
     """The 19x19 batches of 524288 envs, and the Yavalath, Pente, Wolf and
-    Sheep and Draughts batches of 65536 envs."""
+    Sheep, Draughts and Dai Hasami Shogi batches of 65536 envs."""
     seed, base = 3, W.game_id_base(2, b)
     g, grew, gstats = _gpu_batch(b, seed, base)
     _sampled_check(b, g, grew, gstats, seed, base)

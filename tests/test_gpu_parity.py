@@ -30,10 +30,11 @@ GAMES = [
     (ref.PENTE, 7, 7),
     (ref.WOLF_SHEEP, 8, 8),
     (ref.DRAUGHTS, 8, 8),
+    (ref.HASAMI_SHOGI, 9, 9),
 ]
 IDS = ["ttt", "c4", "hex11", "reversi", "gomoku15", "hex19", "gomoku19", "yavalath9", "yavalath5", "pente19",
-       "pente7", "wolf_sheep", "draughts"]
-MOVES = [GAMES[-2], GAMES[-1]]
+       "pente7", "wolf_sheep", "draughts", "hasami_shogi"]
+MOVES = GAMES[-3:]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -300,8 +301,8 @@ def test_step_blocks_without_running_env(g):
     assert_same_state(s, from_device(d))
 
 
-@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7], GAMES[9], GAMES[12]],
-                         ids=["hex11", "reversi", "gomoku15", "yavalath9", "pente19", "draughts"])
+@pytest.mark.parametrize("g", [GAMES[2], GAMES[3], GAMES[4], GAMES[7], GAMES[9], GAMES[12], GAMES[13]],
+                         ids=["hex11", "reversi", "gomoku15", "yavalath9", "pente19", "draughts", "hasami_shogi"])
 def test_policy_step_sequences(g):
     """ludax_policy_step ply by ply against the oracle's draw + step, with
     random logits: every action equals the oracle's, except where the
@@ -355,7 +356,7 @@ def test_policy_step_sequences(g):
     assert close_calls <= 2
 
 
-@pytest.mark.parametrize("g", MOVES, ids=["wolf_sheep", "draughts"])
+@pytest.mark.parametrize("g", MOVES, ids=["wolf_sheep", "draughts", "hasami_shogi"])
 def test_moves_deep_positions(g):
     """Movement games from positions deep into the game (Draughts: kings,
     pending extra turns): mask, stepped plies with next masks, then the
@@ -363,7 +364,7 @@ def test_moves_deep_positions(g):
     og, dg = pair(*g)
     rng = np.random.default_rng(61)
     n = 300
-    s = random_states(og, n, 150 if g[0] == ref.DRAUGHTS else 50, rng)
+    s = random_states(og, n, 50 if g[0] == ref.WOLF_SHEEP else 150, rng)
     if g[0] == ref.DRAUGHTS:
         assert (s.board >= 5).any() and ((s.passes > 0) & (s.status == ref.RUNNING)).any()
     d = to_device(dg, s)
