@@ -49,10 +49,16 @@ __host__ __device__ __forceinline__ int tpos(int c)
 __host__ __device__ __forceinline__ uint32_t field9(u128 x, int pos) { return (uint32_t)(x >> pos) & 0x1FFu; }
 __host__ __device__ __forceinline__ int high_bit(uint32_t x) { return 31 - __builtin_clz(x); } // x != 0
 __host__ __device__ __forceinline__ int low_bit(uint32_t x) { return __builtin_ctz(x); }        // x != 0
+// lowest set bit of a nonzero board (below bit 96), without a branch: the
+// lowest nonzero 32-bit word picked by two selects
+__host__ __device__ __forceinline__ uint32_t first_set(uint32_t w) { return (uint32_t)__builtin_ffs((int)w) - 1u; }
 __host__ __device__ __forceinline__ int low_bit128(u128 x)
 {
-    const uint64_t lo = (uint64_t)x;
-    return lo ? __builtin_ctzll(lo) : 64 + __builtin_ctzll((uint64_t)(x >> 64));
+    const uint32_t w0 = (uint32_t)x, w1 = (uint32_t)(x >> 32), w2 = (uint32_t)(x >> 64);
+    uint32_t r = first_set(w2) + 64u;
+    r = w1 ? first_set(w1) + 32u : r;
+    r = w0 ? first_set(w0) : r;
+    return (int)r;
 }
 
 // Moves of the piece on (r, c) given the occupancy of its row (bit =
@@ -260,6 +266,43 @@ __device__ __forceinline__ BB<3> from_u128(u128 x)
     return b;
 }
 
+// Move count of `me` that also leaves, for the select below, every piece's
+// (source << 24 | move count << 16 | packed moves) in the lane's column of
+// an LDS array (entry i at cache[i * BLOCK], conflict-free across the wave).  A player
+// never has more than its 18 start pieces; on a hand-edited board with
+// more, pieces past the 18th are counted but not cached, and the select
+// then stays inside the cache (a legal move, not necessarily the k-th).
+constexpr int SHOGI_MAX_PIECES = 18;
+
+__device__ __forceinline__ int count_cached(const Shogi &g, int me, uint32_t *cache)
+{
+    int n = 0, i = 0;
+    for (u128 x = me == 1 ? g.p1 : g.p2; x; x &= x - 1, ++i) {
+        const int s = hs::low_bit128(x);
+        const uint32_t pm = g.moves_of(s);
+        const int m = hs::n_moves(pm);
+        if (i < SHOGI_MAX_PIECES) cache[i * BLOCK] = ((uint32_t)s << 24) | ((uint32_t)m << 16) | pm;
+        n += m;
+    }
+    return n;
+}
+
+// the k-th legal move from the cache of the last count_cached (n > 0):
+// the piece whose moves hold it, then its destination
+__device__ __forceinline__ void select_cached(const uint32_t *cache, int k, int &src, int &dst)
+{
+    uint32_t v = cache[0];
+    int i = 0;
+#pragma unroll 1
+    while ((int)((v >> 16) & 0xFFu) <= k && i + 1 < SHOGI_MAX_PIECES) {
+        k -= (int)((v >> 16) & 0xFFu);
+        v = cache[++i * BLOCK];
+    }
+    const int m = (int)((v >> 16) & 0xFFu);
+    src = (int)(v >> 24);
+    dst = hs::nth_dst(v & 0xFFFFu, src, k < m ? k : 0);
+}
+
 // One lane's row of move summaries (per cell: the packed moves of the
 // mover's piece there, 0 elsewhere), for the mask writer.
 __device__ __forceinline__ void shogi_summary(const Shogi &g, int me, bool running, uint16_t *row)
@@ -319,10 +362,11 @@ __device__ __forceinline__ uint32_t ply_word(uint64_t id, int ply, uint32_t key0
 }
 
 // After the mover's ply: the end rules (five, then a next player without a
-// legal move) given apply's outcome; nl = the next player's move count.
-__device__ __forceinline__ int shogi_outcome(const Shogi &g, int me, int five, int &nl)
+// legal move) given apply's outcome; nl = the next player's move count,
+// whose moves are left in the cache.
+__device__ __forceinline__ int shogi_outcome(const Shogi &g, int me, int five, int &nl, uint32_t *cache)
 {
-    nl = g.count(3 - me);
+    nl = count_cached(g, 3 - me, cache);
     return five >= 0 ? five : (nl == 0 ? me : -1);
 }
 
@@ -380,9 +424,11 @@ __global__ __launch_bounds__(BLOCK) void k_sh_step(DevState st, int64_t n, int m
 {
     __shared__ __align__(16) int8_t lds[BLOCK * 81 + STAGE_SLACK];
     __shared__ uint16_t summ[BLOCK * 81];
+    __shared__ uint32_t cache_all[SHOGI_MAX_PIECES * BLOCK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     const int t = threadIdx.x;
+    uint32_t *cache = cache_all + t;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
     const int64_t ec = valid ? e : e0;
@@ -423,11 +469,11 @@ __global__ __launch_bounds__(BLOCK) void k_sh_step(DevState st, int64_t n, int m
             }
             legal = g.legal(me, src, dst);
         } else {
-            const int nl = g.count(me);
+            const int nl = count_cached(g, me, cache);
             legal = nl > 0;
             const uint32_t w = ply_word((uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec), ply, key0, key1);
             if constexpr (MODE == 1) {
-                if (legal) g.select(me, (int)__umulhi(w, (uint32_t)nl), src, dst);
+                if (legal) select_cached(cache, (int)__umulhi(w, (uint32_t)nl), src, dst);
             } else if (legal) {
                 const float *lg = logits + ec * hs::A;
                 const u128 own = me == 1 ? g.p1 : g.p2;
@@ -470,7 +516,7 @@ __global__ __launch_bounds__(BLOCK) void k_sh_step(DevState st, int64_t n, int m
             ply += 1;
             last = src * 81 + dst;
             int nl;
-            const int outcome = shogi_outcome(g, me, five, nl);
+            const int outcome = shogi_outcome(g, me, five, nl, cache);
             if (outcome >= 0) {
                 status = TERMINAL;
                 winner = outcome;
@@ -514,10 +560,12 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
                                                       uint8_t *__restrict__ terminal)
 {
     __shared__ __align__(16) int8_t lds[BLOCK * 81 + STAGE_SLACK];
+    __shared__ uint32_t cache_all[SHOGI_MAX_PIECES * BLOCK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     stage_in<81>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
+    uint32_t *cache = cache_all + t;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
     const int64_t ec = valid ? e : e0;
@@ -530,7 +578,7 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
     const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
     const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
     const bool was_running = valid && status == RUNNING;
-    int nl = was_running ? g.count(me) : 0;
+    int nl = was_running ? count_cached(g, me, cache) : 0;
     uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
     if (was_running) {
         const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
@@ -555,7 +603,7 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
             break;
         }
         int src, dst;
-        g.select(me, (int)__umulhi(w0, (uint32_t)nl), src, dst);
+        select_cached(cache, (int)__umulhi(w0, (uint32_t)nl), src, dst);
         w0 = w1;
         w1 = w2;
         w2 = w3;
@@ -563,7 +611,7 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
         passes = 0;
         ply += 1;
         last = src * 81 + dst;
-        const int outcome = shogi_outcome(g, me, five, nl);
+        const int outcome = shogi_outcome(g, me, five, nl, cache);
         if (outcome >= 0) {
             status = TERMINAL;
             winner = outcome;
