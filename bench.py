@@ -370,6 +370,42 @@ def _more_games_section(seed: int, reps: int):
         v = st.cpu().tolist()
         out[b.name] = {"playout_kernel_ms": ms, "env_steps_per_s": v[0] / reps / (ms / 1e3),
                        "mean_plies": v[0] / reps / b.n, "p1_wins": v[1], "p2_wins": v[2], "draws": v[3]}
+    # the unbounded movement games: a few games run to the 200-ply cap, so a
+    # plain batch waits for them; the persistent batch (ludax_mixed_*, one
+    # kind) refills a lane as soon as its game ends
+    for b in (W.DRAUGHTS_65536, W.HASAMI_SHOGI_65536):
+        n_games, slots = 4 * b.n, b.n
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        s = ludax.State(g, n_games)
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        m = ludax.Mixed([g])
+        m.slots = [slots]
+        res = ludax.MixedResult(n_games, 1)
+        mst = torch.zeros((1, 4), dtype=torch.int64, device="cuda")
+        ludax.init(g, s)
+        ludax.playout(g, s, seed, 0, stats=None)
+        m.playout(seed, 0, n_games, out=res, stats=None)
+        torch.cuda.synchronize()
+        p_ms, q_ms = [], []
+        for k in range(reps):
+            base = (k + 1) * n_games
+            ludax.init(g, s)
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            ludax.playout(g, s, seed, base, stats=st)
+            e1.record()
+            m.playout(seed, base, n_games, out=res, stats=mst)
+            e2.record()
+            p_ms.append((e0, e1))
+            q_ms.append((e1, e2))
+        torch.cuda.synchronize()
+        pm = sum(a.elapsed_time(c) for a, c in p_ms) / reps
+        qm = sum(a.elapsed_time(c) for a, c in q_ms) / reps
+        steps = st[0].item() / reps
+        assert mst[0, 0].item() == st[0].item()  # the same games, the same plies
+        out[b.name.replace(f"_n{b.n}", f"_games{n_games}")] = {
+            "plain_ms": pm, "plain_env_steps_per_s": steps / (pm / 1e3),
+            "persistent_slots": slots, "persistent_ms": qm, "persistent_env_steps_per_s": steps / (qm / 1e3)}
     return out
 
 

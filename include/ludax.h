@@ -272,8 +272,7 @@ int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t 
  * ------------------------------------------------------------------------ */
 typedef struct ludax_mixed ludax_mixed;
 
-/* 1 <= n_kinds <= 8 game handles (they must outlive the mixed handle);
- * the movement games have no mixed batch (LUDAX_E_UNSUPPORTED).
+/* 1 <= n_kinds <= 8 game handles (they must outlive the mixed handle).
  * Creates the internal streams and events; the default plan gives every
  * kind 65536 slots.  A mixed handle serves one host thread at a time. */
 int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mixed **out);

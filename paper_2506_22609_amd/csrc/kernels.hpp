@@ -18,7 +18,8 @@
 //              of the wave has ended; final board written back through LDS
 //   k_playout_fill  the same result for Hex, Tic-Tac-Toe and Connect Four by
 //              fill-then-resolve (random fill, then a binary search of the end)
-//   k_persist_ply / k_persist_fill  the mixed persistent batch
+//   k_persist_ply / k_persist_fill  the mixed persistent batch (and
+//              k_persist_lane for the movement games)
 //   k_stats    step and outcome counters (a difference of two reductions)
 #pragma once
 
@@ -847,6 +848,73 @@ __global__ __launch_bounds__(BLOCK) void k_persist_ply(MixedArgs a)
                 a.winner[j] = (int8_t)(status == TERMINAL ? winner : -1);
                 a.plies[j] = (int16_t)ply;
                 a.last[j] = (int16_t)last;
+                i = -1;
+            }
+        }
+    }
+}
+
+// The same schedule for the movement games, over a lane adapter L:
+// L::Shared is the block's LDS the adapter needs, bind(shared, lane) sets
+// it up, start() begins a game at the start position, step(w, max_plies)
+// plays one ply with Philox word w and returns whether the game goes on,
+// and ply / last / status / winner report it.  Every ply is one wave step,
+// so the Philox blocks stay aligned exactly as in k_persist_ply.
+template <class L>
+__global__ __launch_bounds__(BLOCK) void k_persist_lane(MixedArgs a)
+{
+    __shared__ typename L::Shared shared;
+    const int t = threadIdx.x;
+    const uint64_t below = (1ull << t) - 1ull;
+    L lane;
+    lane.bind(shared, t);
+    int64_t i = -1; // game of this kind played by the lane, -1 = idle
+    uint32_t id_lo = 0u, id_hi = 0u, w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
+    int64_t pool = 0, pool_end = 0; // wave-uniform: unassigned games [pool, pool_end)
+    bool exhausted = false;
+    for (int s = 0;; ++s) {
+        if ((s & 3) == 0) {
+            uint64_t need = __ballot(i < 0);
+            while (need != 0ull && !exhausted) {
+                if (pool == pool_end) {
+                    pool = next_chunk(a.counter) * BLOCK;
+                    pool_end = pool + BLOCK < a.count ? pool + BLOCK : a.count;
+                    if (pool >= a.count) {
+                        exhausted = true;
+                        break;
+                    }
+                }
+                const int take = (int)(pool_end - pool) < __popcll(need) ? (int)(pool_end - pool) : __popcll(need);
+                const int rank = __popcll(need & below);
+                if (((need >> t) & 1ull) && rank < take) {
+                    i = pool + rank;
+                    const uint64_t id = (uint64_t)(a.id_base + a.j0 + i * a.stride);
+                    id_lo = (uint32_t)id;
+                    id_hi = (uint32_t)(id >> 32);
+                    lane.start();
+                }
+                pool += take;
+                need = __ballot(i < 0);
+            }
+            if (__ballot(i >= 0) == 0ull) break;
+            if (i >= 0) {
+                const Philox4 f = philox4x32_10((uint32_t)lane.ply >> 2, id_lo, id_hi, 0u, a.key0, a.key1);
+                w0 = f.v[0];
+                w1 = f.v[1];
+                w2 = f.v[2];
+                w3 = f.v[3];
+            }
+        }
+        if (i >= 0) {
+            const bool going = lane.step(w0, a.max_plies);
+            w0 = w1;
+            w1 = w2;
+            w2 = w3;
+            if (!going) {
+                const int64_t j = a.j0 + i * a.stride;
+                a.winner[j] = (int8_t)(lane.status == TERMINAL ? lane.winner : -1);
+                a.plies[j] = (int16_t)lane.ply;
+                a.last[j] = (int16_t)lane.last;
                 i = -1;
             }
         }

@@ -570,8 +570,35 @@ __global__ __launch_bounds__(BLOCK) void k_mv_playout(DevState st, int64_t n, in
     terminal[e] = 1;
 }
 
+// Lane adapter of the mixed persistent batch (k_persist_lane).
+template <class G>
+struct DiagLane {
+    struct Shared {
+        int unused;
+    };
+    G g;
+    MoveSets cur;
+    int me, cont, ply, last, status, winner;
+    __device__ void bind(Shared &, int) {}
+    __device__ void start()
+    {
+        g.start();
+        me = 1;
+        cont = 0;
+        ply = 0;
+        last = -1;
+        status = RUNNING;
+        winner = -1;
+        cur = g.moves(1, 0);
+    }
+    __device__ bool step(uint32_t w, int max_plies)
+    {
+        return move_ply(g, cur, me, cont, ply, last, status, winner, w, max_plies);
+    }
+};
+
 // ---------------------------------------------------------------------------
-// host launchers (no mixed persistent batch for the movement games)
+// host launchers
 // ---------------------------------------------------------------------------
 template <class G>
 struct MoveLaunch {
@@ -622,10 +649,16 @@ struct MoveLaunch {
         if (stats != nullptr) return launch_stats(st, n, +1, stats, s);
         return hipSuccess;
     }
+    static hipError_t persist(const MixedArgs &a, int slots, hipStream_t s)
+    {
+        hipLaunchKernelGGL(k_persist_lane<DiagLane<G>>, dim3((unsigned)((slots + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                           s, a);
+        return hipGetLastError();
+    }
     static constexpr GameOps ops()
     {
         return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step,
-                       &playout, nullptr};
+                       &playout, &persist};
     }
 };
 

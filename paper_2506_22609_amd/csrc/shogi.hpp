@@ -370,6 +370,56 @@ __device__ __forceinline__ int shogi_outcome(const Shogi &g, int me, int five, i
     return five >= 0 ? five : (nl == 0 ? me : -1);
 }
 
+// One ply of a running game with Philox word w, from the move cache of
+// the last count (nl moves); returns whether the game goes on.  Also the
+// lane adapter of the mixed persistent batch (k_persist_lane).
+struct ShogiLane {
+    struct Shared {
+        uint32_t cache[SHOGI_MAX_PIECES * BLOCK];
+    };
+    Shogi g;
+    uint32_t *cache;
+    int me, passes, ply, last, status, winner, nl;
+    __device__ void bind(Shared &sh, int t) { cache = sh.cache + t; }
+    __device__ void start()
+    {
+        g.start();
+        me = 1;
+        passes = 0;
+        ply = 0;
+        last = -1;
+        status = RUNNING;
+        winner = -1;
+        nl = count_cached(g, 1, cache);
+    }
+    __device__ bool step(uint32_t w, int max_plies)
+    {
+        if (nl == 0) { // only on a hand-edited state
+            status = ILLEGAL;
+            return false;
+        }
+        int src, dst;
+        select_cached(cache, (int)__umulhi(w, (uint32_t)nl), src, dst);
+        const int five = g.apply(me, src, dst);
+        passes = 0;
+        ply += 1;
+        last = src * 81 + dst;
+        const int outcome = shogi_outcome(g, me, five, nl, cache);
+        if (outcome >= 0) {
+            status = TERMINAL;
+            winner = outcome;
+            return false;
+        }
+        me = 3 - me;
+        if (ply >= max_plies) {
+            status = TRUNCATED;
+            winner = -1;
+            return false;
+        }
+        return true;
+    }
+};
+
 // a1
 __global__ __launch_bounds__(BLOCK) void k_sh_init(DevState st, int64_t n)
 {
@@ -560,29 +610,33 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
                                                       uint8_t *__restrict__ terminal)
 {
     __shared__ __align__(16) int8_t lds[BLOCK * 81 + STAGE_SLACK];
-    __shared__ uint32_t cache_all[SHOGI_MAX_PIECES * BLOCK];
+    __shared__ ShogiLane::Shared shared;
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     stage_in<81>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
-    uint32_t *cache = cache_all + t;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
     const int64_t ec = valid ? e : e0;
     BB<3> c1, c2;
     read_board<81, 3>(lds + t * 81, c1, c2);
-    Shogi g;
-    g.set(to_u128(c1), to_u128(c2));
-    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
-    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    ShogiLane L;
+    L.bind(shared, t);
+    L.g.set(to_u128(c1), to_u128(c2));
+    L.me = st.to_move[ec];
+    L.status = valid ? (int)st.status[ec] : ILLEGAL;
+    L.winner = st.winner[ec];
+    L.passes = st.passes[ec];
+    L.ply = st.ply[ec];
+    L.last = st.last_action[ec];
     const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
     const uint32_t id_lo = (uint32_t)id, id_hi = (uint32_t)(id >> 32);
-    const bool was_running = valid && status == RUNNING;
-    int nl = was_running ? count_cached(g, me, cache) : 0;
+    const bool was_running = valid && L.status == RUNNING;
+    L.nl = was_running ? count_cached(L.g, L.me, L.cache) : 0;
     uint32_t w0 = 0u, w1 = 0u, w2 = 0u, w3 = 0u;
     if (was_running) {
-        const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
-        const int r = ply & 3;
+        const Philox4 f = philox4x32_10((uint32_t)L.ply >> 2, id_lo, id_hi, 0u, key0, key1);
+        const int r = L.ply & 3;
         w0 = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
         w1 = r == 0 ? f.v[1] : (r == 1 ? f.v[2] : f.v[3]);
         w2 = r == 0 ? f.v[2] : f.v[3];
@@ -590,50 +644,28 @@ __global__ __launch_bounds__(BLOCK) void k_sh_playout(DevState st, int64_t n, in
     }
     bool running = was_running, first = true;
     while (running) {
-        if ((ply & 3) == 0 && !first) {
-            const Philox4 f = philox4x32_10((uint32_t)ply >> 2, id_lo, id_hi, 0u, key0, key1);
+        if ((L.ply & 3) == 0 && !first) {
+            const Philox4 f = philox4x32_10((uint32_t)L.ply >> 2, id_lo, id_hi, 0u, key0, key1);
             w0 = f.v[0];
             w1 = f.v[1];
             w2 = f.v[2];
             w3 = f.v[3];
         }
         first = false;
-        if (nl == 0) { // only on a hand-edited state
-            status = ILLEGAL;
-            break;
-        }
-        int src, dst;
-        select_cached(cache, (int)__umulhi(w0, (uint32_t)nl), src, dst);
+        running = L.step(w0, max_plies);
         w0 = w1;
         w1 = w2;
         w2 = w3;
-        const int five = g.apply(me, src, dst);
-        passes = 0;
-        ply += 1;
-        last = src * 81 + dst;
-        const int outcome = shogi_outcome(g, me, five, nl, cache);
-        if (outcome >= 0) {
-            status = TERMINAL;
-            winner = outcome;
-            running = false;
-        } else {
-            me = 3 - me;
-            if (ply >= max_plies) {
-                status = TRUNCATED;
-                winner = -1;
-                running = false;
-            }
-        }
     }
-    const int r1 = was_running && status == TERMINAL ? (winner == 1 ? 1 : -1) : 0;
+    const int r1 = was_running && L.status == TERMINAL ? (L.winner == 1 ? 1 : -1) : 0;
     if (valid) {
-        write_board<81, 3>(lds + t * 81, from_u128(g.p1), from_u128(g.p2));
-        st.to_move[e] = (int8_t)me;
-        st.status[e] = (int8_t)status;
-        st.winner[e] = (int8_t)winner;
-        st.passes[e] = (int8_t)passes;
-        st.ply[e] = (int16_t)ply;
-        st.last_action[e] = (int16_t)last;
+        write_board<81, 3>(lds + t * 81, from_u128(L.g.p1), from_u128(L.g.p2));
+        st.to_move[e] = (int8_t)L.me;
+        st.status[e] = (int8_t)L.status;
+        st.winner[e] = (int8_t)L.winner;
+        st.passes[e] = (int8_t)L.passes;
+        st.ply[e] = (int16_t)L.ply;
+        st.last_action[e] = (int16_t)L.last;
         reward[2 * e] = (int8_t)r1;
         reward[2 * e + 1] = (int8_t)-r1;
         terminal[e] = 1;
@@ -689,10 +721,16 @@ struct ShogiLaunch {
         if (stats != nullptr) return launch_stats(st, n, +1, stats, s);
         return hipSuccess;
     }
+    static hipError_t persist(const MixedArgs &a, int slots, hipStream_t s)
+    {
+        hipLaunchKernelGGL(k_persist_lane<ShogiLane>, dim3((unsigned)((slots + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s,
+                           a);
+        return hipGetLastError();
+    }
     static constexpr GameOps ops()
     {
         return GameOps{Shogi::KIND, Shogi::H, Shogi::W, Shogi::CELLS, Shogi::A, &init, &mask, &step, &random_step,
-                       &policy_step, &playout, nullptr};
+                       &policy_step, &playout, &persist};
     }
 };
 

@@ -142,11 +142,6 @@ def test_mixed_argument_checks_need_no_gpu():
     assert L.ludax_mixed_set_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_get_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_playout(None, 1, 0, 10, 16, 16, 16, None, 16, None) == ludax.E_INVALID
-    # the movement games have no mixed persistent batch
-    rc, hd = _create(9, 8, 8)
-    both = (ctypes.c_void_p * 2)(h.value, hd.value)
-    assert L.ludax_mixed_create(both, 2, ctypes.byref(out)) == ludax.E_UNSUPPORTED
-    L.ludax_game_destroy(hd)
     L.ludax_game_destroy(h)
 
 

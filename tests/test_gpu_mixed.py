@@ -168,3 +168,17 @@ def test_mixed_with_pente_matches_oracle():
     assert np.array_equal(out.plies.cpu().numpy(), p)
     assert np.array_equal(out.last_action.cpu().numpy(), l)
     assert np.array_equal(stats.cpu().numpy(), st)
+
+
+def test_mixed_with_movement_games_matches_oracle():
+    """Wolf and Sheep, English Draughts and Dai Hasami Shogi (Draughts and
+    Dai Hasami Shogi games cut at 200 plies report winner -1) beside Hex,
+    with few slots so that every lane plays several games."""
+    kinds = [(ref.DRAUGHTS, 8, 8), (ref.WOLF_SHEEP, 8, 8), (ref.HASAMI_SHOGI, 9, 9), (ref.HEX, 11, 11)]
+    out, stats, _ = run_mixed(kinds, 31, 9, 2201, [128, 64, 128, 64])
+    w, p, l, st = oracle_batch(kinds, 31, 9, 2201)
+    assert (w == -1).any()
+    assert np.array_equal(out.winner.cpu().numpy(), w)
+    assert np.array_equal(out.plies.cpu().numpy(), p)
+    assert np.array_equal(out.last_action.cpu().numpy(), l)
+    assert np.array_equal(stats.cpu().numpy(), st)
