@@ -189,13 +189,21 @@ class State:
         self.last_action = torch.empty(n, dtype=torch.int16, device=device)
 
     def _c(self) -> _State:
-        for f in self.FIELDS:
-            t = getattr(self, f)
+        # the checked C view is kept while the same field tensors, at the
+        # same addresses, are in place (every call passes it)
+        ts = [getattr(self, f) for f in self.FIELDS]
+        key = tuple(t.data_ptr() for t in ts)
+        hit = self.__dict__.get("_cview")
+        if hit is not None and hit[0] == key and all(a is b for a, b in zip(hit[1], ts)):
+            return hit[2]
+        for f, t in zip(self.FIELDS, ts):
             if not t.is_contiguous() or t.device.type != "cuda":
                 raise ValueError(f"state.{f} must be a contiguous device tensor")
-        if self.board.data_ptr() % 16:
+        if key[0] % 16:
             raise ValueError("state.board must be 16-byte aligned")
-        return _State(*[_ptr(getattr(self, f)) for f in self.FIELDS], None)
+        view = _State(*[ctypes.c_void_p(p) for p in key], None)
+        self._cview = (key, ts, view)
+        return view
 
     @classmethod
     def from_tensors(cls, game: Game, **fields) -> "State":
