@@ -271,6 +271,25 @@ __device__ __forceinline__ int select_bit(const BB<NW> &m, int k)
     return base + select_in_word(wsel, k - off);
 }
 
+// The same search returning the word index of the k-th set bit and that bit
+// within its word.
+template <int NW>
+__device__ __forceinline__ void select_bit_split(const BB<NW> &m, int k, int &word, uint32_t &bit)
+{
+    uint32_t wsel = m.w[0];
+    int wi = 0, off = 0, pre = __popc(m.w[0]);
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+        const bool ge = k >= pre;
+        wsel = ge ? m.w[i] : wsel;
+        wi = ge ? i : wi;
+        off = ge ? pre : off;
+        pre += __popc(m.w[i]);
+    }
+    word = wi;
+    bit = 1u << select_in_word(wsel, k - off);
+}
+
 // The legal action of a uniform draw: with n = popcount(m) set bits and a
 // 32-bit random word w, the k-th set bit for k = (w * n) >> 32.
 template <int NW>
