@@ -33,11 +33,11 @@ sys.path.insert(0, ROOT)
 # this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt).  Peak:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (the fp64
 # vector rate 78.6 TFLOP/s counts an FMA as two operations).
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 279, "hex11x11_n65536": 181}
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 279, "hex11x11_n65536": 179}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes of one Hex playout launch: FETCH_SIZE and WRITE_SIZE scaled by
 # a 256 MiB copy (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
-HEX_TRAFFIC_BYTES = 19.91e6
+HEX_TRAFFIC_BYTES = 19.93e6
 HBM_PEAK_GBS = 8000.0
 
 
