@@ -29,7 +29,9 @@ FLAGS = [
     # the SLP vectorizer has nothing to gain on this integer code and
     # crashes on some of the larger Gomoku step kernels
     "-fno-slp-vectorize",
-    "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}",
+    # bitwise | and & on booleans are deliberate: no short-circuit branches
+    # in lane-divergent code
+    "-Wall", "-Wno-unused-function", "-Wno-bitwise-instead-of-logical", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
 
