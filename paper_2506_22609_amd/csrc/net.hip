@@ -589,7 +589,11 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t *__restrict__
 // conv weight gradient: dW[o][i][t] = sum_{b,p} dZ[b][p][o] X[b][p + tap t][i]
 // and db[o] = sum dZ[b][p][o], per block partial sums.  M = 64 output
 // channels (4 tiles), N = (tap, input channel) columns, K = cells (padded to
-// 32 per board).  Four waves split the column tiles.
+// 32 per board).  Four waves split the column tiles.  A block walks its
+// boards one at a time: the next board's dZ and X are loaded into registers
+// while the current one is multiplied, then transposed into LDS (cell-major
+// rows per channel); the bias gradient is summed by wave 0 from the A
+// fragments it already holds.
 // part layout per block: [64 * CR * 9] (param order o, i, t) then [64] db.
 // ---------------------------------------------------------------------------
 template <int N, int CIN>
@@ -603,6 +607,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     constexpr int NCOL = 9 * CIN, NT = (NCOL + 15) / 16;      // column tiles
     constexpr int NTW = (NT + 3) / 4;                         // column tiles per wave
     constexpr int PART = C * CR * 9 + C;
+    // per-thread loads of one board: dZ interior cells x 8 channel groups of
+    // 8; X cells x 8 groups (64 channels) or cells (4 channels, 8 B each)
+    constexpr int DZ_ITEMS = PIX * 8, DZ_R = (DZ_ITEMS + 255) / 256;
+    constexpr int X_ITEMS = CIN == 4 ? PP : PP * 8, X_R = (X_ITEMS + 255) / 256;
     __shared__ __align__(16) uint16_t dzt[C * DS];
     __shared__ __align__(16) uint16_t xt[CIN * PPS];
 
@@ -613,7 +621,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int j = 0; j < NTW; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float dbias = 0.f;
+    float dsum[4] = {0.f, 0.f, 0.f, 0.f}; // wave 0: bias-gradient partial sums of channels mt*16 + row
     // this lane's B column in each of its tiles: (tap offset, channel)
     int col_off[NTW], col_ch[NTW];
 #pragma unroll
@@ -628,52 +636,88 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     for (int j = threadIdx.x; j < C * (PIXP - PIX); j += 256)
         dzt[(j / (PIXP - PIX)) * DS + PIX + j % (PIXP - PIX)] = 0;
 
-    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
-        __syncthreads();
+    uint4 dzr[DZ_R], xr4[X_R];
+    auto load_board = [&](int64_t b) {
         const uint16_t *db = dz + b * (int64_t)PP * C;
         const uint16_t *xb = x + b * (int64_t)PP * CIN;
-        for (int j = threadIdx.x; j < PIX * 8; j += 256) { // interior cells of dZ, 8 channels each
-            const int q = j >> 3, c0 = (j & 7) * 8;
-            const uint4 v = *reinterpret_cast<const uint4 *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C + c0);
-            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                dzt[(c0 + 2 * h) * DS + q] = (uint16_t)(wd[h] & 0xFFFFu);
-                dzt[(c0 + 2 * h + 1) * DS + q] = (uint16_t)(wd[h] >> 16);
+        for (int r = 0; r < DZ_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < DZ_ITEMS) {
+                const int q = j >> 3, c0 = (j & 7) * 8;
+                dzr[r] = *reinterpret_cast<const uint4 *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C + c0);
             }
         }
-        if constexpr (CIN == 4) {
-            for (int q = threadIdx.x; q < PP; q += 256) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(xb + (int64_t)q * 4);
-                xt[0 * PPS + q] = (uint16_t)(v.x & 0xFFFFu);
-                xt[1 * PPS + q] = (uint16_t)(v.x >> 16);
-                xt[2 * PPS + q] = (uint16_t)(v.y & 0xFFFFu);
-                xt[3 * PPS + q] = (uint16_t)(v.y >> 16);
+#pragma unroll
+        for (int r = 0; r < X_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < X_ITEMS) {
+                if constexpr (CIN == 4) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(xb + (int64_t)j * 4);
+                    xr4[r] = uint4{v.x, v.y, 0u, 0u};
+                } else {
+                    xr4[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)(j >> 3) * C + (j & 7) * 8);
+                }
             }
-        } else {
-            for (int j = threadIdx.x; j < PP * 8; j += 256) {
+        }
+    };
+    if ((int64_t)blockIdx.x < n) load_board(blockIdx.x);
+
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads(); // the previous board's fragments are read
+#pragma unroll
+        for (int r = 0; r < DZ_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < DZ_ITEMS) {
                 const int q = j >> 3, c0 = (j & 7) * 8;
-                const uint4 v = *reinterpret_cast<const uint4 *>(xb + (int64_t)q * C + c0);
-                const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+                const uint32_t wd[4] = {dzr[r].x, dzr[r].y, dzr[r].z, dzr[r].w};
 #pragma unroll
                 for (int h = 0; h < 4; ++h) {
-                    xt[(c0 + 2 * h) * PPS + q] = (uint16_t)(wd[h] & 0xFFFFu);
-                    xt[(c0 + 2 * h + 1) * PPS + q] = (uint16_t)(wd[h] >> 16);
+                    dzt[(c0 + 2 * h) * DS + q] = (uint16_t)(wd[h] & 0xFFFFu);
+                    dzt[(c0 + 2 * h + 1) * DS + q] = (uint16_t)(wd[h] >> 16);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < X_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < X_ITEMS) {
+                if constexpr (CIN == 4) {
+                    xt[0 * PPS + j] = (uint16_t)(xr4[r].x & 0xFFFFu);
+                    xt[1 * PPS + j] = (uint16_t)(xr4[r].x >> 16);
+                    xt[2 * PPS + j] = (uint16_t)(xr4[r].y & 0xFFFFu);
+                    xt[3 * PPS + j] = (uint16_t)(xr4[r].y >> 16);
+                } else {
+                    const int q = j >> 3, c0 = (j & 7) * 8;
+                    const uint32_t wd[4] = {xr4[r].x, xr4[r].y, xr4[r].z, xr4[r].w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h) {
+                        xt[(c0 + 2 * h) * PPS + q] = (uint16_t)(wd[h] & 0xFFFFu);
+                        xt[(c0 + 2 * h + 1) * PPS + q] = (uint16_t)(wd[h] >> 16);
+                    }
                 }
             }
         }
         __syncthreads();
-        if (threadIdx.x < C) { // bias gradient: row sums of dZ^T
-            float s = 0.f;
-            for (int q = 0; q < PIX; ++q) s += bf2f(dzt[threadIdx.x * DS + q]);
-            dbias += s;
-        }
+        if (b + gridDim.x < n) load_board(b + gridDim.x); // in flight during the products
         for (int ks = 0; ks < PIXP / 32; ++ks) {
             const int p0 = ks * 32 + quad * 8; // this lane's 8 consecutive cells
+            uint4 araw[4];
             bf16x8 afr[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
-                afr[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(dzt + (mt * 16 + row) * DS + p0));
+            for (int mt = 0; mt < 4; ++mt) {
+                araw[mt] = *reinterpret_cast<const uint4 *>(dzt + (mt * 16 + row) * DS + p0);
+                afr[mt] = as_bf16x8(araw[mt]);
+            }
+            if (wave == 0) {
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const uint32_t wd[4] = {araw[mt].x, araw[mt].y, araw[mt].z, araw[mt].w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        dsum[mt] += __uint_as_float(wd[h] << 16) + __uint_as_float(wd[h] & 0xFFFF0000u);
+                }
+            }
             int cq[8]; // top-left tap of each of the 8 cells in the padded frame
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -683,10 +727,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
 #pragma unroll
             for (int j = 0; j < NTW; ++j) {
                 if (wave * NTW + j >= NT) break;
-                const uint16_t *xr = xt + col_ch[j] * PPS + col_off[j];
+                const uint16_t *xrow = xt + col_ch[j] * PPS + col_off[j];
                 uint32_t u[4];
 #pragma unroll
-                for (int h = 0; h < 4; ++h) u[h] = (uint32_t)xr[cq[2 * h]] | ((uint32_t)xr[cq[2 * h + 1]] << 16);
+                for (int h = 0; h < 4; ++h) u[h] = (uint32_t)xrow[cq[2 * h]] | ((uint32_t)xrow[cq[2 * h + 1]] << 16);
                 const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt)
@@ -709,7 +753,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
                 o[(co * CR + i) * 9 + t] = acc[mt][j][r];
             }
     }
-    if (threadIdx.x < C) o[C * CR * 9 + threadIdx.x] = dbias;
+    if (wave == 0) {
+        // the four quads of a row held different cells of the same channel
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            dsum[mt] += __shfl_xor(dsum[mt], 16, 64);
+            dsum[mt] += __shfl_xor(dsum[mt], 32, 64);
+        }
+        if (quad == 0) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) o[C * CR * 9 + mt * 16 + row] = dsum[mt];
+        }
+    }
 }
 
 // out[j] = sum over rows r < rows of part[r * stride + j], j < cols: a block
