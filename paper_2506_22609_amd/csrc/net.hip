@@ -767,6 +767,164 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     }
 }
 
+// The same product for the 64-channel layers with the B operand read as
+// whole fragments: both LDS frames use a row stride RS that is a multiple
+// of 8 cells (dZ^T holds interior cell (r, c) at r * RS + c, X^T padded cell
+// (r, c) at r * RS + c, zeros elsewhere), so K runs over dZ^T positions and
+// the tap (tr, tc) of position q is X^T position q + tr * RS + tc.  The 16
+// columns of a tile share one tap, so a lane's 8 B values are X^T positions
+// q0 + off .. + 7 of its channel: two aligned 16-byte reads and a funnel
+// shift by tc cells, instead of eight 2-byte gathers.  K grows from the
+// cells padded to 32 to N * RS padded to 32 (the extra positions are
+// zero in dZ^T).
+template <int N>
+__global__ __launch_bounds__(256) void k_conv_wgrad64(const uint16_t *__restrict__ dz, const uint16_t *__restrict__ x,
+                                                      int64_t n, float *__restrict__ part)
+{
+    constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
+    constexpr int RS = (NP + 7) / 8 * 8;                      // frame row stride
+    constexpr int KP = (N * RS + 31) / 32 * 32;               // dZ^T positions, whole k-steps
+    constexpr int DS = KP + 8;                                // dZ^T row stride
+    constexpr int XS = KP + 2 * RS + 16 + 8;                  // X^T row stride (reads reach KP + 2 RS + 10)
+    constexpr int NCOL = 9 * C, NT = NCOL / 16, NTW = NT / 4; // 36 column tiles, 9 per wave
+    constexpr int PART = C * C * 9 + C;
+    constexpr int DZ_ITEMS = PIX * 8, DZ_R = (DZ_ITEMS + 255) / 256;
+    constexpr int X_ITEMS = PP * 8, X_R = (X_ITEMS + 255) / 256;
+    __shared__ __align__(16) uint16_t dzt[C * DS];
+    __shared__ __align__(16) uint16_t xt[C * XS];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, quad = lane >> 4;
+    f32x4 acc[4][NTW];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) acc[mt][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dsum[4] = {0.f, 0.f, 0.f, 0.f}; // wave 0: bias-gradient partial sums of channels mt*16 + row
+    // every position that no board writes (frame padding, slack) stays zero
+    for (int j = threadIdx.x; j < C * DS / 8; j += 256) reinterpret_cast<uint4 *>(dzt)[j] = uint4{0u, 0u, 0u, 0u};
+    for (int j = threadIdx.x; j < C * XS / 8; j += 256) reinterpret_cast<uint4 *>(xt)[j] = uint4{0u, 0u, 0u, 0u};
+
+    uint4 dzr[DZ_R], xr4[X_R];
+    auto load_board = [&](int64_t b) {
+        const uint16_t *db = dz + b * (int64_t)PP * C;
+        const uint16_t *xb = x + b * (int64_t)PP * C;
+#pragma unroll
+        for (int r = 0; r < DZ_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < DZ_ITEMS) {
+                const int q = j >> 3, c0 = (j & 7) * 8;
+                dzr[r] = *reinterpret_cast<const uint4 *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C + c0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < X_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < X_ITEMS) xr4[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)(j >> 3) * C + (j & 7) * 8);
+        }
+    };
+    if ((int64_t)blockIdx.x < n) load_board(blockIdx.x);
+
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads(); // the zero fill, or the previous board's fragments, are done
+#pragma unroll
+        for (int r = 0; r < DZ_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < DZ_ITEMS) {
+                const int q = j >> 3, c0 = (j & 7) * 8;
+                const int pos = (q / N) * RS + q % N;
+                const uint32_t wd[4] = {dzr[r].x, dzr[r].y, dzr[r].z, dzr[r].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    dzt[(c0 + 2 * h) * DS + pos] = (uint16_t)(wd[h] & 0xFFFFu);
+                    dzt[(c0 + 2 * h + 1) * DS + pos] = (uint16_t)(wd[h] >> 16);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < X_R; ++r) {
+            const int j = threadIdx.x + 256 * r;
+            if (j < X_ITEMS) {
+                const int q = j >> 3, c0 = (j & 7) * 8;
+                const int pos = (q / NP) * RS + q % NP;
+                const uint32_t wd[4] = {xr4[r].x, xr4[r].y, xr4[r].z, xr4[r].w};
+#pragma unroll
+                for (int h = 0; h < 4; ++h) {
+                    xt[(c0 + 2 * h) * XS + pos] = (uint16_t)(wd[h] & 0xFFFFu);
+                    xt[(c0 + 2 * h + 1) * XS + pos] = (uint16_t)(wd[h] >> 16);
+                }
+            }
+        }
+        __syncthreads();
+        if (b + gridDim.x < n) load_board(b + gridDim.x); // in flight during the products
+        for (int ks = 0; ks < KP / 32; ++ks) {
+            const int q0 = ks * 32 + quad * 8; // this lane's 8 consecutive positions
+            uint4 araw[4];
+            bf16x8 afr[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                araw[mt] = *reinterpret_cast<const uint4 *>(dzt + (mt * 16 + row) * DS + q0);
+                afr[mt] = as_bf16x8(araw[mt]);
+            }
+            if (wave == 0) {
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const uint32_t wd[4] = {araw[mt].x, araw[mt].y, araw[mt].z, araw[mt].w};
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        dsum[mt] += __uint_as_float(wd[h] << 16) + __uint_as_float(wd[h] & 0xFFFF0000u);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < NTW; ++j) {
+                const int tile = wave * NTW + j;     // columns tile*16 .. +15: tap t, channels
+                const int t = tile >> 2;             // (tile & 3) * 16 .. +15
+                const int tr = t / 3, tc = t - 3 * tr;
+                const int base = ((tile & 3) * 16 + row) * XS + q0 + tr * RS; // 8-cell aligned
+                const uint4 lo = *reinterpret_cast<const uint4 *>(xt + base);
+                const uint4 hi = *reinterpret_cast<const uint4 *>(xt + base + 8);
+                const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                uint32_t u[4];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    // cells tc .. tc + 7 of the 16 read: dword d = cells tc + 2d, tc + 2d + 1
+                    const uint32_t a0 = tc >= 2 ? w[d + 1] : w[d];
+                    const uint32_t a1 = tc >= 2 ? w[d + 2] : w[d + 1];
+                    u[d] = __builtin_amdgcn_alignbyte(a1, a0, (tc & 1) * 2);
+                }
+                const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt)
+                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][j], 0, 0, 0);
+            }
+        }
+    }
+    float *o = part + (int64_t)blockIdx.x * PART;
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) {
+        const int col = (wave * NTW + j) * 16 + row;
+        const int t = col / C, i = col % C;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = mt * 16 + quad * 4 + r;
+                o[(co * C + i) * 9 + t] = acc[mt][j][r];
+            }
+    }
+    if (wave == 0) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            dsum[mt] += __shfl_xor(dsum[mt], 16, 64);
+            dsum[mt] += __shfl_xor(dsum[mt], 32, 64);
+        }
+        if (quad == 0) {
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) o[C * C * 9 + mt * 16 + row] = dsum[mt];
+        }
+    }
+}
+
 // out[j] = sum over rows r < rows of part[r * stride + j], j < cols: a block
 // takes 32 columns, its 8 waves' worth of row groups add up in LDS
 __global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part, int64_t rows, int stride, int cols,
@@ -949,7 +1107,14 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
                        HEAD_PART, grads + WP_OFF);
     constexpr int PART64 = C * C * 9 + C, PART4 = C * 27 + C;
     for (int l = 4; l >= 2; --l) {
-        hipLaunchKernelGGL((k_conv_wgrad<N, 64>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
+        // 19x19: aligned B fragments (K = 19 x 24 positions padded to 480
+        // against 361 cells padded to 384); 11x11: the 2-byte gathers win,
+        // since its K would grow by half (176 positions padded to 192
+        // against 121 cells padded to 128)
+        if constexpr (N == 19)
+            hipLaunchKernelGGL((k_conv_wgrad64<N>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
+        else
+            hipLaunchKernelGGL((k_conv_wgrad<N, 64>), dim3(wb), dim3(256), 0, s, ga, y[l - 1], n, part);
         hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
         hipLaunchKernelGGL((k_conv_lds<N, 1>), dim3(lb), dim3(LC::THREADS), 0, s, ga, packed + pb_off(l),
