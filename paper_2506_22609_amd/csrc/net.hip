@@ -607,9 +607,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     constexpr int NCOL = 9 * CIN, NT = (NCOL + 15) / 16;      // column tiles
     constexpr int NTW = (NT + 3) / 4;                         // column tiles per wave
     constexpr int PART = C * CR * 9 + C;
-    // per-thread loads of one board: dZ interior cells x 8 channel groups of
-    // 8; X cells x 8 groups (64 channels) or cells (4 channels, 8 B each)
-    constexpr int DZ_ITEMS = PIX * 8, DZ_R = (DZ_ITEMS + 255) / 256;
+    // per-thread loads of one board.  dZ: an item is (channel pair, group of
+    // 8 cells) -- the 32 lanes of a half-wave read one cell's 128 bytes --
+    // written as two 16-byte rows of dZ^T (cells past the board are its zero
+    // padding).  X: a (cell, 8 channels) item, 16 bytes (64 channels), or a
+    // cell, 8 bytes (4 channels), written as single cells of X^T.
+    constexpr int DZ_ITEMS = 32 * (PIXP / 8), DZ_R = (DZ_ITEMS + 255) / 256;
     constexpr int X_ITEMS = CIN == 4 ? PP : PP * 8, X_R = (X_ITEMS + 255) / 256;
     __shared__ __align__(16) uint16_t dzt[C * DS];
     __shared__ __align__(16) uint16_t xt[CIN * PPS];
@@ -632,20 +635,21 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
         col_off[j] = (t / 3) * NP + (t % 3);
         col_ch[j] = i;
     }
-    // zero the padded cells of dZ^T once (cells PIX .. PIXP-1)
-    for (int j = threadIdx.x; j < C * (PIXP - PIX); j += 256)
-        dzt[(j / (PIXP - PIX)) * DS + PIX + j % (PIXP - PIX)] = 0;
-
-    uint4 dzr[DZ_R], xr4[X_R];
+    uint32_t dzv[DZ_R][8]; // the next board: 8 cells of a channel pair per item
+    uint4 xv[X_R];
     auto load_board = [&](int64_t b) {
         const uint16_t *db = dz + b * (int64_t)PP * C;
         const uint16_t *xb = x + b * (int64_t)PP * CIN;
 #pragma unroll
         for (int r = 0; r < DZ_R; ++r) {
             const int j = threadIdx.x + 256 * r;
-            if (j < DZ_ITEMS) {
-                const int q = j >> 3, c0 = (j & 7) * 8;
-                dzr[r] = *reinterpret_cast<const uint4 *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C + c0);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int q = (j >> 5) * 8 + i; // cells past PIX are the zero padding of dZ^T
+                dzv[r][i] = j < DZ_ITEMS && q < PIX
+                                ? *reinterpret_cast<const uint32_t *>(db + (int64_t)((q / N + 1) * NP + q % N + 1) * C +
+                                                                      2 * (j & 31))
+                                : 0u;
             }
         }
 #pragma unroll
@@ -654,9 +658,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
             if (j < X_ITEMS) {
                 if constexpr (CIN == 4) {
                     const uint2 v = *reinterpret_cast<const uint2 *>(xb + (int64_t)j * 4);
-                    xr4[r] = uint4{v.x, v.y, 0u, 0u};
+                    xv[r] = uint4{v.x, v.y, 0u, 0u};
                 } else {
-                    xr4[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)(j >> 3) * C + (j & 7) * 8);
+                    xv[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)(j >> 3) * C + (j & 7) * 8);
                 }
             }
         }
@@ -669,13 +673,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
         for (int r = 0; r < DZ_R; ++r) {
             const int j = threadIdx.x + 256 * r;
             if (j < DZ_ITEMS) {
-                const int q = j >> 3, c0 = (j & 7) * 8;
-                const uint32_t wd[4] = {dzr[r].x, dzr[r].y, dzr[r].z, dzr[r].w};
+                // channel 2cp: the low halves of the 8 cells, channel 2cp+1: the high halves
+                uint32_t lo[4], hi[4];
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    dzt[(c0 + 2 * h) * DS + q] = (uint16_t)(wd[h] & 0xFFFFu);
-                    dzt[(c0 + 2 * h + 1) * DS + q] = (uint16_t)(wd[h] >> 16);
+                for (int d = 0; d < 4; ++d) {
+                    lo[d] = __builtin_amdgcn_perm(dzv[r][2 * d + 1], dzv[r][2 * d], 0x05040100u);
+                    hi[d] = __builtin_amdgcn_perm(dzv[r][2 * d + 1], dzv[r][2 * d], 0x07060302u);
                 }
+                const int cp = j & 31, q0 = (j >> 5) * 8;
+                *reinterpret_cast<uint4 *>(dzt + (2 * cp) * DS + q0) = uint4{lo[0], lo[1], lo[2], lo[3]};
+                *reinterpret_cast<uint4 *>(dzt + (2 * cp + 1) * DS + q0) = uint4{hi[0], hi[1], hi[2], hi[3]};
             }
         }
 #pragma unroll
@@ -683,13 +690,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
             const int j = threadIdx.x + 256 * r;
             if (j < X_ITEMS) {
                 if constexpr (CIN == 4) {
-                    xt[0 * PPS + j] = (uint16_t)(xr4[r].x & 0xFFFFu);
-                    xt[1 * PPS + j] = (uint16_t)(xr4[r].x >> 16);
-                    xt[2 * PPS + j] = (uint16_t)(xr4[r].y & 0xFFFFu);
-                    xt[3 * PPS + j] = (uint16_t)(xr4[r].y >> 16);
+                    xt[0 * PPS + j] = (uint16_t)(xv[r].x & 0xFFFFu);
+                    xt[1 * PPS + j] = (uint16_t)(xv[r].x >> 16);
+                    xt[2 * PPS + j] = (uint16_t)(xv[r].y & 0xFFFFu);
+                    xt[3 * PPS + j] = (uint16_t)(xv[r].y >> 16);
                 } else {
                     const int q = j >> 3, c0 = (j & 7) * 8;
-                    const uint32_t wd[4] = {xr4[r].x, xr4[r].y, xr4[r].z, xr4[r].w};
+                    const uint32_t wd[4] = {xv[r].x, xv[r].y, xv[r].z, xv[r].w};
 #pragma unroll
                     for (int h = 0; h < 4; ++h) {
                         xt[(c0 + 2 * h) * PPS + q] = (uint16_t)(wd[h] & 0xFFFFu);
