@@ -395,6 +395,147 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution with the weights resident: one block per CU keeps
+// all 64 x 576 weights in LDS for the whole launch (staged once, instead of
+// once per 4-board group) and walks its share of the BPB-board groups; a
+// group's activations are staged half of the input channels at a time, and
+// the next (group, half) is loaded into registers while the current one is
+// multiplied.  Same wave mapping, MODEs and epilogue as k_conv_lds.  Used
+// for the 19x19 forward, where it measured faster; at 11x11 one block per CU
+// keeps too few bytes in flight and the per-group kernel wins.
+// ---------------------------------------------------------------------------
+constexpr int RES_BLOCKS = 256; // one per CU
+
+template <int N, int MODE>
+__global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
+                                                                     const uint16_t *__restrict__ w,
+                                                                     const float *__restrict__ bias,
+                                                                     const uint16_t *__restrict__ mask,
+                                                                     uint16_t *__restrict__ out, int64_t n)
+{
+    using L = LdsConv<N>;
+    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB;
+    constexpr int NTW = L::NTW, THREADS = L::THREADS;
+    constexpr int WR = K2 + 8;                           // weight row stride (bf16)
+    constexpr int XITEMS = BPB * PP * 4;                 // 16-byte chunks of one (group, half)
+    constexpr int XR = (XITEMS + THREADS - 1) / THREADS; // per thread
+    __shared__ __align__(16) uint16_t wsr[C * WR];
+    __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
+
+    const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
+    const int slot = wave / NG, g = wave % NG;
+    const int row = lane & 15, quad = lane >> 4;
+    int cell_off[8]; // top-left tap of this lane's A row in each tile (padded cells)
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const int p = (g * 8 + mt) * 16 + row;
+        const int pc = p < PIX ? p : 0;
+        cell_off[mt] = (pc / N) * NP + (pc % N);
+    }
+    for (int j = threadIdx.x; j < C * (K2 / 8); j += THREADS) {
+        const int o = j / (K2 / 8), r = j % (K2 / 8);
+        *reinterpret_cast<uint4 *>(wsr + o * WR + r * 8) = *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + r * 8);
+    }
+
+    const int64_t groups = (n + BPB - 1) / BPB;
+    uint4 pre[XR];
+    auto load = [&](int64_t grp, int h) { // chunks (board, cell, 8 channels) of half h
+        // chunk j of a group is 16 bytes at element 8 j of its (board, cell) rows,
+        // 4 chunks per cell and half
+        const uint16_t *base = x + grp * BPB * (int64_t)PP * C + h * 32;
+        const int64_t left = (n - grp * BPB) * (int64_t)PP * 4; // chunks of live boards
+#pragma unroll
+        for (int r = 0; r < XR; ++r) {
+            const int j = threadIdx.x + r * THREADS;
+            pre[r] = j < XITEMS && j < left
+                         ? *reinterpret_cast<const uint4 *>(base + (int64_t)(j >> 2) * C + (j & 3) * 8)
+                         : uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    if ((int64_t)blockIdx.x < groups) load(blockIdx.x, 0);
+
+    for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        const int64_t b = grp * BPB + slot;
+        const bool live = b < n;
+        f32x4 acc[8][NTW];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
+            __syncthreads();          // the weights are in; the previous half's products are done
+#pragma unroll
+            for (int r = 0; r < XR; ++r) {
+                const int j = threadIdx.x + r * THREADS;
+                if (j < XITEMS) {
+                    const int bb = j / (PP * 4), rem = j % (PP * 4), q = rem >> 2, c8 = rem & 3;
+                    // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4 (bank spread)
+                    *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + ((c8 + (q >> 2)) & 3) * 8) = pre[r];
+                }
+            }
+            __syncthreads();
+            {
+                // the next (group, half): this group's second half, or the next group's first
+                const int64_t ng = h == 0 ? grp : grp + gridDim.x;
+                if (ng < groups) load(ng, h ^ 1);
+            }
+            if (!live) continue;
+            const uint16_t *xb = xs + slot * PP * 32;
+#pragma unroll 1
+            for (int t = 0; t < 9; ++t) {
+                const int toff = (t / 3) * NP + (t % 3);
+                bf16x8 bfr[NTW];
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt)
+                    bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(
+                        wsr + ((half * NTW + nt) * 16 + row) * WR + t * 64 + h * 32 + quad * 8));
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    if (g * 8 + mt >= MT) break;
+                    const int q = cell_off[mt] + toff;
+                    const bf16x8 a =
+                        as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+                }
+            }
+        }
+        if (!live) continue;
+        uint16_t *ob = out + b * (int64_t)PP * C;
+        if (g == 0 && half == 0) zero_ring<N>(ob, lane);
+        const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
+        // the output cells' offsets are recomputed per group: an opaque base
+        // keeps the compiler from holding all of them across the launch
+        int pbase = g * 128 + quad * 4;
+        asm volatile("" : "+v"(pbase));
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            if (g * 8 + mt >= MT) break;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int p = pbase + mt * 16 + i;
+                if (p >= PIX) continue;
+                const int o = (((p / N) + 1) * NP + (p % N) + 1) * C; // 32-bit: cheap to keep
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt) {
+                    const int co = (half * NTW + nt) * 16 + row;
+                    float v = acc[mt][nt][i];
+                    if constexpr (MODE == 0) {
+                        v += bias[co];
+                        v = v > 0.f ? v : 0.f;
+                    } else {
+                        const uint16_t m = mb[o + co];
+                        v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
+                    }
+                    ob[o + co] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // heads, forward: one wave per board, lanes over cells.
 // logits in action order (the frame of player 2 is transposed back), and
 // optionally in the mover's frame; value = tanh(wv . mean + bv).
@@ -1059,9 +1200,16 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     uint16_t *in = ya, *out = yb;
     using LC = LdsConv<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
+    const unsigned rb = (unsigned)blocks_min((n + LC::BPB - 1) / LC::BPB, RES_BLOCKS);
     for (int l = 2; l <= 4; ++l) {
-        hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
-                           params + b_off(l), (const uint16_t *)nullptr, out, n);
+        // 19x19: weights resident (measured 9.8 against 10.5 ms per 65536-board
+        // forward); 11x11: the per-group staging measured faster (3.7 against 3.9 ms)
+        if constexpr (N == 19)
+            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
+                               params + b_off(l), (const uint16_t *)nullptr, out, n);
+        else
+            hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
+                               params + b_off(l), (const uint16_t *)nullptr, out, n);
         uint16_t *t = in;
         in = out;
         out = t;
@@ -1102,9 +1250,15 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
                        (const uint16_t *)nullptr, y[1], n);
     using LC = LdsConv<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
-    for (int l = 2; l <= 4; ++l)
-        hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                           params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+    const unsigned rb = (unsigned)blocks_min((n + LC::BPB - 1) / LC::BPB, RES_BLOCKS);
+    for (int l = 2; l <= 4; ++l) {
+        if constexpr (N == 19)
+            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+        else
+            hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+    }
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
                        action, z, n, beta, 1.f / (float)n, dlog, du, lterms, ga);
