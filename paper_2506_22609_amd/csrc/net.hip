@@ -10,9 +10,11 @@
 // tap is a plain pointer offset and needs no bounds test.  The first layer's
 // input has C = 4 (mover, opponent, empty, zero).
 //
-// Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16: M = the cells of
-// one board (16-cell tiles, up to 8 tiles per wave), N = 64 output channels
-// (4 tiles), K = 9 taps x C input channels.  A wave owns one (board, group of
+// Convolution = implicit GEMM on v_mfma_f32_16x16x32_bf16: M = 64 output
+// channels (4 tiles), N = the cells of one board (16-cell tiles, up to 8
+// tiles per wave), K = 9 taps x C input channels; with the channels as M a
+// lane's results are consecutive channels of one cell, written 16 bytes at a
+// time.  A wave owns one (board, group of
 // 8 cell tiles) and keeps 8 x 4 accumulator tiles in registers; the block's
 // weights ([64][K] bf16, rows padded by 8 elements) sit in LDS and are
 // shared by the block's four waves.  The same kernel computes the gradient
@@ -146,6 +148,62 @@ __device__ __forceinline__ void zero_ring(uint16_t *act_b, int lane)
 }
 
 // ---------------------------------------------------------------------------
+// Output-channel placement.  The convolutions multiply the weights (M = the
+// output channels) by the activations (N = the cells of a tile), so a lane
+// of a 16 x 16 product holds four M rows of one cell.  A row m of the wave's
+// channel tile nt is given the weight row of channel
+//   half * 16 NTW + 4 NTW (m / 4) + 4 nt + m % 4,
+// which makes a lane's rows over all its NTW tiles 4 NTW consecutive
+// channels of its cell, stored with 16-byte writes.  w_slot is the inverse:
+// the LDS row that holds output channel o.
+// ---------------------------------------------------------------------------
+template <int NTW>
+__device__ __forceinline__ int w_slot(int o)
+{
+    constexpr int SPAN = 16 * NTW; // output channels of one wave
+    const int half = o / SPAN, r = o % SPAN;
+    const int m = 4 * (r / (4 * NTW)) + (r & 3), nt = (r >> 2) % NTW;
+    return (half * NTW + nt) * 16 + m;
+}
+
+// Epilogue of one cell: acc[nt][k] is channel c0 + 4 nt + k of the cell
+// whose output row starts at orow (mrow: the same row of the mask).
+//   MODE 0: bf16(relu(acc)); the accumulators started at the bias
+//   MODE 1: bf16(acc) where the mask is positive, else 0
+template <int NTW, int MODE>
+__device__ __forceinline__ void store_cell(const f32x4 (&acc)[NTW], const uint16_t *mrow, uint16_t *orow)
+{
+    float v[4 * NTW];
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[4 * nt + k] = acc[nt][k];
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < 4 * NTW; ++j) v[j] = fmaxf(v[j], 0.f);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NTW / 2; ++q) {
+            const uint4 mv = reinterpret_cast<const uint4 *>(mrow)[q];
+            const uint32_t mw[4] = {mv.x, mv.y, mv.z, mv.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t m = (mw[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+                v[8 * q + j] = (m != 0 && (m & 0x8000u) == 0) ? v[8 * q + j] : 0.f;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NTW / 2; ++q) {
+        uint32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            w[j] = (uint32_t)f2bf(v[8 * q + 2 * j]) | ((uint32_t)f2bf(v[8 * q + 2 * j + 1]) << 16);
+        reinterpret_cast<uint4 *>(orow)[q] = uint4{w[0], w[1], w[2], w[3]};
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3x3 convolution, implicit GEMM on MFMA.
 //   MODE 0 (forward):  out = bf16(relu(conv(X, W) + bias))
 //   MODE 1 (data gradient): out = bf16(conv(X, W) * [mask > 0]), X = dZ of the
@@ -168,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
     // stage the weights (all 256 threads), 16 bytes at a time
     for (int j = threadIdx.x; j < C * K / 8; j += 256) {
         const int o = j / (K / 8), k8 = j % (K / 8);
-        reinterpret_cast<uint4 *>(ws + o * KS)[k8] = reinterpret_cast<const uint4 *>(w + (int64_t)o * K)[k8];
+        reinterpret_cast<uint4 *>(ws + w_slot<4>(o) * KS)[k8] = reinterpret_cast<const uint4 *>(w + (int64_t)o * K)[k8];
     }
     __syncthreads();
 
@@ -191,11 +249,17 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
         const int pc = p < PIX ? p : 0;
         cell_off[mt] = ((pc / N) * NP + (pc % N)) * CIN;
     }
+    // accumulators start at the bias of their channels 16 quad + 4 nt + k
     f32x4 acc[8][4];
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 b0 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE == 0)
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < 4; ++k) b0[k] = bias[16 * quad + 4 * nt + k];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = b0;
+    }
 
     // A fragments of K-step ks: this lane's 8 consecutive k of each tile row
     auto load_a = [&](int ks, bf16x8 (&a)[8]) {
@@ -242,36 +306,22 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
             if (g * 8 + mt >= MT) break;
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur[mt], bfr[nt], acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], a_cur[mt], acc[mt][nt], 0, 0, 0);
         }
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) a_cur[mt] = a_nxt[mt];
     }
 
-    // epilogue: lane holds rows 4 * quad + i (cells) of column row (channel)
+    // epilogue: lane holds channels 16 quad .. 16 quad + 15 of cell row of each tile
+    const int c0 = 16 * quad;
     const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
         if (g * 8 + mt >= MT) break;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = (g * 8 + mt) * 16 + quad * 4 + i;
-            if (p >= PIX) continue;
-            const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C;
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-                const int co = nt * 16 + row;
-                float v = acc[mt][nt][i];
-                if constexpr (MODE == 0) {
-                    v += bias[co];
-                    v = v > 0.f ? v : 0.f;
-                } else {
-                    const uint16_t m = mb[o + co];
-                    v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
-                }
-                ob[o + co] = f2bf(v);
-            }
-        }
+        const int p = (g * 8 + mt) * 16 + row;
+        if (p >= PIX) continue;
+        const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C + c0;
+        store_cell<4, MODE>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
     }
 }
 
@@ -322,17 +372,25 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
         const int pc = p < PIX ? p : 0;
         cell_off[mt] = (pc / N) * NP + (pc % N);
     }
+    // this lane's output channels are c0 .. c0 + 4 NTW - 1; the accumulators
+    // start at their bias
+    const int c0 = half * 16 * NTW + 4 * NTW * quad;
     f32x4 acc[8][NTW];
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt)
+    for (int nt = 0; nt < NTW; ++nt) {
+        f32x4 b0 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE == 0)
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < 4; ++k) b0[k] = bias[c0 + 4 * nt + k];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = b0;
+    }
 
     for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
         __syncthreads();
         for (int j = threadIdx.x; j < C * 9 * 4; j += L::THREADS) { // weights: (out, tap, 8-channel chunk)
             const int o = j / 36, r = j % 36, t = r >> 2, c8 = r & 3;
-            *reinterpret_cast<uint4 *>(ws + o * WS + t * 32 + c8 * 8) =
+            *reinterpret_cast<uint4 *>(ws + w_slot<NTW>(o) * WS + t * 32 + c8 * 8) =
                 *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8);
         }
         for (int j = threadIdx.x; j < BPB * PP * 4; j += L::THREADS) { // boards: (board, cell, chunk)
@@ -360,7 +418,7 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
                 const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
 #pragma unroll
                 for (int nt = 0; nt < NTW; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], a, acc[mt][nt], 0, 0, 0);
             }
         }
     }
@@ -372,25 +430,10 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
         if (g * 8 + mt >= MT) break;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = (g * 8 + mt) * 16 + quad * 4 + i;
-            if (p >= PIX) continue;
-            const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C;
-#pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) {
-                const int co = (half * NTW + nt) * 16 + row;
-                float v = acc[mt][nt][i];
-                if constexpr (MODE == 0) {
-                    v += bias[co];
-                    v = v > 0.f ? v : 0.f;
-                } else {
-                    const uint16_t m = mb[o + co];
-                    v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
-                }
-                ob[o + co] = f2bf(v);
-            }
-        }
+        const int p = (g * 8 + mt) * 16 + row;
+        if (p >= PIX) continue;
+        const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C + c0;
+        store_cell<NTW, MODE>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
     }
 }
 
@@ -434,8 +477,16 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint1
     }
     for (int j = threadIdx.x; j < C * (K2 / 8); j += THREADS) {
         const int o = j / (K2 / 8), r = j % (K2 / 8);
-        *reinterpret_cast<uint4 *>(wsr + o * WR + r * 8) = *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + r * 8);
+        *reinterpret_cast<uint4 *>(wsr + w_slot<NTW>(o) * WR + r * 8) =
+            *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + r * 8);
     }
+
+    // this lane's output channels are c0 .. c0 + 4 NTW - 1; each group's
+    // accumulators start at their bias
+    const int c0 = half * 16 * NTW + 4 * NTW * quad;
+    float bv[4 * NTW];
+#pragma unroll
+    for (int j = 0; j < 4 * NTW; ++j) bv[j] = MODE == 0 ? bias[c0 + j] : 0.f;
 
     const int64_t groups = (n + BPB - 1) / BPB;
     uint4 pre[XR];
@@ -461,7 +512,7 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint1
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{bv[4 * nt], bv[4 * nt + 1], bv[4 * nt + 2], bv[4 * nt + 3]};
         for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
             __syncthreads();          // the weights are in; the previous half's products are done
 #pragma unroll
@@ -497,7 +548,7 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint1
                         as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
-                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bfr[nt], acc[mt][nt], 0, 0, 0);
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], a, acc[mt][nt], 0, 0, 0);
                 }
             }
         }
@@ -507,30 +558,15 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint1
         const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
         // the output cells' offsets are recomputed per group: an opaque base
         // keeps the compiler from holding all of them across the launch
-        int pbase = g * 128 + quad * 4;
+        int pbase = g * 128 + row;
         asm volatile("" : "+v"(pbase));
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             if (g * 8 + mt >= MT) break;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = pbase + mt * 16 + i;
-                if (p >= PIX) continue;
-                const int o = (((p / N) + 1) * NP + (p % N) + 1) * C; // 32-bit: cheap to keep
-#pragma unroll
-                for (int nt = 0; nt < NTW; ++nt) {
-                    const int co = (half * NTW + nt) * 16 + row;
-                    float v = acc[mt][nt][i];
-                    if constexpr (MODE == 0) {
-                        v += bias[co];
-                        v = v > 0.f ? v : 0.f;
-                    } else {
-                        const uint16_t m = mb[o + co];
-                        v = (m != 0 && (m & 0x8000u) == 0) ? v : 0.f;
-                    }
-                    ob[o + co] = f2bf(v);
-                }
-            }
+            const int p = pbase + mt * 16;
+            if (p >= PIX) continue;
+            const int o = (((p / N) + 1) * NP + (p % N) + 1) * C + c0; // 32-bit: cheap to keep
+            store_cell<NTW, MODE>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
         }
     }
 }

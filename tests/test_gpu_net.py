@@ -61,6 +61,22 @@ def test_forward_matches_oracle(N, n):
     close(value.cpu().numpy(), f["value"])
 
 
+@pytest.mark.parametrize("N,n", [(19, 700), (11, 1030)])
+def test_forward_large_batch_sampled(N, n):
+    """Batches past one group per block: at 19x19 each of the 256 blocks with
+    the weights resident walks up to two 2-board groups; at 11x11 the last
+    4-board block holds 2 boards.  The oracle checks a sample of the boards,
+    spread over the first and second group of a block and the tail."""
+    g, s = _states(ref.HEX, N, n, 17 + N)
+    net, p = _net(N, 11)
+    logits, value = net.forward(torch.from_numpy(s.board).cuda(), torch.from_numpy(s.to_move).cuda())
+    idx = np.unique(np.r_[np.arange(0, n, 37), 510, 511, 512, 513, n - 3, n - 2, n - 1])
+    sub = s.subset(idx)
+    f = R.forward(p, sub.board, sub.to_move, N, bf16=True)
+    close(logits.cpu().numpy()[idx], f["logits"])
+    close(value.cpu().numpy()[idx], f["value"])
+
+
 @pytest.mark.parametrize("kind", [ref.HEX, ref.GOMOKU], ids=["hex", "gomoku"])
 @pytest.mark.parametrize("N,n", [(11, 67), (19, 9)])
 def test_loss_and_gradient_match_oracle(kind, N, n):
