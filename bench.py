@@ -145,6 +145,26 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     }
 
 
+def _copy_peak_gbs(mib: int = 1024, reps: int = 5) -> float:
+    """Measured stream-copy rate of this GPU: a plain device-to-device copy
+    of `mib` MiB, bytes read plus bytes written per second, event-timed."""
+    import torch
+
+    src = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / sec / 1e9
+
+
 def _plain_step_section(batches, seed: int, reps: int):
     """The per-ply loop with the state in HBM between plies: ludax_init,
     then ludax_random_step launched max_plies times (the game's natural
@@ -153,11 +173,14 @@ def _plain_step_section(batches, seed: int, reps: int):
     8 B of scalars read, 8 B of scalars + 2 B reward + 1 B terminal + the
     1-byte board delta written (cells + 20 B); per env the init writes
     cells + 8 B.  The replay time includes the launches of the tail, when
-    few games are still running, and the gaps between graph nodes."""
+    few games are still running, and the gaps between graph nodes.  The
+    achieved rate is given as a fraction of the nominal HBM peak and of the
+    measured stream-copy rate ("copy_peak_GBs")."""
     import torch
     from paper_2506_22609_amd import ludax
 
-    out = {}
+    copy_gbs = _copy_peak_gbs()
+    out = {"copy_peak_GBs": copy_gbs}
     for b in batches:
         g = ludax.Game(b.kind, b.rows, b.cols)
         s = ludax.State(g, b.n)
@@ -201,6 +224,7 @@ def _plain_step_section(batches, seed: int, reps: int):
                        "env_steps_per_s": steps / el, "alg_bytes_per_env_step": g.cells + 20,
                        "alg_bytes_per_loop": alg, "achieved_GBs": alg / el / 1e9,
                        "hbm_frac": alg / el / 1e9 / HBM_PEAK_GBS,
+                       "hbm_frac_of_copy": alg / el / 1e9 / copy_gbs,
                        "still_running_after_loop": running_after}
         del graph, s
         torch.cuda.synchronize()

@@ -54,6 +54,10 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// pointers of the memory-to-LDS load builtin
+typedef __attribute__((address_space(1))) void glb_void;
+typedef __attribute__((address_space(3))) void lds_void;
+
 // ---------------------------------------------------------------------------
 // parameter offsets in the flat float32 vector
 // ---------------------------------------------------------------------------
@@ -157,6 +161,14 @@ __device__ __forceinline__ void zero_ring(uint16_t *act_b, int lane)
 // channels of its cell, stored with 16-byte writes.  w_slot is the inverse:
 // the LDS row that holds output channel o.
 // ---------------------------------------------------------------------------
+// the output channel whose weights sit in LDS row s (inverse of w_slot)
+template <int NTW>
+__device__ __forceinline__ int w_channel(int s)
+{
+    const int half = s / (16 * NTW), nt = (s / 16) % NTW, m = s % 16;
+    return half * 16 * NTW + 4 * NTW * (m >> 2) + 4 * nt + (m & 3);
+}
+
 template <int NTW>
 __device__ __forceinline__ int w_slot(int o)
 {
@@ -331,33 +343,153 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
 // leaves the MFMA pipes waiting on the vector memory path; here a block
 // stages its boards and the weights in LDS, half of the input channels at a
 // time (two phases of 9 taps x 32 channels), so each activation byte comes
-// from memory once per layer.  N = 11: 4 boards per block, one wave each;
-// N = 19: one board per block, 3 waves of <= 8 cell tiles.  Same MODEs as
-// k_conv.
+// from memory once per layer; the staging copies go from memory to LDS
+// directly, all of a wave's copies in flight together.  N = 11: 4 boards
+// per block, one wave per board with all 64 output channels; N = 19: 2
+// boards per block, each board's cells in 3 groups of <= 8 tiles and its
+// output channels split over 2 waves (12 waves).  Same MODEs as k_conv,
+// plus MODE 2: the first two layers of the forward in one kernel.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, int SPLIT>
 struct LdsConv {
     static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
     static constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
     static constexpr int BPB = N <= 13 ? 4 : 2;        // boards per block
-    static constexpr int NSPLIT = 2;                    // waves sharing a board's 64 output channels
+    static constexpr int NSPLIT = SPLIT;                // waves sharing a board's 64 output channels
     static constexpr int NTW = 4 / NSPLIT;              // output-channel tiles per wave
     static constexpr int THREADS = BPB * NG * NSPLIT * 64;
     static constexpr int WS = 9 * 32 + 8;               // weight row stride (bf16), one half of K
 };
+// the per-group kernel (k_conv_lds) gives each board's 64 output channels to
+// one wave at 11x11 (each activation fragment then feeds four MFMAs instead
+// of two: 0.81 against 0.94 ms per 65536-board layer) and to two at 19x19
+// (measured 3 % faster there); the weights-resident one (k_conv_res) splits
+// them over two (its register prefetch of the next group leaves no room for
+// 128 accumulators)
+template <int N>
+using LdsL = LdsConv<N, N <= 13 ? 1 : 2>;
+template <int N>
+using LdsR = LdsConv<N, 2>;
 
+// The layer-1 side of the fused forward (k_conv_lds MODE 2): the boards and
+// sides to move, and layer 1's packed weights and bias.
+struct L1Args {
+    const int8_t *board, *to_move;
+    const uint16_t *w1;
+    const float *b1;
+};
+
+// Cell codes of the fused forward: for each board of a block and each cell
+// of its padded frame, 0 = the mover's stone, 1 = the opponent's, 2 = empty,
+// 3 = the zero ring, in the mover's frame (player 2 sees the transpose of the
+// board: frame cell (r, c) is board cell c N + r), so a layer-1 tap is one
+// byte read.  These are the encoder's planes (mover, opponent, empty, 0).
+template <int N>
+__device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t n, uint8_t *cc)
+{
+    using L = LdsL<N>;
+    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, BPB = L::BPB;
+    constexpr int ITEMS = BPB * PP, R = (ITEMS + L::THREADS - 1) / L::THREADS;
+    int x[R], me[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) { // all loads first
+        const int j = threadIdx.x + k * L::THREADS, bb = j / PP, q = j % PP, rr = q / NP - 1, c = q % NP - 1;
+        const bool in = j < ITEMS && b0 + bb < n && (unsigned)rr < (unsigned)N && (unsigned)c < (unsigned)N;
+        me[k] = in ? (int)a1.to_move[b0 + bb] : 0;
+        x[k] = in ? (int)a1.board[(b0 + bb) * PIX + (me[k] == 2 ? c * N + rr : rr * N + c)] : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int j = threadIdx.x + k * L::THREADS;
+        if (j < ITEMS) cc[j] = (uint8_t)(x[k] < 0 ? 3 : (x[k] == me[k] ? 0 : (x[k] == 0 ? 2 : 1)));
+    }
+}
+
+// Layer 1 (3 input planes, 64 output channels) for the output channels
+// 32 h .. 32 h + 31 of the block's BPB boards, written bf16(relu) into the
+// interior cells of the block's LDS tile in the layout layer 2 reads (cell q
+// of board bb at xs + (bb PP + q) 32, chunk c8 at position (c8 + q / 4) mod 4).
+// The input planes come from the cell codes (cc).  Work items (board,
+// 16-cell tile, 16-channel tile) are spread over the block's waves (a wave
+// always gets the same channel tile, so its weight fragments are loaded
+// once); an item is two MFMAs (K = 9 taps x 4 planes, padded to 64) with the
+// channels as M, so a lane ends with 4 consecutive channels of one cell: one
+// 8-byte LDS write.
+template <int N>
+__device__ __forceinline__ void layer1_half(const L1Args &a1, int h, int64_t b0, int64_t n, const uint8_t *cc,
+                                            uint16_t *xs)
+{
+    using L = LdsL<N>;
+    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, BPB = L::BPB;
+    constexpr int NWAVES = L::THREADS / 64;
+    static_assert(NWAVES % 2 == 0, "a wave keeps one channel tile");
+    const int lane = threadIdx.x & 63, row = lane & 15, quad = lane >> 4;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int co = 32 * h + 16 * (wid & 1); // the wave's channel tile
+    uint4 wa[K1 / 32];
+#pragma unroll
+    for (int ks = 0; ks < K1 / 32; ++ks)
+        wa[ks] = *reinterpret_cast<const uint4 *>(a1.w1 + (co + row) * K1 + ks * 32 + quad * 8);
+    const f32x4 bias = {a1.b1[co + 4 * quad], a1.b1[co + 4 * quad + 1], a1.b1[co + 4 * quad + 2],
+                        a1.b1[co + 4 * quad + 3]};
+    // frame offsets of this lane's taps 8 ks + 2 quad + e; taps >= 9 (zero
+    // weights) read tap 0
+    int toff[K1 / 32][2];
+#pragma unroll
+    for (int ks = 0; ks < K1 / 32; ++ks)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int t = 8 * ks + 2 * quad + e, u = t < 9 ? t : 0;
+            toff[ks][e] = (u / 3) * NP + u % 3;
+        }
+    constexpr uint32_t ONE = 0x3F80u; // bf16 1.0
+#pragma unroll 1
+    for (int it = wid; it < BPB * MT * 2; it += NWAVES) {
+        const int bb = it / (MT * 2), mt = (it % (MT * 2)) >> 1;
+        if (b0 + bb >= n) continue; // a board past the batch end: its tile is never read
+        const int p = mt * 16 + row, pc = p < PIX ? p : 0;
+        const uint8_t *cb = cc + bb * PP + (pc / N) * NP + pc % N; // top-left tap of cell p
+        f32x4 acc = bias;
+#pragma unroll
+        for (int ks = 0; ks < K1 / 32; ++ks) {
+            uint32_t v[4];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint32_t code = cb[toff[ks][e]];
+                v[2 * e] = code < 2 ? ONE << (16 * code) : 0u; // planes 0, 1
+                v[2 * e + 1] = code == 2 ? ONE : 0u;           // planes 2, 3
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(wa[ks]), as_bf16x8(uint4{v[0], v[1], v[2], v[3]}),
+                                                          acc, 0, 0, 0);
+        }
+        if (p < PIX) { // channels co + 4 quad + k, k < 4, of cell p
+            const int q = (p / N + 1) * NP + p % N + 1, c = co - 32 * h + 4 * quad;
+            const uint2 o = {(uint32_t)f2bf(fmaxf(acc[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1], 0.f)) << 16),
+                             (uint32_t)f2bf(fmaxf(acc[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3], 0.f)) << 16)};
+            *reinterpret_cast<uint2 *>(xs + (bb * PP + q) * 32 + (((c >> 3) + (q >> 2)) & 3) * 8 + (c & 7)) = o;
+        }
+    }
+}
+
+// MODE 2 (forward of the first two layers): each channel half of layer 1's
+// output is computed by the block from its boards (a1) straight into the LDS
+// tile that layer 2 reads, so layer 1's activations never go to memory; x is
+// unused, w / bias are layer 2's and the output is layer 2's.
 template <int N, int MODE>
-__global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint16_t *__restrict__ x,
+__global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
                                                                      const float *__restrict__ bias,
                                                                      const uint16_t *__restrict__ mask,
-                                                                     uint16_t *__restrict__ out, int64_t n)
+                                                                     uint16_t *__restrict__ out, int64_t n,
+                                                                     L1Args a1)
 {
-    using L = LdsConv<N>;
+    using L = LdsL<N>;
     constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
     constexpr int NTW = L::NTW;
     __shared__ __align__(16) uint16_t ws[C * WS];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
+    // MODE 2: the cell codes of the block's boards
+    __shared__ uint8_t cc[MODE == 2 ? BPB * PP : 1];
 
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
@@ -365,45 +497,78 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
     const int64_t b = b0 + slot;
     const bool live = b < n;
     const int row = lane & 15, quad = lane >> 4;
-    int cell_off[8]; // top-left tap of this lane's A row in each tile (padded cells)
-#pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-        const int p = (g * 8 + mt) * 16 + row;
-        const int pc = p < PIX ? p : 0;
-        cell_off[mt] = (pc / N) * NP + (pc % N);
-    }
     // this lane's output channels are c0 .. c0 + 4 NTW - 1; the accumulators
     // start at their bias
     const int c0 = half * 16 * NTW + 4 * NTW * quad;
     f32x4 acc[8][NTW];
 #pragma unroll
     for (int nt = 0; nt < NTW; ++nt) {
-        f32x4 b0 = {0.f, 0.f, 0.f, 0.f};
-        if constexpr (MODE == 0)
+        f32x4 bv = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (MODE != 1)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) b0[k] = bias[c0 + 4 * nt + k];
+            for (int k = 0; k < 4; ++k) bv[k] = bias[c0 + 4 * nt + k];
 #pragma unroll
-        for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = b0;
+        for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = bv;
     }
 
+    if constexpr (MODE == 2) cell_codes<N>(a1, b0, n, cc); // read after the barrier below
     for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
-        __syncthreads();
-        for (int j = threadIdx.x; j < C * 9 * 4; j += L::THREADS) { // weights: (out, tap, 8-channel chunk)
-            const int o = j / 36, r = j % 36, t = r >> 2, c8 = r & 3;
-            *reinterpret_cast<uint4 *>(ws + w_slot<NTW>(o) * WS + t * 32 + c8 * 8) =
-                *reinterpret_cast<const uint4 *>(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8);
+        // the staging goes straight from memory to LDS (no registers), every
+        // load of a wave in flight at once; a wave instruction fills 64
+        // consecutive 16-byte chunks of the tile, one per lane, so each lane
+        // picks the source of its chunk
+        __syncthreads(); // the previous half's products are done
+        {
+            const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            constexpr int NWAVES = L::THREADS / 64, WCH = C * (WS / 8); // 37 chunks a row, the last one padding
+            for (int base = wid * 64; base < WCH; base += NWAVES * 64) {
+                const int i = base + lane, srow = i / (WS / 8), col = i % (WS / 8);
+                const int o = w_channel<NTW>(srow), t = col < 36 ? col >> 2 : 0, c8 = col < 36 ? col & 3 : 0;
+                if (i < WCH)
+                    __builtin_amdgcn_global_load_lds(
+                        (glb_void *)(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8), (lds_void *)(ws + base * 8), 16,
+                        0, 0);
+            }
+            if constexpr (MODE != 2) {
+                constexpr int XCH = BPB * PP * 4;
+                for (int base = wid * 64; base < XCH; base += NWAVES * 64) {
+                    // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4: the 16 cells
+                    // a fragment read touches then fall on 16 different LDS bank groups
+                    const int i = base + lane, bb = i / (PP * 4), q = (i % (PP * 4)) >> 2;
+                    const int c8 = ((i & 3) - (q >> 2)) & 3;
+                    const int64_t bsrc = b0 + bb < n ? b0 + bb : b0; // a board past the end: any valid one
+                    if (i < XCH)
+                        __builtin_amdgcn_global_load_lds((glb_void *)(x + (bsrc * PP + q) * C + h * 32 + c8 * 8),
+                                                         (lds_void *)(xs + base * 8), 16, 0, 0);
+                }
+            }
         }
-        for (int j = threadIdx.x; j < BPB * PP * 4; j += L::THREADS) { // boards: (board, cell, chunk)
-            const int bb = j / (PP * 4), r = j % (PP * 4), q = r >> 2, c8 = r & 3;
-            // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4: the 16 cells a
-            // fragment read touches then fall on 16 different LDS bank groups
-            if (b0 + bb < n)
-                *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + ((c8 + (q >> 2)) & 3) * 8) =
-                    *reinterpret_cast<const uint4 *>(x + ((b0 + bb) * PP + q) * (int64_t)C + h * 32 + c8 * 8);
+        if constexpr (MODE == 2) {
+            if (h == 0) {
+                // the ring of every board's tile stays zero for both halves
+                for (int j = threadIdx.x; j < BPB * 4 * (NP - 1) * 4; j += L::THREADS) {
+                    const int bb = j / (4 * (NP - 1) * 4), r = j % (4 * (NP - 1) * 4);
+                    const int q = ring_cell<NP>(r >> 2);
+                    *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
+                }
+            }
+            layer1_half<N>(a1, h, b0, n, cc, xs);
         }
+        __builtin_amdgcn_s_waitcnt(0); // this wave's memory-to-LDS loads have landed
         __syncthreads();
         if (!live) continue;
         const uint16_t *xb = xs + slot * PP * 32;
+        // top-left tap of this lane's cell in each tile (padded cells), formed
+        // per half (an opaque base keeps them out of the layer-1 phase)
+        int pbase = g * 128 + row;
+        asm volatile("" : "+v"(pbase));
+        int cell_off[8];
+#pragma unroll
+        for (int mt = 0; mt < 8; ++mt) {
+            const int p = pbase + mt * 16;
+            const int pc = p < PIX ? p : 0;
+            cell_off[mt] = (pc / N) * NP + (pc % N);
+        }
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int toff = (t / 3) * NP + (t % 3);
@@ -433,7 +598,7 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
         const int p = (g * 8 + mt) * 16 + row;
         if (p >= PIX) continue;
         const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C + c0;
-        store_cell<NTW, MODE>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
+        store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
     }
 }
 
@@ -450,13 +615,13 @@ __global__ __launch_bounds__(LdsConv<N>::THREADS, 2) void k_conv_lds(const uint1
 constexpr int RES_BLOCKS = 256; // one per CU
 
 template <int N, int MODE>
-__global__ __launch_bounds__(LdsConv<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
+__global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
                                                                      const float *__restrict__ bias,
                                                                      const uint16_t *__restrict__ mask,
                                                                      uint16_t *__restrict__ out, int64_t n)
 {
-    using L = LdsConv<N>;
+    using L = LdsR<N>;
     constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB;
     constexpr int NTW = L::NTW, THREADS = L::THREADS;
     constexpr int WR = K2 + 8;                           // weight row stride (bf16)
@@ -1218,6 +1383,11 @@ struct Sizes {
     }
 };
 
+// forward: layers 1 and 2 fused (k_conv_lds MODE 2) at 11x11; at 19x19 the
+// weights-resident kernel for layer 2 is kept
+template <int N>
+constexpr bool FUSE_L1 = N == 11;
+
 template <int N>
 hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
                      int64_t n, float *logits, float *value, void *ws, hipStream_t s)
@@ -1230,22 +1400,32 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     uint16_t *yb = cv.take<uint16_t>(S::act(n));
     const unsigned eb = (unsigned)((n * S::PP + 255) / 256), cb = (unsigned)((n * NG + 3) / 4),
                    hb = (unsigned)((n + 3) / 4);
-    hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
-    hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, reinterpret_cast<const uint16_t *>(a0),
-                       packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
-    uint16_t *in = ya, *out = yb;
-    using LC = LdsConv<N>;
+    using LC = LdsL<N>;
+    using LR = LdsR<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
-    const unsigned rb = (unsigned)blocks_min((n + LC::BPB - 1) / LC::BPB, RES_BLOCKS);
-    for (int l = 2; l <= 4; ++l) {
+    const unsigned rb = (unsigned)blocks_min((n + LR::BPB - 1) / LR::BPB, RES_BLOCKS);
+    int l0 = 2;
+    if constexpr (FUSE_L1<N>) {
+        // layers 1 and 2 in one kernel from the boards, layer 1's activations kept in LDS
+        hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
+                           packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n,
+                           L1Args{board, to_move, packed + pf_off(1), params + b_off(1)});
+        l0 = 3;
+    } else {
+        hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
+        hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, reinterpret_cast<const uint16_t *>(a0),
+                           packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
+    }
+    uint16_t *in = ya, *out = yb;
+    for (int l = l0; l <= 4; ++l) {
         // 19x19: weights resident (measured 9.8 against 10.5 ms per 65536-board
         // forward); 11x11: the per-group staging measured faster (3.7 against 3.9 ms)
         if constexpr (N == 19)
-            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
+            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, in, packed + pf_off(l),
                                params + b_off(l), (const uint16_t *)nullptr, out, n);
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n);
+                               params + b_off(l), (const uint16_t *)nullptr, out, n, L1Args{});
         uint16_t *t = in;
         in = out;
         out = t;
@@ -1284,16 +1464,17 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
     hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, y[0], packed + pf_off(1), params + b_off(1),
                        (const uint16_t *)nullptr, y[1], n);
-    using LC = LdsConv<N>;
+    using LC = LdsL<N>;
+    using LR = LdsR<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
-    const unsigned rb = (unsigned)blocks_min((n + LC::BPB - 1) / LC::BPB, RES_BLOCKS);
+    const unsigned rb = (unsigned)blocks_min((n + LR::BPB - 1) / LR::BPB, RES_BLOCKS);
     for (int l = 2; l <= 4; ++l) {
         if constexpr (N == 19)
-            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
+            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, y[l - 1], packed + pf_off(l),
                                params + b_off(l), (const uint16_t *)nullptr, y[l], n);
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, L1Args{});
     }
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
@@ -1315,7 +1496,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
         hipLaunchKernelGGL((k_conv_lds<N, 1>), dim3(lb), dim3(LC::THREADS), 0, s, ga, packed + pb_off(l),
-                           (const float *)nullptr, y[l - 1], gb, n);
+                           (const float *)nullptr, y[l - 1], gb, n, L1Args{});
         uint16_t *t = ga;
         ga = gb;
         gb = t;
