@@ -352,6 +352,7 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
 // ---------------------------------------------------------------------------
 template <int N, int SPLIT>
 struct LdsConv {
+    static constexpr int SIDE = N;
     static constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
     static constexpr int MT = (PIX + 15) / 16, NG = (MT + 7) / 8;
     static constexpr int BPB = N <= 13 ? 4 : 2;        // boards per block
@@ -384,25 +385,50 @@ struct L1Args {
 // 3 = the zero ring, in the mover's frame (player 2 sees the transpose of the
 // board: frame cell (r, c) is board cell c N + r), so a layer-1 tap is one
 // byte read.  These are the encoder's planes (mover, opponent, empty, 0).
-template <int N>
-__device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t n, uint8_t *cc)
-{
-    using L = LdsL<N>;
-    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, BPB = L::BPB;
-    constexpr int ITEMS = BPB * PP, R = (ITEMS + L::THREADS - 1) / L::THREADS;
+// The raw inputs of one thread's cell codes (board byte and side to move of
+// each of its cells; x = -1 for a ring cell or a board past the batch end),
+// loaded ahead of the store so that the loads' latencies overlap.
+template <class L>
+struct CodeIn {
+    static constexpr int R = (L::BPB * L::PP + L::THREADS - 1) / L::THREADS;
     int x[R], me[R];
+};
+
+template <class L>
+__device__ __forceinline__ void code_load(const L1Args &a1, int64_t b0, int64_t n, CodeIn<L> &ci)
+{
+    constexpr int N = L::SIDE, NP = L::NP, PP = L::PP, PIX = L::PIX, ITEMS = L::BPB * PP;
 #pragma unroll
-    for (int k = 0; k < R; ++k) { // all loads first
+    for (int k = 0; k < CodeIn<L>::R; ++k) {
         const int j = threadIdx.x + k * L::THREADS, bb = j / PP, q = j % PP, rr = q / NP - 1, c = q % NP - 1;
         const bool in = j < ITEMS && b0 + bb < n && (unsigned)rr < (unsigned)N && (unsigned)c < (unsigned)N;
-        me[k] = in ? (int)a1.to_move[b0 + bb] : 0;
-        x[k] = in ? (int)a1.board[(b0 + bb) * PIX + (me[k] == 2 ? c * N + rr : rr * N + c)] : -1;
+        ci.me[k] = in ? (int)a1.to_move[b0 + bb] : 0;
+        ci.x[k] = in ? (int)a1.board[(b0 + bb) * PIX + (ci.me[k] == 2 ? c * N + rr : rr * N + c)] : -1;
     }
+}
+
+template <class L>
+__device__ __forceinline__ void code_store(const CodeIn<L> &ci, uint8_t *cc)
+{
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
+    for (int k = 0; k < CodeIn<L>::R; ++k) {
         const int j = threadIdx.x + k * L::THREADS;
-        if (j < ITEMS) cc[j] = (uint8_t)(x[k] < 0 ? 3 : (x[k] == me[k] ? 0 : (x[k] == 0 ? 2 : 1)));
+        if (j < L::BPB * L::PP)
+            cc[j] = (uint8_t)(ci.x[k] < 0 ? 3 : (ci.x[k] == ci.me[k] ? 0 : (ci.x[k] == 0 ? 2 : 1)));
     }
+}
+
+// Cell codes of the fused forward: for each board of a block and each cell
+// of its padded frame, 0 = the mover's stone, 1 = the opponent's, 2 = empty,
+// 3 = the zero ring, in the mover's frame (player 2 sees the transpose of the
+// board: frame cell (r, c) is board cell c N + r), so a layer-1 tap is one
+// byte read.  These are the encoder's planes (mover, opponent, empty, 0).
+template <class L>
+__device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t n, uint8_t *cc)
+{
+    CodeIn<L> ci;
+    code_load<L>(a1, b0, n, ci);
+    code_store<L>(ci, cc);
 }
 
 // Layer 1 (3 input planes, 64 output channels) for the output channels
@@ -415,12 +441,11 @@ __device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t
 // once); an item is two MFMAs (K = 9 taps x 4 planes, padded to 64) with the
 // channels as M, so a lane ends with 4 consecutive channels of one cell: one
 // 8-byte LDS write.
-template <int N>
+template <class L>
 __device__ __forceinline__ void layer1_half(const L1Args &a1, int h, int64_t b0, int64_t n, const uint8_t *cc,
                                             uint16_t *xs)
 {
-    using L = LdsL<N>;
-    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, BPB = L::BPB;
+    constexpr int N = L::SIDE, NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, BPB = L::BPB;
     constexpr int NWAVES = L::THREADS / 64;
     static_assert(NWAVES % 2 == 0, "a wave keeps one channel tile");
     const int lane = threadIdx.x & 63, row = lane & 15, quad = lane >> 4;
@@ -511,7 +536,7 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = bv;
     }
 
-    if constexpr (MODE == 2) cell_codes<N>(a1, b0, n, cc); // read after the barrier below
+    if constexpr (MODE == 2) cell_codes<L>(a1, b0, n, cc); // read after the barrier below
     for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
         // the staging goes straight from memory to LDS (no registers), every
         // load of a wave in flight at once; a wave instruction fills 64
@@ -552,7 +577,7 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
                     *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
                 }
             }
-            layer1_half<N>(a1, h, b0, n, cc, xs);
+            layer1_half<L>(a1, h, b0, n, cc, xs);
         }
         __builtin_amdgcn_s_waitcnt(0); // this wave's memory-to-LDS loads have landed
         __syncthreads();
@@ -614,21 +639,26 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
 // ---------------------------------------------------------------------------
 constexpr int RES_BLOCKS = 256; // one per CU
 
+// MODE 2 as in k_conv_lds: the first two layers, layer 1 computed per group
+// from its cell codes; the next group's board bytes are loaded into
+// registers while the current group is multiplied.
 template <int N, int MODE>
 __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
                                                                      const float *__restrict__ bias,
                                                                      const uint16_t *__restrict__ mask,
-                                                                     uint16_t *__restrict__ out, int64_t n)
+                                                                     uint16_t *__restrict__ out, int64_t n,
+                                                                     L1Args a1)
 {
     using L = LdsR<N>;
     constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB;
     constexpr int NTW = L::NTW, THREADS = L::THREADS;
     constexpr int WR = K2 + 8;                           // weight row stride (bf16)
     constexpr int XITEMS = BPB * PP * 4;                 // 16-byte chunks of one (group, half)
-    constexpr int XR = (XITEMS + THREADS - 1) / THREADS; // per thread
+    constexpr int XR = MODE == 2 ? 1 : (XITEMS + THREADS - 1) / THREADS; // per thread
     __shared__ __align__(16) uint16_t wsr[C * WR];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
+    __shared__ uint8_t cc[MODE == 2 ? BPB * PP : 1]; // MODE 2: the group's cell codes
 
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
@@ -651,9 +681,13 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
     const int c0 = half * 16 * NTW + 4 * NTW * quad;
     float bv[4 * NTW];
 #pragma unroll
-    for (int j = 0; j < 4 * NTW; ++j) bv[j] = MODE == 0 ? bias[c0 + j] : 0.f;
+    for (int j = 0; j < 4 * NTW; ++j) bv[j] = MODE != 1 ? bias[c0 + j] : 0.f;
 
     const int64_t groups = (n + BPB - 1) / BPB;
+    CodeIn<L> ci; // MODE 2: the next group's cell-code inputs
+    if constexpr (MODE == 2) {
+        if ((int64_t)blockIdx.x < groups) code_load<L>(a1, (int64_t)blockIdx.x * BPB, n, ci);
+    }
     uint4 pre[XR];
     auto load = [&](int64_t grp, int h) { // chunks (board, cell, 8 channels) of half h
         // chunk j of a group is 16 bytes at element 8 j of its (board, cell) rows,
@@ -668,7 +702,17 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
                          : uint4{0u, 0u, 0u, 0u};
         }
     };
-    if ((int64_t)blockIdx.x < groups) load(blockIdx.x, 0);
+    if constexpr (MODE != 2) {
+        if ((int64_t)blockIdx.x < groups) load(blockIdx.x, 0);
+    } else {
+        // layer 1 writes only the interior cells: the ring of the tile stays
+        // zero for the whole launch (ordered by the first barrier below)
+        for (int j = threadIdx.x; j < BPB * 4 * (NP - 1) * 4; j += THREADS) {
+            const int bb = j / (4 * (NP - 1) * 4), r = j % (4 * (NP - 1) * 4);
+            const int q = ring_cell<NP>(r >> 2);
+            *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
+        }
+    }
 
     for (int64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
         const int64_t b = grp * BPB + slot;
@@ -680,20 +724,31 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{bv[4 * nt], bv[4 * nt + 1], bv[4 * nt + 2], bv[4 * nt + 3]};
         for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
             __syncthreads();          // the weights are in; the previous half's products are done
-#pragma unroll
-            for (int r = 0; r < XR; ++r) {
-                const int j = threadIdx.x + r * THREADS;
-                if (j < XITEMS) {
-                    const int bb = j / (PP * 4), rem = j % (PP * 4), q = rem >> 2, c8 = rem & 3;
-                    // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4 (bank spread)
-                    *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + ((c8 + (q >> 2)) & 3) * 8) = pre[r];
+            if constexpr (MODE == 2) {
+                if (h == 0) {
+                    code_store<L>(ci, cc);
+                    __syncthreads();
+                    const int64_t ng = grp + gridDim.x;
+                    if (ng < groups) code_load<L>(a1, ng * BPB, n, ci);
                 }
-            }
-            __syncthreads();
-            {
-                // the next (group, half): this group's second half, or the next group's first
-                const int64_t ng = h == 0 ? grp : grp + gridDim.x;
-                if (ng < groups) load(ng, h ^ 1);
+                layer1_half<L>(a1, h, grp * BPB, n, cc, xs);
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int r = 0; r < XR; ++r) {
+                    const int j = threadIdx.x + r * THREADS;
+                    if (j < XITEMS) {
+                        const int bb = j / (PP * 4), rem = j % (PP * 4), q = rem >> 2, c8 = rem & 3;
+                        // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4 (bank spread)
+                        *reinterpret_cast<uint4 *>(xs + (bb * PP + q) * 32 + ((c8 + (q >> 2)) & 3) * 8) = pre[r];
+                    }
+                }
+                __syncthreads();
+                {
+                    // the next (group, half): this group's second half, or the next group's first
+                    const int64_t ng = h == 0 ? grp : grp + gridDim.x;
+                    if (ng < groups) load(ng, h ^ 1);
+                }
             }
             if (!live) continue;
             const uint16_t *xb = xs + slot * PP * 32;
@@ -731,7 +786,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             const int p = pbase + mt * 16;
             if (p >= PIX) continue;
             const int o = (((p / N) + 1) * NP + (p % N) + 1) * C + c0; // 32-bit: cheap to keep
-            store_cell<NTW, MODE>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
+            store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
         }
     }
 }
@@ -1383,10 +1438,10 @@ struct Sizes {
     }
 };
 
-// forward: layers 1 and 2 fused (k_conv_lds MODE 2) at 11x11; at 19x19 the
-// weights-resident kernel for layer 2 is kept
+// forward: layers 1 and 2 fused (MODE 2 of k_conv_lds at 11x11, of the
+// weights-resident k_conv_res at 19x19)
 template <int N>
-constexpr bool FUSE_L1 = N == 11;
+constexpr bool FUSE_L1 = true;
 
 template <int N>
 hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
@@ -1407,9 +1462,13 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     int l0 = 2;
     if constexpr (FUSE_L1<N>) {
         // layers 1 and 2 in one kernel from the boards, layer 1's activations kept in LDS
-        hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
-                           packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n,
-                           L1Args{board, to_move, packed + pf_off(1), params + b_off(1)});
+        const L1Args a1{board, to_move, packed + pf_off(1), params + b_off(1)};
+        if constexpr (N == 19)
+            hipLaunchKernelGGL((k_conv_res<N, 2>), dim3(rb), dim3(LR::THREADS), 0, s, (const uint16_t *)nullptr,
+                               packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
+        else
+            hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
+                               packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
         l0 = 3;
     } else {
         hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
@@ -1422,7 +1481,7 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
         // forward); 11x11: the per-group staging measured faster (3.7 against 3.9 ms)
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n);
+                               params + b_off(l), (const uint16_t *)nullptr, out, n, L1Args{});
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
                                params + b_off(l), (const uint16_t *)nullptr, out, n, L1Args{});
@@ -1471,7 +1530,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     for (int l = 2; l <= 4; ++l) {
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n);
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, L1Args{});
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
                                params + b_off(l), (const uint16_t *)nullptr, y[l], n, L1Args{});
