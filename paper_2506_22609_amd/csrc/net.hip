@@ -338,6 +338,54 @@ __global__ __launch_bounds__(256, 2) void k_conv(const uint16_t *__restrict__ x,
 }
 
 // ---------------------------------------------------------------------------
+// Cells of the 16-lane tiles of the LDS convolutions.  An activation
+// fragment read takes 16 bytes of each of the tile's 16 cells, at a 64-byte
+// cell pitch with the 16-byte chunks rotated by q / 4 (q = the cell's
+// top-left tap in the padded frame): conflict-free exactly when the 16 q
+// cover every residue mod 16, and a tap shifts all of them by one offset.
+// Runs of 16 consecutive board cells cross a row wrap of the padded frame,
+// where two residues repeat (a second pass over the banks).  So lane r of
+// tile t takes the t-th cell in board order with q mod 16 = r.  Entry: q of
+// the lane's cell, or -1 - q0 for a lane left without one (it reads the
+// first filled lane's q0: the same addresses, served by broadcast).
+// ---------------------------------------------------------------------------
+template <int N>
+struct TileCells {
+    static constexpr int NP = N + 2, PIX = N * N, MT = (PIX + 15) / 16;
+    int16_t v[MT * 16];
+    bool ok; // every residue class fits in MT tiles
+    constexpr TileCells() : v{}, ok(true)
+    {
+        int count[16] = {};
+        for (int i = 0; i < MT * 16; ++i) v[i] = -32768;
+        for (int p = 0; p < PIX; ++p) {
+            const int q = (p / N) * NP + p % N, r = q % 16, t = count[r]++;
+            if (t >= MT) ok = false;
+            else v[t * 16 + r] = (int16_t)q;
+        }
+        for (int t = 0; t < MT; ++t) {
+            int first = 0;
+            for (int r = 15; r >= 0; --r)
+                if (v[t * 16 + r] >= 0) first = v[t * 16 + r];
+            for (int r = 0; r < 16; ++r)
+                if (v[t * 16 + r] == -32768) v[t * 16 + r] = (int16_t)(-1 - first);
+        }
+    }
+};
+static_assert(TileCells<11>().ok && TileCells<19>().ok, "tile partition");
+__constant__ TileCells<11> kTiles11 = TileCells<11>();
+__constant__ TileCells<19> kTiles19 = TileCells<19>();
+
+// the entry of lane `row` of tile `mt` (see TileCells)
+template <int N>
+__device__ __forceinline__ int tile_entry(int mt, int row)
+{
+    if constexpr (N == 11) return kTiles11.v[mt * 16 + row];
+    else return kTiles19.v[mt * 16 + row];
+}
+__device__ __forceinline__ int entry_q(int e) { return e >= 0 ? e : -1 - e; }
+
+// ---------------------------------------------------------------------------
 // The 64-channel convolution with both operands in LDS.  Reading A (the
 // activations) straight from memory re-reads every cell once per tap, which
 // leaves the MFMA pipes waiting on the vector memory path; here a block
@@ -509,7 +557,7 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
                                                                      L1Args a1)
 {
     using L = LdsL<N>;
-    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
+    constexpr int NP = L::NP, PP = L::PP, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
     constexpr int NTW = L::NTW;
     __shared__ __align__(16) uint16_t ws[C * WS];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
@@ -522,6 +570,16 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
     const int64_t b = b0 + slot;
     const bool live = b < n;
     const int row = lane & 15, quad = lane >> 4;
+    // this lane's cell in each tile (see TileCells): its top-left tap in the
+    // padded frame, and bit mt set if the lane has a cell in tile mt
+    int cell_off[8];
+    unsigned vmask = 0;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const int e = g * 8 + mt < MT ? tile_entry<N>(g * 8 + mt, row) : -1;
+        cell_off[mt] = entry_q(e);
+        vmask |= (e >= 0 ? 1u : 0u) << mt;
+    }
     // this lane's output channels are c0 .. c0 + 4 NTW - 1; the accumulators
     // start at their bias
     const int c0 = half * 16 * NTW + 4 * NTW * quad;
@@ -583,17 +641,6 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         __syncthreads();
         if (!live) continue;
         const uint16_t *xb = xs + slot * PP * 32;
-        // top-left tap of this lane's cell in each tile (padded cells), formed
-        // per half (an opaque base keeps them out of the layer-1 phase)
-        int pbase = g * 128 + row;
-        asm volatile("" : "+v"(pbase));
-        int cell_off[8];
-#pragma unroll
-        for (int mt = 0; mt < 8; ++mt) {
-            const int p = pbase + mt * 16;
-            const int pc = p < PIX ? p : 0;
-            cell_off[mt] = (pc / N) * NP + (pc % N);
-        }
 #pragma unroll 1
         for (int t = 0; t < 9; ++t) {
             const int toff = (t / 3) * NP + (t % 3);
@@ -620,9 +667,8 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
         if (g * 8 + mt >= MT) break;
-        const int p = (g * 8 + mt) * 16 + row;
-        if (p >= PIX) continue;
-        const int64_t o = (int64_t)(((p / N) + 1) * NP + (p % N) + 1) * C + c0;
+        if (!((vmask >> mt) & 1u)) continue;
+        const int64_t o = (int64_t)(cell_off[mt] + NP + 1) * C + c0; // the cell: one row and column in
         store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
     }
 }
@@ -651,7 +697,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
                                                                      L1Args a1)
 {
     using L = LdsR<N>;
-    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, NG = L::NG, BPB = L::BPB;
+    constexpr int NP = L::NP, PP = L::PP, MT = L::MT, NG = L::NG, BPB = L::BPB;
     constexpr int NTW = L::NTW, THREADS = L::THREADS;
     constexpr int WR = K2 + 8;                           // weight row stride (bf16)
     constexpr int XITEMS = BPB * PP * 4;                 // 16-byte chunks of one (group, half)
@@ -663,12 +709,15 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
     const int row = lane & 15, quad = lane >> 4;
-    int cell_off[8]; // top-left tap of this lane's A row in each tile (padded cells)
+    // this lane's cell in each tile (see TileCells): its top-left tap in the
+    // padded frame, and bit mt set if the lane has a cell in tile mt
+    int cell_off[8];
+    unsigned vmask = 0;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
-        const int p = (g * 8 + mt) * 16 + row;
-        const int pc = p < PIX ? p : 0;
-        cell_off[mt] = (pc / N) * NP + (pc % N);
+        const int e = g * 8 + mt < MT ? tile_entry<N>(g * 8 + mt, row) : -1;
+        cell_off[mt] = entry_q(e);
+        vmask |= (e >= 0 ? 1u : 0u) << mt;
     }
     for (int j = threadIdx.x; j < C * (K2 / 8); j += THREADS) {
         const int o = j / (K2 / 8), r = j % (K2 / 8);
@@ -776,16 +825,15 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
         uint16_t *ob = out + b * (int64_t)PP * C;
         if (g == 0 && half == 0) zero_ring<N>(ob, lane);
         const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
-        // the output cells' offsets are recomputed per group: an opaque base
-        // keeps the compiler from holding all of them across the launch
-        int pbase = g * 128 + row;
-        asm volatile("" : "+v"(pbase));
+        // the output cells' offsets are formed per group from opaque copies:
+        // the compiler would otherwise hold all of them across the launch
 #pragma unroll
         for (int mt = 0; mt < 8; ++mt) {
             if (g * 8 + mt >= MT) break;
-            const int p = pbase + mt * 16;
-            if (p >= PIX) continue;
-            const int o = (((p / N) + 1) * NP + (p % N) + 1) * C + c0; // 32-bit: cheap to keep
+            if (!((vmask >> mt) & 1u)) continue;
+            int co = cell_off[mt];
+            asm volatile("" : "+v"(co));
+            const int o = (co + NP + 1) * C + c0; // the cell itself
             store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
         }
     }
