@@ -420,12 +420,16 @@ using LdsL = LdsConv<N, N <= 13 ? 1 : 2>;
 template <int N>
 using LdsR = LdsConv<N, 2>;
 
-// The layer-1 side of the fused forward (k_conv_lds MODE 2): the boards and
-// sides to move, and layer 1's packed weights and bias.
-struct L1Args {
+// The board and head sides of the fused forward: the boards and sides to
+// move, layer 1's packed weights and bias (MODE 2: layers 1 and 2 in one
+// kernel), and the parameter vector and outputs of the heads (MODE 3: the
+// last layer and the heads in one kernel).
+struct FwdArgs {
     const int8_t *board, *to_move;
     const uint16_t *w1;
     const float *b1;
+    const float *params;
+    float *logits, *value;
 };
 
 // Cell codes of the fused forward: for each board of a block and each cell
@@ -443,7 +447,7 @@ struct CodeIn {
 };
 
 template <class L>
-__device__ __forceinline__ void code_load(const L1Args &a1, int64_t b0, int64_t n, CodeIn<L> &ci)
+__device__ __forceinline__ void code_load(const FwdArgs &a1, int64_t b0, int64_t n, CodeIn<L> &ci)
 {
     constexpr int N = L::SIDE, NP = L::NP, PP = L::PP, PIX = L::PIX, ITEMS = L::BPB * PP;
 #pragma unroll
@@ -472,7 +476,7 @@ __device__ __forceinline__ void code_store(const CodeIn<L> &ci, uint8_t *cc)
 // board: frame cell (r, c) is board cell c N + r), so a layer-1 tap is one
 // byte read.  These are the encoder's planes (mover, opponent, empty, 0).
 template <class L>
-__device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t n, uint8_t *cc)
+__device__ __forceinline__ void cell_codes(const FwdArgs &a1, int64_t b0, int64_t n, uint8_t *cc)
 {
     CodeIn<L> ci;
     code_load<L>(a1, b0, n, ci);
@@ -490,7 +494,7 @@ __device__ __forceinline__ void cell_codes(const L1Args &a1, int64_t b0, int64_t
 // channels as M, so a lane ends with 4 consecutive channels of one cell: one
 // 8-byte LDS write.
 template <class L>
-__device__ __forceinline__ void layer1_half(const L1Args &a1, int h, int64_t b0, int64_t n, const uint8_t *cc,
+__device__ __forceinline__ void layer1_half(const FwdArgs &a1, int h, int64_t b0, int64_t n, const uint8_t *cc,
                                             uint16_t *xs)
 {
     constexpr int N = L::SIDE, NP = L::NP, PP = L::PP, PIX = L::PIX, MT = L::MT, BPB = L::BPB;
@@ -544,21 +548,79 @@ __device__ __forceinline__ void layer1_half(const L1Args &a1, int h, int64_t b0,
     }
 }
 
+// The heads on the last layer's accumulators (k_conv_lds MODE 3), for a
+// wave that holds all 64 channels (NTW = 4, lane channels c0 = 16 quad ..
+// c0 + 15) of all cells of its board b (tiles mt < 8, cell_off / vmask as in
+// k_conv_lds): the layer's output y = bf16(relu(acc)) as the next layer would
+// read it, then per cell the policy logit wp . y + bp (written in action
+// order: player 2's frame is transposed back) and the value
+// tanh(wv . mean over cells of y + bv), the same sums as k_heads.
+template <int N, int NTW>
+__device__ __forceinline__ void heads_epilogue(const f32x4 (&acc)[8][NTW], const int (&cell_off)[8], unsigned vmask,
+                                               int c0, int64_t b, const FwdArgs &a1)
+{
+    static_assert(NTW == 4, "one wave holds all channels of its cells");
+    constexpr int NP = N + 2, PIX = N * N;
+    const int lane = threadIdx.x & 63, quad = lane >> 4;
+    float wp[16], wv[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        wp[j] = a1.params[WP_OFF + c0 + j];
+        wv[j] = a1.params[WV_OFF + c0 + j];
+    }
+    const float bp = a1.params[BP_OFF];
+    const int me = a1.to_move[b];
+    float sv = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const bool valid = (vmask >> mt) & 1u;
+        float lp = 0.f, lv = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
+                lp += y * wp[4 * nt + k];
+                lv += y * wv[4 * nt + k];
+            }
+        // the four quads hold the four 16-channel parts of the same cell
+        lp += __shfl_xor(lp, 16);
+        lp += __shfl_xor(lp, 32);
+        lv += __shfl_xor(lv, 16);
+        lv += __shfl_xor(lv, 32);
+        if (valid) {
+            sv += lv;
+            if (quad == 0) {
+                const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
+                a1.logits[b * PIX + (me == 2 ? c * N + r : r * N + c)] = lp + bp;
+            }
+        }
+    }
+    // the 16 rows of a quad cover all cells of the board once
+#pragma unroll
+    for (int s = 8; s >= 1; s >>= 1) sv += __shfl_xor(sv, s);
+    if (lane == 0) a1.value[b] = tanhf(sv / (float)PIX + a1.params[BV_OFF]);
+}
+
 // MODE 2 (forward of the first two layers): each channel half of layer 1's
 // output is computed by the block from its boards (a1) straight into the LDS
 // tile that layer 2 reads, so layer 1's activations never go to memory; x is
 // unused, w / bias are layer 2's and the output is layer 2's.
+// MODE 3 (the last layer and the heads, 11x11): a forward layer whose output
+// goes through the heads in registers (heads_epilogue) instead of to memory;
+// out is unused, the logits and values go to a1.logits / a1.value.
 template <int N, int MODE>
 __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
                                                                      const float *__restrict__ bias,
                                                                      const uint16_t *__restrict__ mask,
                                                                      uint16_t *__restrict__ out, int64_t n,
-                                                                     L1Args a1)
+                                                                     FwdArgs a1)
 {
     using L = LdsL<N>;
     constexpr int NP = L::NP, PP = L::PP, MT = L::MT, NG = L::NG, BPB = L::BPB, WS = L::WS;
     constexpr int NTW = L::NTW;
+    static_assert(MODE != 3 || (NG == 1 && MT <= 8 && NTW == 4), "MODE 3: one wave holds a whole board");
     __shared__ __align__(16) uint16_t ws[C * WS];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
     // MODE 2: the cell codes of the block's boards
@@ -661,6 +723,10 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
     }
     if (!live) return;
 
+    if constexpr (MODE == 3) {
+        heads_epilogue<N, NTW>(acc, cell_off, vmask, c0, b, a1);
+        return;
+    }
     uint16_t *ob = out + b * (int64_t)PP * C;
     if (g == 0 && half == 0) zero_ring<N>(ob, lane);
     const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
@@ -694,7 +760,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
                                                                      const float *__restrict__ bias,
                                                                      const uint16_t *__restrict__ mask,
                                                                      uint16_t *__restrict__ out, int64_t n,
-                                                                     L1Args a1)
+                                                                     FwdArgs a1)
 {
     using L = LdsR<N>;
     constexpr int NP = L::NP, PP = L::PP, MT = L::MT, NG = L::NG, BPB = L::BPB;
@@ -1510,7 +1576,7 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     int l0 = 2;
     if constexpr (FUSE_L1<N>) {
         // layers 1 and 2 in one kernel from the boards, layer 1's activations kept in LDS
-        const L1Args a1{board, to_move, packed + pf_off(1), params + b_off(1)};
+        const FwdArgs a1{board, to_move, packed + pf_off(1), params + b_off(1)};
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 2>), dim3(rb), dim3(LR::THREADS), 0, s, (const uint16_t *)nullptr,
                                packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
@@ -1524,21 +1590,28 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
                            packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
     }
     uint16_t *in = ya, *out = yb;
-    for (int l = l0; l <= 4; ++l) {
+    // 11x11: the last layer and the heads in one kernel
+    constexpr int LAST = N == 11 ? 3 : 4;
+    for (int l = l0; l <= LAST; ++l) {
         // 19x19: weights resident (measured 9.8 against 10.5 ms per 65536-board
         // forward); 11x11: the per-group staging measured faster (3.7 against 3.9 ms)
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n, L1Args{});
+                               params + b_off(l), (const uint16_t *)nullptr, out, n, FwdArgs{});
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n, L1Args{});
+                               params + b_off(l), (const uint16_t *)nullptr, out, n, FwdArgs{});
         uint16_t *t = in;
         in = out;
         out = t;
     }
-    hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, in, params, to_move, n, logits, (float *)nullptr,
-                       value);
+    if constexpr (N == 11)
+        hipLaunchKernelGGL((k_conv_lds<N, 3>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(4),
+                           params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n,
+                           FwdArgs{nullptr, to_move, nullptr, nullptr, params, logits, value});
+    else
+        hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, in, params, to_move, n, logits, (float *)nullptr,
+                           value);
     return hipGetLastError();
 }
 
@@ -1578,10 +1651,10 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     for (int l = 2; l <= 4; ++l) {
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, L1Args{});
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, FwdArgs{});
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, L1Args{});
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, FwdArgs{});
     }
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
@@ -1603,7 +1676,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
         hipLaunchKernelGGL((k_conv_lds<N, 1>), dim3(lb), dim3(LC::THREADS), 0, s, ga, packed + pb_off(l),
-                           (const float *)nullptr, y[l - 1], gb, n, L1Args{});
+                           (const float *)nullptr, y[l - 1], gb, n, FwdArgs{});
         uint16_t *t = ga;
         ga = gb;
         gb = t;
