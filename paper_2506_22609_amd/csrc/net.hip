@@ -754,6 +754,11 @@ constexpr int RES_BLOCKS = 256; // one per CU
 // MODE 2 as in k_conv_lds: the first two layers, layer 1 computed per group
 // from its cell codes; the next group's board bytes are loaded into
 // registers while the current group is multiplied.
+// MODE 3: the last layer and the heads (see heads_epilogue).  A board's
+// channels and cells are spread over 2 x 3 waves, so each wave adds its
+// per-cell policy partials and its value partial into LDS (float atomics);
+// a finished group is written out after the next group's first barrier
+// (the last one after the loop), and its accumulators are cleared there.
 template <int N, int MODE>
 __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
@@ -771,6 +776,10 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
     __shared__ __align__(16) uint16_t wsr[C * WR];
     __shared__ __align__(16) uint16_t xs[BPB * PP * 32];
     __shared__ uint8_t cc[MODE == 2 ? BPB * PP : 1]; // MODE 2: the group's cell codes
+    // MODE 3: head weights (wp, wv), the group's logit and value sums
+    __shared__ float hw[MODE == 3 ? 2 * C : 1];
+    __shared__ float hl[MODE == 3 ? BPB * L::PIX : 1];
+    __shared__ float hv[MODE == 3 ? BPB : 1];
 
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
@@ -817,6 +826,31 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
                          : uint4{0u, 0u, 0u, 0u};
         }
     };
+    if constexpr (MODE == 3) { // ordered by the first barrier below
+        for (int j = threadIdx.x; j < 2 * C; j += THREADS)
+            hw[j] = a1.params[(j < C ? WP_OFF : WV_OFF) + (j & (C - 1))];
+        for (int j = threadIdx.x; j < BPB * L::PIX; j += THREADS) hl[j] = 0.f;
+        if (threadIdx.x < BPB) hv[threadIdx.x] = 0.f;
+    }
+    // MODE 3: write out the sums of group pg and clear them (after a barrier)
+    auto flush = [&](int64_t pg) {
+        constexpr int PIX = L::PIX;
+        const float bp = a1.params[BP_OFF], bvv = a1.params[BV_OFF];
+        for (int j = threadIdx.x; j < BPB * PIX; j += THREADS) {
+            const int bb = j / PIX, p = j % PIX;
+            const int64_t bo = pg * BPB + bb;
+            if (bo < n) {
+                const int me = a1.to_move[bo], r = p / N, c = p % N;
+                a1.logits[bo * PIX + (me == 2 ? c * N + r : p)] = hl[j] + bp;
+            }
+            hl[j] = 0.f;
+        }
+        if (threadIdx.x < BPB) {
+            const int64_t bo = pg * BPB + threadIdx.x;
+            if (bo < n) a1.value[bo] = tanhf(hv[threadIdx.x] / (float)PIX + bvv);
+            hv[threadIdx.x] = 0.f;
+        }
+    };
     if constexpr (MODE != 2) {
         if ((int64_t)blockIdx.x < groups) load(blockIdx.x, 0);
     } else {
@@ -839,6 +873,10 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = f32x4{bv[4 * nt], bv[4 * nt + 1], bv[4 * nt + 2], bv[4 * nt + 3]};
         for (int h = 0; h < 2; ++h) { // input channels 32h .. 32h+31
             __syncthreads();          // the weights are in; the previous half's products are done
+            if constexpr (MODE == 3) {
+                // the previous group's head sums are complete (its epilogue came before this barrier)
+                if (h == 0 && grp != (int64_t)blockIdx.x) flush(grp - gridDim.x);
+            }
             if constexpr (MODE == 2) {
                 if (h == 0) {
                     code_store<L>(ci, cc);
@@ -888,6 +926,38 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             }
         }
         if (!live) continue;
+        if constexpr (MODE == 3) {
+            // this lane's 4 NTW channels of each of its cells: policy and value dots
+            float sv = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < 8; ++mt) {
+                if (g * 8 + mt >= MT) break;
+                float lp = 0.f, lv = 0.f;
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
+                        lp += y * hw[c0 + 4 * nt + k];
+                        lv += y * hw[C + c0 + 4 * nt + k];
+                    }
+                lp += __shfl_xor(lp, 16); // the four quads: the same cell
+                lp += __shfl_xor(lp, 32);
+                lv += __shfl_xor(lv, 16);
+                lv += __shfl_xor(lv, 32);
+                if ((vmask >> mt) & 1u) {
+                    sv += lv;
+                    if (quad == 0) {
+                        const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
+                        atomicAdd(&hl[slot * L::PIX + r * N + c], lp);
+                    }
+                }
+            }
+#pragma unroll
+            for (int s2 = 8; s2 >= 1; s2 >>= 1) sv += __shfl_xor(sv, s2); // the 16 rows
+            if (lane == 0) atomicAdd(&hv[slot], sv);
+            continue;
+        }
         uint16_t *ob = out + b * (int64_t)PP * C;
         if (g == 0 && half == 0) zero_ring<N>(ob, lane);
         const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
@@ -902,6 +972,12 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             const int o = (co + NP + 1) * C + c0; // the cell itself
             store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
         }
+    }
+    if constexpr (MODE == 3) {
+        // the block's last group
+        const int64_t mine = (int64_t)blockIdx.x < groups ? (groups - 1 - blockIdx.x) / gridDim.x : -1;
+        __syncthreads();
+        if (mine >= 0) flush((int64_t)blockIdx.x + mine * gridDim.x);
     }
 }
 
@@ -1552,66 +1628,41 @@ struct Sizes {
     }
 };
 
-// forward: layers 1 and 2 fused (MODE 2 of k_conv_lds at 11x11, of the
-// weights-resident k_conv_res at 19x19)
-template <int N>
-constexpr bool FUSE_L1 = true;
-
 template <int N>
 hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
                      int64_t n, float *logits, float *value, void *ws, hipStream_t s)
 {
     using S = Sizes<N>;
-    constexpr int MT = (S::PIX + 15) / 16, NG = (MT + 7) / 8;
     Carve cv{static_cast<char *>(ws)};
-    uint2 *a0 = cv.take<uint2>(S::a0(n));
+    cv.take<uint2>(S::a0(n)); // the input planes' share of the workspace (unused by the fused forward)
     uint16_t *ya = cv.take<uint16_t>(S::act(n));
     uint16_t *yb = cv.take<uint16_t>(S::act(n));
-    const unsigned eb = (unsigned)((n * S::PP + 255) / 256), cb = (unsigned)((n * NG + 3) / 4),
-                   hb = (unsigned)((n + 3) / 4);
     using LC = LdsL<N>;
     using LR = LdsR<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
     const unsigned rb = (unsigned)blocks_min((n + LR::BPB - 1) / LR::BPB, RES_BLOCKS);
-    int l0 = 2;
-    if constexpr (FUSE_L1<N>) {
-        // layers 1 and 2 in one kernel from the boards, layer 1's activations kept in LDS
-        const FwdArgs a1{board, to_move, packed + pf_off(1), params + b_off(1)};
-        if constexpr (N == 19)
-            hipLaunchKernelGGL((k_conv_res<N, 2>), dim3(rb), dim3(LR::THREADS), 0, s, (const uint16_t *)nullptr,
-                               packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
-        else
-            hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
-                               packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
-        l0 = 3;
+    // Three kernels: layers 1 + 2 from the boards (layer 1's activations kept
+    // in LDS), layer 3, layer 4 + the heads (layer 4's activations kept in
+    // registers).  19x19: the weights-resident kernel (measured 9.8 against
+    // 10.5 ms per 65536-board forward); 11x11: the per-group staging measured
+    // faster (3.7 against 3.9 ms).
+    const FwdArgs a1{board, to_move, packed + pf_off(1), params + b_off(1), nullptr, nullptr, nullptr};
+    const FwdArgs ah{nullptr, to_move, nullptr, nullptr, params, logits, value};
+    if constexpr (N == 19) {
+        hipLaunchKernelGGL((k_conv_res<N, 2>), dim3(rb), dim3(LR::THREADS), 0, s, (const uint16_t *)nullptr,
+                           packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
+        hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, ya, packed + pf_off(3),
+                           params + b_off(3), (const uint16_t *)nullptr, yb, n, FwdArgs{});
+        hipLaunchKernelGGL((k_conv_res<N, 3>), dim3(rb), dim3(LR::THREADS), 0, s, yb, packed + pf_off(4),
+                           params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n, ah);
     } else {
-        hipLaunchKernelGGL(k_encode<N>, dim3(eb), dim3(256), 0, s, board, to_move, n, a0);
-        hipLaunchKernelGGL((k_conv<N, 4, 0>), dim3(cb), dim3(256), 0, s, reinterpret_cast<const uint16_t *>(a0),
-                           packed + pf_off(1), params + b_off(1), (const uint16_t *)nullptr, ya, n);
+        hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
+                           packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
+        hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, ya, packed + pf_off(3),
+                           params + b_off(3), (const uint16_t *)nullptr, yb, n, FwdArgs{});
+        hipLaunchKernelGGL((k_conv_lds<N, 3>), dim3(lb), dim3(LC::THREADS), 0, s, yb, packed + pf_off(4),
+                           params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n, ah);
     }
-    uint16_t *in = ya, *out = yb;
-    // 11x11: the last layer and the heads in one kernel
-    constexpr int LAST = N == 11 ? 3 : 4;
-    for (int l = l0; l <= LAST; ++l) {
-        // 19x19: weights resident (measured 9.8 against 10.5 ms per 65536-board
-        // forward); 11x11: the per-group staging measured faster (3.7 against 3.9 ms)
-        if constexpr (N == 19)
-            hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n, FwdArgs{});
-        else
-            hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, out, n, FwdArgs{});
-        uint16_t *t = in;
-        in = out;
-        out = t;
-    }
-    if constexpr (N == 11)
-        hipLaunchKernelGGL((k_conv_lds<N, 3>), dim3(lb), dim3(LC::THREADS), 0, s, in, packed + pf_off(4),
-                           params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n,
-                           FwdArgs{nullptr, to_move, nullptr, nullptr, params, logits, value});
-    else
-        hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, in, params, to_move, n, logits, (float *)nullptr,
-                           value);
     return hipGetLastError();
 }
 

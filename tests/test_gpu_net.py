@@ -51,7 +51,7 @@ def _net(N, seed):
     return net, p.astype(np.float64)
 
 
-@pytest.mark.parametrize("N,n", [(11, 70), (11, 1), (19, 21)])
+@pytest.mark.parametrize("N,n", [(11, 70), (11, 1), (11, 3), (19, 21), (19, 1)])
 def test_forward_matches_oracle(N, n):
     g, s = _states(ref.HEX, N, n, 1 + N)
     net, p = _net(N, 2)
