@@ -703,21 +703,65 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         __syncthreads();
         if (!live) continue;
         const uint16_t *xb = xs + slot * PP * 32;
-#pragma unroll 1
-        for (int t = 0; t < 9; ++t) {
-            const int toff = (t / 3) * NP + (t % 3);
-            bf16x8 bfr[NTW];
+        // the 9 taps.  With all 64 channels in the wave (and registers to
+        // spare: not MODE 2), unrolled, tap t + 1's fragments read from LDS
+        // while tap t's products run; else one tap at a time.
+        constexpr bool PIPE = NTW == 4 && MODE != 2;
+        auto frag_b = [&](int t, bf16x8 (&bf)[NTW]) {
 #pragma unroll
             for (int nt = 0; nt < NTW; ++nt)
-                bfr[nt] = as_bf16x8(*reinterpret_cast<const uint4 *>(ws + ((half * NTW + nt) * 16 + row) * WS + t * 32 + quad * 8));
+                bf[nt] = as_bf16x8(
+                    *reinterpret_cast<const uint4 *>(ws + ((half * NTW + nt) * 16 + row) * WS + t * 32 + quad * 8));
+        };
+        auto frag_a = [&](int t, bf16x8 (&af)[8]) {
+            const int toff = (t / 3) * NP + (t % 3);
 #pragma unroll
-            for (int mt = 0; mt < 8; ++mt) {
-                if (g * 8 + mt >= MT) break;
-                const int q = cell_off[mt] + toff;
-                const bf16x8 a = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
+            for (int mt = 0; mt < 8; ++mt)
+                if (g * 8 + mt < MT) {
+                    const int q = cell_off[mt] + toff;
+                    af[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
+                }
+        };
+        if constexpr (PIPE) {
+            bf16x8 bcur[NTW], acur[8], bnxt[NTW], anxt[8];
+            frag_b(0, bcur);
+            frag_a(0, acur);
 #pragma unroll
-                for (int nt = 0; nt < NTW; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], a, acc[mt][nt], 0, 0, 0);
+            for (int t = 0; t < 9; ++t) {
+                if (t + 1 < 9) {
+                    frag_b(t + 1, bnxt);
+                    frag_a(t + 1, anxt);
+                }
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt)
+                    if (g * 8 + mt < MT)
+#pragma unroll
+                        for (int nt = 0; nt < NTW; ++nt)
+                            acc[mt][nt] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(bcur[nt], acur[mt], acc[mt][nt], 0, 0, 0);
+                if (t + 1 < 9) {
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt) bcur[nt] = bnxt[nt];
+#pragma unroll
+                    for (int mt = 0; mt < 8; ++mt) acur[mt] = anxt[mt];
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int t = 0; t < 9; ++t) {
+                const int toff = (t / 3) * NP + (t % 3);
+                bf16x8 bf[NTW];
+                frag_b(t, bf);
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt) {
+                    if (g * 8 + mt >= MT) break;
+                    const int q = cell_off[mt] + toff;
+                    const bf16x8 a =
+                        as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
+#pragma unroll
+                    for (int nt = 0; nt < NTW; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[nt], a, acc[mt][nt], 0, 0, 0);
+                }
             }
         }
     }
