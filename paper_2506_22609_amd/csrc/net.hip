@@ -1094,11 +1094,12 @@ __global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ 
 {
     constexpr int NP = N + 2, PP = NP * NP, PIX = N * N, QL = (PIX + 63) / 64;
     __shared__ float hw[2 * C];
+    __shared__ float dsh[4][PIX]; // each wave's logit gradients, for the gradient pass
     if (threadIdx.x < C) hw[threadIdx.x] = p[WP_OFF + threadIdx.x];
     else if (threadIdx.x < 2 * C) hw[threadIdx.x] = p[WV_OFF + threadIdx.x - C];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * 4 + wave;
     if (b >= n) return;
     const int me = to_move[b];
     const int act = action[b];
@@ -1152,24 +1153,32 @@ __global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ 
         }
         d *= inv_n;
         dlog[b * PIX + q] = d;
-        const int64_t o = (int64_t)((q / N + 1) * NP + (q % N) + 1) * C;
-        const uint4 *src = reinterpret_cast<const uint4 *>(yb + o);
-        uint4 *dst = reinterpret_cast<uint4 *>(gb + o);
+        dsh[wave][q] = d;
+    }
+    // dZ4 = [y4 > 0] (d wp + dv wv), 8 cells at a time: lane = (cell, 16-byte
+    // chunk of 8 channels), so each load and store covers whole 128-byte cells
+    // (the wave's own LDS writes above come first in its instruction order)
+    const int sub = lane >> 3, k = lane & 7;
+    float wp8[8], wv8[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint4 yv = src[k];
-            const uint32_t wd[4] = {yv.x, yv.y, yv.z, yv.w};
-            uint32_t od[4];
+    for (int i = 0; i < 8; ++i) {
+        wp8[i] = hw[8 * k + i];
+        wv8[i] = hw[C + 8 * k + i];
+    }
+    for (int q = sub; q < PIX; q += 8) {
+        const float d = dsh[wave][q];
+        const int64_t o = (int64_t)((q / N + 1) * NP + (q % N) + 1) * C + 8 * k;
+        const uint4 yv = *reinterpret_cast<const uint4 *>(yb + o);
+        const uint32_t wd[4] = {yv.x, yv.y, yv.z, yv.w};
+        uint32_t od[4];
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int c0 = k * 8 + 2 * h;
-                const uint16_t y0 = (uint16_t)(wd[h] & 0xFFFFu), y1 = (uint16_t)(wd[h] >> 16);
-                const float g0 = (y0 != 0 && (y0 & 0x8000u) == 0) ? d * hw[c0] + dv * hw[C + c0] : 0.f;
-                const float g1 = (y1 != 0 && (y1 & 0x8000u) == 0) ? d * hw[c0 + 1] + dv * hw[C + c0 + 1] : 0.f;
-                od[h] = (uint32_t)f2bf(g0) | ((uint32_t)f2bf(g1) << 16);
-            }
-            dst[k] = uint4{od[0], od[1], od[2], od[3]};
+        for (int h = 0; h < 4; ++h) {
+            const uint16_t y0 = (uint16_t)(wd[h] & 0xFFFFu), y1 = (uint16_t)(wd[h] >> 16);
+            const float g0 = (y0 != 0 && (y0 & 0x8000u) == 0) ? d * wp8[2 * h] + dv * wv8[2 * h] : 0.f;
+            const float g1 = (y1 != 0 && (y1 & 0x8000u) == 0) ? d * wp8[2 * h + 1] + dv * wv8[2 * h + 1] : 0.f;
+            od[h] = (uint32_t)f2bf(g0) | ((uint32_t)f2bf(g1) << 16);
         }
+        *reinterpret_cast<uint4 *>(gb + o) = uint4{od[0], od[1], od[2], od[3]};
     }
 }
 
@@ -1195,12 +1204,17 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t *__restrict__
         const uint16_t *yb = y4 + b * (int64_t)PP * C;
         const float *db = dlog + b * PIX;
         float mv = 0.f;
-        for (int q = 0; q < PIX; ++q) {
-            const float y = bf2f(yb[(int64_t)((q / N + 1) * NP + (q % N) + 1) * C + c]);
-            const float d = db[q];
-            ap += d * y;
-            mv += y;
-            sp += d; // every lane adds the same sum; lane 0's is kept
+        for (int r = 0; r < N; ++r) { // cells in order, a row's loads issued together
+            const uint16_t *yr = yb + (int64_t)((r + 1) * NP + 1) * C + c;
+            const float *dr = db + r * N;
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const float y = bf2f(yr[q * C]);
+                const float d = dr[q];
+                ap += d * y;
+                mv += y;
+                sp += d; // every lane adds the same sum; lane 0's is kept
+            }
         }
         av += du[b] * mv / (float)PIX;
         sv += du[b];
@@ -1573,7 +1587,13 @@ __global__ __launch_bounds__(256) void k_sum_rows(const float *__restrict__ part
     const int j = blockIdx.x * 32 + cl;
     float s = 0.f;
     if (j < cols)
-        for (int64_t r = grp; r < rows; r += 8) s += part[r * stride + j];
+        for (int64_t r = grp; r < rows; r += 64) { // 8 rows' loads in flight at a time
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = r + 8 * k < rows ? part[(r + 8 * k) * stride + j] : 0.f;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += v[k];
+        }
     red[grp][cl] = s;
     __syncthreads();
     if (grp == 0 && j < cols) {
@@ -1589,9 +1609,16 @@ __global__ __launch_bounds__(256) void k_sum_loss(const float *__restrict__ term
 {
     __shared__ float red[2][256];
     float a = 0.f, b = 0.f;
-    for (int64_t r = threadIdx.x; r < n; r += 256) {
-        a += terms[2 * r];
-        b += terms[2 * r + 1];
+    for (int64_t r = threadIdx.x; r < n; r += 8 * 256) { // 8 pairs' loads in flight at a time
+        float2 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            v[k] = r + 256 * k < n ? reinterpret_cast<const float2 *>(terms)[r + 256 * k] : float2{0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a += v[k].x;
+            b += v[k].y;
+        }
     }
     red[0][threadIdx.x] = a;
     red[1][threadIdx.x] = b;
