@@ -330,8 +330,8 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
         base.to_move.copy_(e.to_move)
         base.ply.copy_((e.board != 0).sum(1).to(torch.int16))
         sub = 2048
-        judge = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
-        tr = learn.truth(g, judge, 256, seed=seed + 950, id_base=2 * 10**9)
+        held = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
+        tr = learn.truth(g, held, 256, seed=seed + 950, id_base=2 * 10**9)
         est = torch.empty(n, dtype=torch.float32, device="cuda")
         timings = {}
         for name in ("plain_full_playout", "value_budgeted"):
@@ -358,7 +358,7 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
                                    "mse_vs_256_playout_mean": timings["plain_full_playout_mse"]},
             "value_budgeted": {"playouts_per_s": n / timings["value_budgeted"],
                                "mse_vs_256_playout_mean": timings["value_budgeted_mse"]}}
-        del base, judge, net
+        del base, held, net
         torch.cuda.synchronize()
     return res
 
@@ -469,8 +469,8 @@ def _learned_section(seed: int, train_games: int, steps: int):
     base.to_move.copy_(e.to_move)
     base.ply.copy_((e.board != 0).sum(1).to(torch.int16))
     sub = 4096
-    judge = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
-    tr = learn.truth(g, judge, 256, seed=seed + 300, id_base=2 * 10**9)
+    held = ludax.State.from_tensors(g, **{f: getattr(base, f)[:sub].contiguous() for f in ludax.State.FIELDS})
+    tr = learn.truth(g, held, 256, seed=seed + 300, id_base=2 * 10**9)
 
     r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
     t = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -492,7 +492,7 @@ def _learned_section(seed: int, train_games: int, steps: int):
         return net.estimate(s)
 
     out = {"workload": f"hex11x11: training on {train_games} random games, {steps} Adam steps of 4096; "
-                       f"{n} held-out positions (error judged on {sub} of them against 256 full random "
+                       f"{n} held-out positions (error measured on {sub} of them against 256 full random "
                        f"playouts each)",
            "collect_s": t_collect, "train_s": t_train, "train_ms_per_step": t_train / steps * 1e3,
            "train_tflops": 3 * 4096 * flops_fwd / (t_train / steps) / 1e12,
@@ -575,8 +575,9 @@ def main():
                          "(a known-size reference for HBM byte counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (the playouts are independent per game; "
-              f"--gpus {args.gpus} is not supported by this build)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} asked for more): the playouts are independent "
+              f"per game, and how the batch would shard over GPUs is described with the design, not run here",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
