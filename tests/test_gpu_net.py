@@ -77,6 +77,24 @@ def test_forward_large_batch_sampled(N, n):
     close(value.cpu().numpy()[idx], f["value"])
 
 
+@pytest.mark.parametrize("N,n", [(11, 65536), (19, 20000)])
+def test_forward_bench_scale_sampled(N, n):
+    """The forward at the benchmark's batch sizes (11x11: 16384 four-board
+    blocks; 19x19: each of the 256 weights-resident blocks walks about 39
+    two-board groups, writing out the head sums of each), checked on a sample
+    of boards.  The boards are seeded random fillings (the network reads any
+    cell values 0 / 1 / 2 and either side to move; legality plays no part)."""
+    rng = np.random.default_rng(31 + N)
+    board = rng.integers(0, 3, size=(n, N * N), dtype=np.int8)
+    to_move = rng.integers(1, 3, size=n, dtype=np.int8)
+    net, p = _net(N, 12)
+    logits, value = net.forward(torch.from_numpy(board).cuda(), torch.from_numpy(to_move).cuda())
+    idx = np.unique(np.r_[rng.choice(n, 24, replace=False), 0, 1, 511, 512, n - 2, n - 1])
+    f = R.forward(p, board[idx], to_move[idx], N, bf16=True)
+    close(logits.cpu().numpy()[idx], f["logits"])
+    close(value.cpu().numpy()[idx], f["value"])
+
+
 @pytest.mark.parametrize("kind", [ref.HEX, ref.GOMOKU], ids=["hex", "gomoku"])
 @pytest.mark.parametrize("N,n", [(11, 67), (19, 9)])
 def test_loss_and_gradient_match_oracle(kind, N, n):
