@@ -493,30 +493,43 @@ __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &o
                                             E *moves, int t)
 {
     using M = typename G::M;
-    // Hex and Tic-Tac-Toe: the legal cells are the empty cells, so the empty
-    // set and its size are carried from ply to ply (the chosen cell's bit
-    // leaves one and joins the mover's stones); Connect Four recomputes its
-    // legal cells, which a placement can add to.
+    // The legal set and its size are carried from ply to ply (the chosen
+    // cell's bit leaves it and joins the mover's stones).  Hex and
+    // Tic-Tac-Toe: the legal cells are the empty cells.  Connect Four: the
+    // lowest empty cell of each column, so the cell above the chosen one
+    // (one row stride up) joins the set, or the set shrinks when a column
+    // fills.
     constexpr bool EMPTY_IS_LEGAL = G::KIND == 1 || G::KIND == 3;
+    constexpr bool CARRY = EMPTY_IS_LEGAL || G::KIND == 2;
     M open = bb_zero<G::NWI>();
     int n_open = 0;
-    if constexpr (EMPTY_IS_LEGAL) {
+    if constexpr (CARRY) {
         open = G::open_cells(cur, oth);
         n_open = popcount(open);
     }
     auto play = [&](M &mine, const M &theirs, int j, uint32_t w) {
-        if constexpr (EMPTY_IS_LEGAL) {
+        if constexpr (CARRY) {
             int wi;
             uint32_t bit;
             select_bit_split(open, (int)__umulhi(w, (uint32_t)n_open), wi, bit);
-            moves[j * BLOCK + t] = (E)(32 * wi + __builtin_ctz(bit));
+            const int b = 32 * wi + __builtin_ctz(bit);
+            moves[j * BLOCK + t] = (E)b;
             static_for<G::NWI>([&](auto I) {
                 constexpr int i = I;
                 const uint32_t x = wi == i ? bit : 0u;
                 mine.w[i] |= x;
                 open.w[i] ^= x;
             });
-            --n_open;
+            if constexpr (EMPTY_IS_LEGAL) {
+                --n_open;
+            } else {
+                const int up = b - G::S; // the cell above (same column, one row up)
+                static_for<G::NWI>([&](auto I) {
+                    constexpr int i = I;
+                    open.w[i] |= (up >= 0 && (up >> 5) == i) ? 1u << (up & 31) : 0u;
+                });
+                n_open -= up < 0 ? 1 : 0;
+            }
         } else {
             const int b = select_uniform(G::open_cells(mine, theirs), w);
             moves[j * BLOCK + t] = (E)b;
