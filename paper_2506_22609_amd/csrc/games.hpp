@@ -452,15 +452,27 @@ struct Gomoku {
 
     __device__ M placements(int) const { return and_mask<Valid, NBITS, NWI>(~(p1 | p2)); }
 
-    // starts of maximal runs of exactly five along step D
+    // starts i of runs of five or more along step D (i .. i+4D all set)
     template <int D>
-    __device__ static bool five_along(const M &x)
+    __device__ static M five_plus(const M &x)
     {
-        const M a1 = x & shr<D>(x);         // i, i+D
-        const M a2 = a1 & shr<2 * D>(a1);   // i .. i+3D
-        const M a3 = a2 & shr<4 * D>(x);    // i .. i+4D
-        const M e = andnot(andnot(a3, shl<D>(x)), shr<5 * D>(x));
-        return any(e);
+        const M a1 = x & shr<D>(x);       // i, i+D
+        const M a2 = a1 & shr<2 * D>(a1); // i .. i+3D
+        return a2 & shr<4 * D>(x);        // i .. i+4D
+    }
+    // among those, a run of exactly five: neither i-D nor i+5D set
+    template <int D>
+    __device__ static bool exact_five(const M &x, const M &a3)
+    {
+        return any(andnot(andnot(a3, shl<D>(x)), shr<5 * D>(x)));
+    }
+    // a run of exactly five in some direction; the exactness shifts run only
+    // where some run of five or more exists (in a game, at its last ply)
+    __device__ static bool any_exact_five(const M &x)
+    {
+        const M h = five_plus<1>(x), v = five_plus<S>(x), d1 = five_plus<S - 1>(x), d2 = five_plus<S + 1>(x);
+        if (!any(h | v | d1 | d2)) return false;
+        return exact_five<1>(x, h) | exact_five<S>(x, v) | exact_five<S - 1>(x, d1) | exact_five<S + 1>(x, d2);
     }
 
     __device__ int place(int b, int me, int &extra)
@@ -468,8 +480,7 @@ struct Gomoku {
         M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
         p1 = pick(me == 1, own, p1);
         p2 = pick(me == 1, p2, own);
-        if (five_along<1>(own) | five_along<S>(own) | five_along<S - 1>(own) | five_along<S + 1>(own))
-            return me;
+        if (any_exact_five(own)) return me;
         if (popcount(p1 | p2) == CELLS) return 0;
         return -1;
     }
