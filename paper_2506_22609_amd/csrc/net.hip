@@ -1669,6 +1669,12 @@ namespace {
 
 constexpr int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 constexpr int WG_BLOCKS = 256;  // blocks of the conv weight-gradient reductions
+// blocks of the first layer's weight gradient: its partial sums are small
+// (64 x 27 + 64 floats) and its blocks light enough for two per CU, so more
+// blocks (fewer boards each) keep more loads in flight; the partials still
+// fit the 64-channel layers' buffer
+constexpr int WG1_BLOCKS = 512;
+static_assert((int64_t)WG1_BLOCKS * (C * 27 + C) <= (int64_t)WG_BLOCKS * (C * C * 9 + C), "partials");
 constexpr int HW_BLOCKS = 1024; // blocks of the head weight-gradient reduction
 
 int64_t blocks_min(int64_t n, int64_t cap) { return n < cap ? n : cap; }
@@ -1803,8 +1809,9 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         ga = gb;
         gb = t;
     }
-    hipLaunchKernelGGL((k_conv_wgrad<N, 4>), dim3(wb), dim3(256), 0, s, ga, y[0], n, part);
-    hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART4, PART4,
+    const unsigned wb1 = (unsigned)blocks_min(n, WG1_BLOCKS);
+    hipLaunchKernelGGL((k_conv_wgrad<N, 4>), dim3(wb1), dim3(256), 0, s, ga, y[0], n, part);
+    hipLaunchKernelGGL(k_sum_rows, dim3((PART4 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb1, PART4, PART4,
                        grads + w_off(1));
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(256), 0, s, lterms, n, loss);
     return hipGetLastError();
