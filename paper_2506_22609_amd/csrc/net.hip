@@ -81,6 +81,9 @@ constexpr int K1 = 64, K2 = 576;
 __host__ __device__ constexpr int64_t pf_off(int l) { return l == 1 ? 0 : (int64_t)C * K1 + (int64_t)(l - 2) * C * K2; }
 __host__ __device__ constexpr int64_t pb_off(int l) { return (int64_t)C * K1 + 3 * (int64_t)C * K2 + (int64_t)(l - 2) * C * K2; }
 constexpr int64_t PACKED_ELEMS = (int64_t)C * K1 + 6 * (int64_t)C * K2;
+// 16 zero bytes inside the packed weights: layer 1's row 0 at k = 40 .. 47
+// (taps 10 and 11, past the 9 taps, are packed as zeros)
+__host__ __device__ inline const uint16_t *zero16(const uint16_t *packed) { return packed + pf_off(1) + 40; }
 
 __global__ void k_pack(const float *__restrict__ p, uint16_t *__restrict__ out)
 {
@@ -430,6 +433,12 @@ struct FwdArgs {
     const float *b1;
     const float *params;
     float *logits, *value;
+    // Every LDS convolution takes the zero ring of its input from zero16 (16
+    // zero bytes) instead of from memory, so an output's ring is written only
+    // when ring != 0: the training forward, whose activations the weight
+    // gradients read with their taps.
+    const uint16_t *zero16;
+    int ring;
 };
 
 // Cell codes of the fused forward: for each board of a block and each cell
@@ -680,11 +689,12 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
                     // chunk c8 of cell q sits at chunk position (c8 + q / 4) mod 4: the 16 cells
                     // a fragment read touches then fall on 16 different LDS bank groups
                     const int i = base + lane, bb = i / (PP * 4), q = (i % (PP * 4)) >> 2;
-                    const int c8 = ((i & 3) - (q >> 2)) & 3;
+                    const int c8 = ((i & 3) - (q >> 2)) & 3, qr = q / NP, qc = q % NP;
+                    const bool ring = qr == 0 || qr == NP - 1 || qc == 0 || qc == NP - 1;
                     const int64_t bsrc = b0 + bb < n ? b0 + bb : b0; // a board past the end: any valid one
+                    const uint16_t *src = ring ? a1.zero16 : x + (bsrc * PP + q) * C + h * 32 + c8 * 8;
                     if (i < XCH)
-                        __builtin_amdgcn_global_load_lds((glb_void *)(x + (bsrc * PP + q) * C + h * 32 + c8 * 8),
-                                                         (lds_void *)(xs + base * 8), 16, 0, 0);
+                        __builtin_amdgcn_global_load_lds((glb_void *)src, (lds_void *)(xs + base * 8), 16, 0, 0);
                 }
             }
         }
@@ -772,7 +782,7 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         return;
     }
     uint16_t *ob = out + b * (int64_t)PP * C;
-    if (g == 0 && half == 0) zero_ring<N>(ob, lane);
+    if (g == 0 && half == 0 && a1.ring) zero_ring<N>(ob, lane);
     const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
 #pragma unroll
     for (int mt = 0; mt < 8; ++mt) {
@@ -864,8 +874,9 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
         const int64_t left = (n - grp * BPB) * (int64_t)PP * 4; // chunks of live boards
 #pragma unroll
         for (int r = 0; r < XR; ++r) {
-            const int j = threadIdx.x + r * THREADS;
-            pre[r] = j < XITEMS && j < left
+            const int j = threadIdx.x + r * THREADS, q = (j >> 2) % PP, qr = q / NP, qc = q % NP;
+            const bool ring = qr == 0 || qr == NP - 1 || qc == 0 || qc == NP - 1; // zeros, not read
+            pre[r] = j < XITEMS && j < left && !ring
                          ? *reinterpret_cast<const uint4 *>(base + (int64_t)(j >> 2) * C + (j & 3) * 8)
                          : uint4{0u, 0u, 0u, 0u};
         }
@@ -1003,7 +1014,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             continue;
         }
         uint16_t *ob = out + b * (int64_t)PP * C;
-        if (g == 0 && half == 0) zero_ring<N>(ob, lane);
+        if (g == 0 && half == 0 && a1.ring) zero_ring<N>(ob, lane);
         const uint16_t *mb = MODE == 1 ? mask + b * (int64_t)PP * C : nullptr;
         // the output cells' offsets are formed per group from opaque copies:
         // the compiler would otherwise hold all of them across the launch
@@ -1723,20 +1734,22 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     // registers).  19x19: the weights-resident kernel (measured 9.8 against
     // 10.5 ms per 65536-board forward); 11x11: the per-group staging measured
     // faster (3.7 against 3.9 ms).
-    const FwdArgs a1{board, to_move, packed + pf_off(1), params + b_off(1), nullptr, nullptr, nullptr};
-    const FwdArgs ah{nullptr, to_move, nullptr, nullptr, params, logits, value};
+    const uint16_t *z = zero16(packed);
+    const FwdArgs a1{board, to_move, packed + pf_off(1), params + b_off(1), nullptr, nullptr, nullptr, z, 0};
+    const FwdArgs ah{nullptr, to_move, nullptr, nullptr, params, logits, value, z, 0};
+    const FwdArgs a3{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, z, 0};
     if constexpr (N == 19) {
         hipLaunchKernelGGL((k_conv_res<N, 2>), dim3(rb), dim3(LR::THREADS), 0, s, (const uint16_t *)nullptr,
                            packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
         hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, ya, packed + pf_off(3),
-                           params + b_off(3), (const uint16_t *)nullptr, yb, n, FwdArgs{});
+                           params + b_off(3), (const uint16_t *)nullptr, yb, n, a3);
         hipLaunchKernelGGL((k_conv_res<N, 3>), dim3(rb), dim3(LR::THREADS), 0, s, yb, packed + pf_off(4),
                            params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n, ah);
     } else {
         hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
                            packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
         hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, ya, packed + pf_off(3),
-                           params + b_off(3), (const uint16_t *)nullptr, yb, n, FwdArgs{});
+                           params + b_off(3), (const uint16_t *)nullptr, yb, n, a3);
         hipLaunchKernelGGL((k_conv_lds<N, 3>), dim3(lb), dim3(LC::THREADS), 0, s, yb, packed + pf_off(4),
                            params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n, ah);
     }
@@ -1776,13 +1789,17 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
     using LR = LdsR<N>;
     const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
     const unsigned rb = (unsigned)blocks_min((n + LR::BPB - 1) / LR::BPB, RES_BLOCKS);
+    // forward layers write their rings (the weight gradients read them); the
+    // data gradients' rings are never read from memory
+    const FwdArgs fr{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, zero16(packed), 1};
+    const FwdArgs fd{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, zero16(packed), 0};
     for (int l = 2; l <= 4; ++l) {
         if constexpr (N == 19)
             hipLaunchKernelGGL((k_conv_res<N, 0>), dim3(rb), dim3(LR::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, FwdArgs{});
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, fr);
         else
             hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, y[l - 1], packed + pf_off(l),
-                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, FwdArgs{});
+                               params + b_off(l), (const uint16_t *)nullptr, y[l], n, fr);
     }
     hipLaunchKernelGGL(k_heads<N>, dim3(hb), dim3(256), 0, s, y[4], params, to_move, n, logits, lframe, value);
     hipLaunchKernelGGL(k_heads_bwd<N>, dim3(hb), dim3(256), 0, s, y[4], a0, params, lframe, value, to_move,
@@ -1804,7 +1821,7 @@ hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t
         hipLaunchKernelGGL(k_sum_rows, dim3((PART64 + 31) / 32), dim3(256), 0, s, part, (int64_t)wb, PART64,
                            PART64, grads + w_off(l));
         hipLaunchKernelGGL((k_conv_lds<N, 1>), dim3(lb), dim3(LC::THREADS), 0, s, ga, packed + pb_off(l),
-                           (const float *)nullptr, y[l - 1], gb, n, FwdArgs{});
+                           (const float *)nullptr, y[l - 1], gb, n, fd);
         uint16_t *t = ga;
         ga = gb;
         gb = t;
