@@ -121,7 +121,7 @@ def conv3x3(x, w, bias=None):
     out = np.zeros((n, w.shape[0], N, N))
     for dr in range(3):
         for dc in range(3):
-            out += np.einsum("nihw,oi->nohw", xp[:, :, dr:dr + N, dc:dc + N], w[:, :, dr, dc])
+            out += np.einsum("nihw,oi->nohw", xp[:, :, dr:dr + N, dc:dc + N], w[:, :, dr, dc], optimize=True)
     if bias is not None:
         out += bias[None, :, None, None]
     return out
@@ -135,8 +135,8 @@ def conv3x3_backward(x, w, dz):
     dw = np.zeros_like(w)
     for dr in range(3):
         for dc in range(3):
-            dxp[:, :, dr:dr + N, dc:dc + N] += np.einsum("nohw,oi->nihw", dz, w[:, :, dr, dc])
-            dw[:, :, dr, dc] = np.einsum("nohw,nihw->oi", dz, xp[:, :, dr:dr + N, dc:dc + N])
+            dxp[:, :, dr:dr + N, dc:dc + N] += np.einsum("nohw,oi->nihw", dz, w[:, :, dr, dc], optimize=True)
+            dw[:, :, dr, dc] = np.einsum("nohw,nihw->oi", dz, xp[:, :, dr:dr + N, dc:dc + N], optimize=True)
     return dxp[:, :, 1:N + 1, 1:N + 1], dw, dz.sum(axis=(0, 2, 3))
 
 

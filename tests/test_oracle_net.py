@@ -261,3 +261,63 @@ def test_float32_sums_move_the_gradient_by_less_than_a_quarter_of_the_gpu_tolera
             e = np.linalg.norm(g32[o:o + k] - g64[o:o + k]) / np.linalg.norm(g64[o:o + k])
             assert e < 1.1e-3, (name, e)
         o += k
+
+
+def test_adam_several_steps_match_torch_optim_adam():
+    """Five Adam steps of the oracle (bias correction at every step, not
+    only the first) against torch.optim.Adam in float64 on the same
+    gradients: the two implementations put eps after the bias-corrected
+    square root alike, so they agree to float64 rounding."""
+    rng = np.random.default_rng(21)
+    p0 = rng.standard_normal(300)
+    grads = [rng.standard_normal(300) * 10.0 ** rng.integers(-4, 1) for _ in range(5)]
+    t = torch.from_numpy(p0.copy()).requires_grad_()
+    opt = torch.optim.Adam([t], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    q, m, v = p0.copy(), np.zeros(300), np.zeros(300)
+    for k, g in enumerate(grads):
+        t.grad = torch.from_numpy(g.copy())
+        opt.step()
+        q, m, v = R.adam(q, g, m, v, k + 1, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8)
+        assert np.allclose(q, t.detach().numpy(), rtol=0, atol=1e-15), k
+    st = opt.state[t]
+    assert np.allclose(m, st["exp_avg"].numpy(), rtol=1e-14, atol=0)
+    assert np.allclose(v, st["exp_avg_sq"].numpy(), rtol=1e-14, atol=0)
+
+
+def test_policy_action_boundaries():
+    """Hand cases of the draw rule: a single legal action is always played;
+    two equal logits split the unit interval at one half, u = 1/2 itself
+    going to the second action (the first running sum must EXCEED u times
+    the total); illegal actions are never played."""
+    lg = np.array([0.3, 9.0, 0.3, -2.0], np.float32)
+    legal = np.array([True, False, True, False])
+    for w in (0, 1 << 31, 0xFFFFFFFF):
+        assert R.policy_action(lg, np.array([False, False, True, False]), w)[0] == 2
+    half = (1 << 23) << 8  # u = 2^23 / 2^24
+    assert R.policy_action(lg, legal, half - 256)[0] == 0
+    assert R.policy_action(lg, legal, half)[0] == 2
+    assert R.policy_action(lg, legal, 0)[0] == 0
+    assert R.policy_action(lg, legal, 0xFFFFFFFF)[0] == 2
+
+
+def test_policy_action_draws_follow_masked_softmax():
+    """The law of the policy draw over Philox words (the oracle's generator,
+    pinned by the known-answer vectors) is the masked softmax of the
+    logits: a chi-square test of 60000 draws over the legal actions of a
+    row with logits spread over several units (1 % level)."""
+    from scipy.stats import chisquare
+
+    rng = np.random.default_rng(22)
+    A = 12
+    lg = (rng.standard_normal(A) * 1.5).astype(np.float32)
+    legal = rng.random(A) < 0.7
+    legal[[1, 7]] = True
+    p = R.masked_softmax(lg[None].astype(np.float64), legal[None])[0]
+    draws = 60000
+    counts = np.zeros(A, np.int64)
+    for j in range(draws // 4):
+        for w in ref.philox([j, 0, 0, 0], [5, 0]):
+            counts[R.policy_action(lg, legal, int(w))[0]] += 1
+    assert counts[~legal].sum() == 0
+    idx = np.flatnonzero(legal)
+    assert chisquare(counts[idx], p[idx] * draws).pvalue > 0.01
