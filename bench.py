@@ -39,31 +39,104 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # a 256 MiB copy (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
 HEX_TRAFFIC_BYTES = 19.93e6
 HBM_PEAK_GBS = 8000.0
+# DRAM bytes (read + written) per env-step of the per-ply loop, from the
+# FETCH_SIZE / WRITE_SIZE counters of every ludax_random_step dispatch of one
+# loop, each scaled by what the counter reads for a 1 GiB device copy in the
+# same profiled run (profiles/random_step_hex19_n1048576_hbm_bytes.txt).
+DRAM_BYTES_PER_ENV_STEP = {}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _cpu_baseline(batches, budget_s: float):
-    """The oracle as it stands, on the host's cores, over whole batches of
-    the same workload until about budget_s seconds have elapsed."""
+    """The oracle as it stands on the host's cores: 3 warm-up and then at
+    least 20 timed batches of the same workload (distinct game ids), with
+    all the process's cores and with one thread; each batch's rate is
+    recorded and the median and standard deviation reported.  The
+    one-thread batches hold 4096 envs per game (a whole 65536-env batch
+    takes seconds on one core; the oracle's per-env cost does not depend
+    on the batch size).  budget_s bounds the timed batches of each leg."""
+    import statistics
+
     from oracle import ref
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 64))
-    steps, t0, reps = 0, time.perf_counter(), 0
-    while True:
-        for b in batches:
-            g = ref.Game(b.kind, b.rows, b.cols)
-            s = ref.init(g, b.n)
-            _, _, st = ref.playout(g, s, 1, b.n * (1000 + reps), threads=cores)
-            steps += int(st[0])
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 50:
-            break
-    return {"value": steps / el, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} x ({' + '.join(b.name for b in batches)}), full batches, "
-                      f"{steps} env-steps in {el:.1f} s"}
+
+    def leg(threads: int, n_env: int, budget: float):
+        rates, steps_total, el_total, k = [], 0, 0.0, 0
+        while len(rates) < 20 or (el_total < budget and len(rates) < 200):
+            steps, t0 = 0, time.perf_counter()
+            for b in batches:
+                g = ref.Game(b.kind, b.rows, b.cols)
+                s = ref.init(g, n_env)
+                _, _, st = ref.playout(g, s, 1, n_env * (1000 + k), threads=threads)
+                steps += int(st[0])
+            el = time.perf_counter() - t0
+            if k >= 3:
+                rates.append(steps / el)
+                steps_total += steps
+                el_total += el
+            k += 1
+        return {"median": statistics.median(rates), "std": statistics.pstdev(rates), "batches": len(rates),
+                "envs_per_game": n_env, "threads": threads, "env_steps": steps_total, "seconds": el_total}
+
+    full = leg(cores, batches[0].n, 0.5 * budget_s)
+    one = leg(1, 4096, 0.5 * budget_s)
+    names = " + ".join(b.name for b in batches)
+    return {"value": full["median"], "unit": "env-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{full['batches']} timed batches of ({names}) after 3 warm-up batches, "
+                      f"median of the per-batch rates",
+            "cpu_model": _cpu_model(), "compiler": "gcc -O2 -std=c11 (oracle/ludax_ref.c), pthreads",
+            "all_cores": full, "one_thread": one}
+
+
+def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: int = 3, steps: int = 20):
+    """The benchmark step repeated per seed: warm-up steps, then `steps`
+    steps each bracketed by events on the stream (both batches: init,
+    playout, counters), fresh game ids every step; per seed the median and
+    standard deviation of the per-step env-steps/s."""
+    import statistics
+
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    stream = torch.cuda.current_stream()
+    out = {}
+    for seed in seeds:
+        st = torch.zeros((steps, len(batches), 4), dtype=torch.int64, device="cuda")
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for k in range(warmup + steps):
+            rec = k >= warmup
+            if rec:
+                evs[k - warmup][0].record(stream)
+            for j, (b, g, s, r, t) in enumerate(zip(batches, games, states, rewards, terms)):
+                ludax.init(g, s, stream=stream)
+                ludax.playout(g, s, seed, W.game_id_base(1000 + k, b), reward=r, terminal=t,
+                              stats=st[k - warmup, j] if rec else None, stream=stream)
+            if rec:
+                evs[k - warmup][1].record(stream)
+        torch.cuda.synchronize()
+        env_steps = st[:, :, 0].sum(dim=1).cpu().tolist()
+        ms = [a.elapsed_time(c) for a, c in evs]
+        rates = [e / (m / 1e3) for e, m in zip(env_steps, ms)]
+        out[f"seed{seed}"] = {"median_env_steps_per_s": statistics.median(rates),
+                              "std_env_steps_per_s": statistics.pstdev(rates),
+                              "median_ms_per_step": statistics.median(ms), "std_ms_per_step": statistics.pstdev(ms),
+                              "steps": steps, "warmup": warmup}
+    return out
 
 
 def _mixed_section(seed: int, steps: int, warmup: int):
@@ -165,25 +238,41 @@ def _copy_peak_gbs(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * (mib << 20) / sec / 1e9
 
 
-def _plain_step_section(batches, seed: int, reps: int):
+def _alg_bytes_per_env_step(game, aux: bool) -> int:
+    """Algorithmic HBM bytes of one env-step of the per-ply loop.  Without
+    the cache: the board and 8 B of scalars read; 8 B of scalars, 2 B
+    reward, 1 B terminal and the 1-byte board delta written (cells + 20 B).
+    With Hex's component cache: the two players' stones (8 B per 32 cells),
+    the 4-byte tag and 8 B of scalars read; the scalars, reward, terminal,
+    board delta, the changed 4-byte stone word, the tag and the new stone's
+    2-byte parent entry written (the joins' parent reads and writes are
+    data dependent and not counted)."""
+    if not aux:
+        return game.cells + 20
+    nwc = (game.cells + 31) // 32
+    return (8 * nwc + 4 + 8) + (8 + 3 + 1 + 4 + 4 + 2)
+
+
+def _plain_step_section(cases, seed: int, reps: int):
     """The per-ply loop with the state in HBM between plies: ludax_init,
     then ludax_random_step launched max_plies times (the game's natural
     bound, so every game ends inside the loop), captured in one graph per
-    batch and replayed.  Algorithmic HBM bytes: per env-step the board and
-    8 B of scalars read, 8 B of scalars + 2 B reward + 1 B terminal + the
-    1-byte board delta written (cells + 20 B); per env the init writes
-    cells + 8 B.  The replay time includes the launches of the tail, when
-    few games are still running, and the gaps between graph nodes.  The
-    achieved rate is given as a fraction of the nominal HBM peak and of the
-    measured stream-copy rate ("copy_peak_GBs")."""
+    batch and replayed.  cases: (batch, aux) pairs; aux = the Hex component
+    cache (ludax_state.aux).  The replay time includes the launches of the
+    tail, when few games are still running, and the gaps between graph
+    nodes.  The achieved rate of algorithmic bytes is given as a fraction
+    of the nominal HBM peak and of the measured stream-copy rate
+    ("copy_peak_GBs"); where the profile of the per-ply kernels measured
+    DRAM bytes per env-step (DRAM_BYTES_PER_ENV_STEP), their rate too
+    ("hbm_frac_dram")."""
     import torch
     from paper_2506_22609_amd import ludax
 
     copy_gbs = _copy_peak_gbs()
     out = {"copy_peak_GBs": copy_gbs}
-    for b in batches:
+    for b, aux in cases:
         g = ludax.Game(b.kind, b.rows, b.cols)
-        s = ludax.State(g, b.n)
+        s = ludax.State(g, b.n, aux=aux)
         r = torch.empty((b.n, 2), dtype=torch.int8, device="cuda")
         t = torch.empty(b.n, dtype=torch.uint8, device="cuda")
         st = torch.zeros(4, dtype=torch.int64, device="cuda")
@@ -219,13 +308,23 @@ def _plain_step_section(batches, seed: int, reps: int):
             graph.replay()
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / reps
-        alg = steps * (g.cells + 20) + b.n * (g.cells + 8)
-        out[b.name] = {"launches": g.max_plies, "env_steps": steps, "ms_per_loop": el * 1e3,
-                       "env_steps_per_s": steps / el, "alg_bytes_per_env_step": g.cells + 20,
-                       "alg_bytes_per_loop": alg, "achieved_GBs": alg / el / 1e9,
-                       "hbm_frac": alg / el / 1e9 / HBM_PEAK_GBS,
-                       "hbm_frac_of_copy": alg / el / 1e9 / copy_gbs,
-                       "still_running_after_loop": running_after}
+        per = _alg_bytes_per_env_step(g, aux)
+        init_bytes = b.n * (g.cells + 8) + (b.n * (16 + 8 * ((g.cells + 31) // 32)) if aux else 0)
+        alg = steps * per + init_bytes
+        name = b.name + ("_aux" if aux else "")
+        res = {"launches": g.max_plies, "aux": bool(aux), "state_bytes": b.n * (g.cells + 8)
+               + (b.n * g.aux_bytes if aux else 0), "env_steps": steps, "ms_per_loop": el * 1e3,
+               "env_steps_per_s": steps / el, "alg_bytes_per_env_step": per,
+               "alg_bytes_per_loop": alg, "achieved_GBs": alg / el / 1e9,
+               "hbm_frac": alg / el / 1e9 / HBM_PEAK_GBS,
+               "hbm_frac_of_copy": alg / el / 1e9 / copy_gbs,
+               "still_running_after_loop": running_after}
+        dram = DRAM_BYTES_PER_ENV_STEP.get(name)
+        if dram is not None:
+            res["dram_bytes_per_env_step"] = dram
+            res["dram_GBs"] = dram * steps / el / 1e9
+            res["hbm_frac_dram"] = dram * steps / el / 1e9 / HBM_PEAK_GBS
+        out[name] = res
         del graph, s
         torch.cuda.synchronize()
     return out
@@ -679,6 +778,7 @@ def main():
                    "envs_per_batch": batches[0].n, "seed": args.seed, "per_game": per},
         "roofline": roofline,
     }
+    out["protocol"] = _protocol(batches, games, states, rewards, terms)
     sec = set(x for x in args.sections.split(",") if x)
     if args.no_mixed:
         sec.discard("mixed")
@@ -691,8 +791,11 @@ def main():
     if "mixed" in sec:
         out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
     if "plain_step" in sec:
-        out["plain_step"] = _plain_step_section(
-            tuple(batches) + (W.LARGE_BATCHES if "large" in sec else ()), args.seed, args.section_reps)
+        cases = [(b, False) for b in batches]
+        if "large" in sec:
+            cases += [(b, False) for b in W.LARGE_BATCHES] + [(W.HEX19_524288, True), (W.HEX19_1M, False),
+                                                            (W.HEX19_1M, True)]
+        out["plain_step"] = _plain_step_section(cases, args.seed, args.section_reps)
     if "large" in sec:
         out["large"] = _large_section(W.LARGE_BATCHES, args.seed, args.section_reps)
     if "more_games" in sec:

@@ -44,7 +44,7 @@
  *                      empty diagonal neighbour.  The wolf wins on reaching
  *                      the bottom row; a player left without a legal move
  *                      after the opponent's ply loses.  Natural ply bound 56.
- *   LUDAX_DRAUGHTS     8x8 English Draughts (App. B listing): pawns (1, 2)
+ *   LUDAX_DRAUGHTS     8x8 English Draughts (App. A listing): pawns (1, 2)
  *                      step diagonally forward (player 1 up, player 2 down)
  *                      or hop over an adjacent opponent piece into the empty
  *                      cell beyond and capture it; kings (cell value owner |
@@ -160,8 +160,25 @@ typedef struct {
                              (see above), 0 otherwise */
     int16_t *ply;         /* [n] plies applied since the start */
     int16_t *last_action; /* [n] last applied action, -1 before the first */
-    void    *aux;         /* reserved; may be NULL (no game needs it: aux_bytes = 0) */
+    void    *aux;         /* NULL, or [n][aux_bytes] device bytes (16-byte aligned) of a
+                             library-private per-env cache; see "aux" below */
 } ludax_state;
+
+/* aux: Hex keeps its connected components from ply to ply (Sec. 4, dynamic
+ * state attributes: the `connected` end rule is served by a component
+ * array that each move updates locally).  For Hex, aux_bytes > 0 and a
+ * non-NULL state.aux holds, per env, both players' stones as bitboards and
+ * a union-find over the stones with the side flags of each component.
+ * ludax_init writes it; ludax_step, ludax_random_step and ludax_policy_step
+ * then read the stones from it instead of the board and decide the end
+ * test by joining the new stone to its neighbours' components (the board
+ * is still updated, results are identical to aux = NULL).  Every call that
+ * changes the state must pass the same aux; after any other change (a call
+ * with aux = NULL, ludax_playout, a copy of states from elsewhere) call
+ * ludax_aux_sync, or pass aux = NULL.  As a safeguard the cache records the
+ * (ply, last_action) it belongs to, and a step that finds them changed
+ * rebuilds that env's cache from the board first.  Every other call and
+ * game ignores aux (aux_bytes = 0). */
 
 /* Build a game handle.  Host only, no device work.  *out is set on
  * success; release it with ludax_game_destroy. */
@@ -169,14 +186,16 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out);
 int ludax_game_destroy(ludax_game *game);
 
 /* Shapes of a game: cells = rows*cols, num_actions = A, aux_bytes per env
- * (always 0 here), max_plies after resolving 0 to the natural bound.  Any
- * output pointer may be NULL. */
+ * (Hex: the size of its component cache, a multiple of 16; 0 for the other
+ * games), max_plies after resolving 0 to the natural bound.  Any output
+ * pointer may be NULL. */
 int ludax_game_info(const ludax_game *game, int32_t *cells, int32_t *num_actions,
                     int32_t *aux_bytes, int32_t *max_plies);
 
 /* Start position (Sec. 3.1 start rules) for all n environments: empty
  * board (Reversi: the four start discs; the movement games: their start
- * pieces), to_move 1, RUNNING, winner -1, passes 0, ply 0, last_action -1. */
+ * pieces), to_move 1, RUNNING, winner -1, passes 0, ply 0, last_action -1;
+ * and the start of state.aux when it is used (Hex). */
 int ludax_init(const ludax_game *game, ludax_state *state, int64_t n, hipStream_t stream);
 
 /* Legal-action mask (Sec. 3.2: each play mechanic defines one of fixed
@@ -256,6 +275,12 @@ int ludax_policy_step(const ludax_game *game, ludax_state *state, const float *l
  * what ludax_playout's stats argument adds. */
 int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t sign, int64_t *stats,
                       int64_t n, hipStream_t stream);
+
+/* Rebuild the aux cache of all n environments from their boards (Hex;
+ * Sec. 4's component array recomputed from scratch, the lowest cell of each
+ * component its root).  A no-op for games with aux_bytes = 0;
+ * LUDAX_E_INVALID if the game has a cache and state.aux is NULL. */
+int ludax_aux_sync(const ludax_game *game, ludax_state *state, int64_t n, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Mixed persistent batch.  Several rule sets share the device in one call:
@@ -374,6 +399,23 @@ int ludax_net_adam(const ludax_net *net, float *params, const float *grads, floa
  * (rows = cols = N of the net). */
 int ludax_net_estimate(const ludax_net *net, const float *params, const void *packed, const ludax_state *state,
                        int64_t n, float *estimate, void *workspace, hipStream_t stream);
+
+/* One network-guided ply of every env (the move proposal of Sec. 7's
+ * learned policy, fused into the step): the forward pass of this net on the
+ * env's board, then exactly ludax_policy_step with those logits -- the same
+ * Philox word, the same running-sum draw over the legal placements in
+ * increasing action order, the same rules and outputs -- but the logits
+ * never leave the chip: the kernel of the last layer and the heads writes
+ * them to LDS and one lane per env draws and plays the ply there.  Results
+ * are identical to ludax_net_forward followed by ludax_policy_step.
+ * Supported: the 11x11 net with Hex 11x11 or Gomoku 11x11 (else
+ * LUDAX_E_UNSUPPORTED).  reward [n][2], terminal [n] as in ludax_step; game
+ * ids as in ludax_playout; workspace as for ludax_net_forward (inference
+ * size of n).  A state with an aux cache is stepped without it (the cache's
+ * tag check rebuilds it in a later step). */
+int ludax_net_guided_step(const ludax_net *net, const float *params, const void *packed, const ludax_game *game,
+                          ludax_state *state, uint64_t seed, int64_t game_id_base, const int64_t *game_id,
+                          int8_t *reward, uint8_t *terminal, int64_t n, void *workspace, hipStream_t stream);
 
 /* Text of a return code; never NULL. */
 const char *ludax_strerror(int code);

@@ -21,7 +21,7 @@
  *                 four in a row wins / three in a row (without four) loses,
  *                 Pente's five in a row or ten captured stones.
  *   movement      Sec. 3.2 (move mechanic: step, hop; hop priority over
- *                 step; capture, promotion and extra-turn effects), the App. B
+ *                 step; capture, promotion and extra-turn effects), the App. A
  *                 English Draughts listing (start cells, effect order, end
  *                 rule) and the App. C rule texts of Wolf and Sheep and
  *                 English Draughts.
@@ -197,7 +197,7 @@ static void init_env(const game_t *g, env_t *e)
         e->board[3] = 2;
     }
     if (g->kind == LUDAX_REF_DRAUGHTS) {
-        /* the start cells of the App. B listing: the dark cells of rows 5-7
+        /* the start cells of the App. A listing: the dark cells of rows 5-7
          * for player 1 and of rows 0-2 for player 2 */
         static const int P1[12] = {40, 42, 44, 46, 49, 51, 53, 55, 56, 58, 60, 62};
         static const int P2[12] = {1, 3, 5, 7, 8, 10, 12, 14, 17, 19, 21, 23};
@@ -336,7 +336,7 @@ static const int DIAG4[4][2] = {{-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
 
 /* Legal moves of the player to move: pieces of `me` (only the piece on
  * passes - 1 during a Draughts extra turn); the hops if there is any hop
- * (hop priority 0 over step priority 1, App. B listing), else the steps.
+ * (hop priority 0 over step priority 1, App. A listing), else the steps.
  * Marks m[src * cells + dst] and returns the number of moves. */
 static int move_legal(const game_t *g, const env_t *e, uint8_t *m)
 {
@@ -665,7 +665,7 @@ static void shogi_captures(const game_t *g, env_t *e, int dst, int me)
 }
 
 /* A legal move of a movement game and its effects (Sec. 3.2; the order of
- * the App. B Draughts listing: move and capture, then promotion, then the
+ * the App. A Draughts listing: move and capture, then promotion, then the
  * extra-turn test).  Returns the player who moves next. */
 static int apply_move(const game_t *g, env_t *e, int a, int me)
 {

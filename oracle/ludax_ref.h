@@ -47,7 +47,7 @@
  *     on 56, 58, 60, 62, player 2's wolf (value 2) on 3; the wolf wins on
  *     reaching the bottom row (checked before the blocking rule).  A sheep
  *     moves at most 7 times, so a game has at most 56 plies.
- *   - English Draughts (App. B listing, App. C): cell value = owner | 4 for
+ *   - English Draughts (App. A listing, App. C): cell value = owner | 4 for
  *     a king (1, 2 pawns; 5, 6 kings); pawns start on the cells the listing
  *     gives.  After a ply, a pawn on the far row becomes a king; then, if
  *     the ply was a hop and the same piece can hop again, the mover takes an

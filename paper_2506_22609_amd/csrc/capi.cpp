@@ -69,8 +69,10 @@ int device_error(hipError_t e)
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-// Common checks of a state argument; fills the device view.
-int check_state(const ludax_state *s, lx::DevState *d)
+// Common checks of a state argument; fills the device view.  aux is kept
+// only for a game with a per-env cache (aux_bytes > 0), and must then be
+// 16-byte aligned.
+int check_state(const ludax_state *s, lx::DevState *d, int aux_bytes = 0)
 {
     if (s == nullptr || s->board == nullptr || s->to_move == nullptr || s->status == nullptr ||
         s->winner == nullptr || s->passes == nullptr || s->ply == nullptr || s->last_action == nullptr)
@@ -83,6 +85,8 @@ int check_state(const ludax_state *s, lx::DevState *d)
     d->passes = s->passes;
     d->ply = s->ply;
     d->last_action = s->last_action;
+    d->aux = aux_bytes > 0 ? static_cast<uint8_t *>(s->aux) : nullptr;
+    if (d->aux != nullptr && !aligned16(d->aux)) return LUDAX_E_INVALID;
     return LUDAX_OK;
 }
 
@@ -151,7 +155,7 @@ int ludax_game_info(const ludax_game *game, int32_t *cells, int32_t *num_actions
     if (game == nullptr) return LUDAX_E_INVALID;
     if (cells) *cells = game->cells;
     if (num_actions) *num_actions = game->num_actions;
-    if (aux_bytes) *aux_bytes = 0;
+    if (aux_bytes) *aux_bytes = game->ops->aux_bytes;
     if (max_plies) *max_plies = game->max_plies;
     return LUDAX_OK;
 }
@@ -161,7 +165,7 @@ int ludax_init(const ludax_game *game, ludax_state *state, int64_t n, hipStream_
     if (game == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
     if (n == 0) return LUDAX_OK;
     lx::DevState d;
-    int rc = check_state(state, &d);
+    int rc = check_state(state, &d, game->ops->aux_bytes);
     if (rc) return rc;
     return device_error(game->ops->init(d, n, stream));
 }
@@ -187,7 +191,7 @@ int ludax_step(const ludax_game *game, ludax_state *state, const int32_t *action
         (next_mask != nullptr && !aligned16(next_mask)))
         return LUDAX_E_INVALID;
     lx::DevState d;
-    int rc = check_state(state, &d);
+    int rc = check_state(state, &d, game->ops->aux_bytes);
     if (rc) return rc;
     return device_error(
         game->ops->step(d, n, game->max_plies, action, reward, terminal, next_mask, stream));
@@ -215,7 +219,7 @@ int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed,
     if (n == 0) return LUDAX_OK;
     if (reward == nullptr || terminal == nullptr) return LUDAX_E_INVALID;
     lx::DevState d;
-    int rc = check_state(state, &d);
+    int rc = check_state(state, &d, game->ops->aux_bytes);
     if (rc) return rc;
     return device_error(game->ops->random_step(d, n, game->max_plies, seed, game_id_base, game_id, reward,
                                                terminal, stream));
@@ -229,7 +233,7 @@ int ludax_policy_step(const ludax_game *game, ludax_state *state, const float *l
     if (n == 0) return LUDAX_OK;
     if (logits == nullptr || reward == nullptr || terminal == nullptr) return LUDAX_E_INVALID;
     lx::DevState d;
-    int rc = check_state(state, &d);
+    int rc = check_state(state, &d, game->ops->aux_bytes);
     if (rc) return rc;
     return device_error(game->ops->policy_step(d, n, game->max_plies, logits, seed, game_id_base, game_id, reward,
                                                terminal, stream));
@@ -245,6 +249,17 @@ int ludax_state_stats(const ludax_game *game, const ludax_state *state, int32_t 
     int rc = check_state(state, &d);
     if (rc) return rc;
     return device_error(lx::launch_stats(d, n, sign, stats, stream));
+}
+
+int ludax_aux_sync(const ludax_game *game, ludax_state *state, int64_t n, hipStream_t stream)
+{
+    if (game == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (n == 0 || game->ops->aux_bytes == 0) return LUDAX_OK;
+    lx::DevState d;
+    int rc = check_state(state, &d, game->ops->aux_bytes);
+    if (rc) return rc;
+    if (d.aux == nullptr) return LUDAX_E_INVALID;
+    return device_error(game->ops->aux_sync(d, n, stream));
 }
 
 struct ludax_mixed {
@@ -595,6 +610,25 @@ int ludax_net_estimate(const ludax_net *net, const float *params, const void *pa
         workspace == nullptr || !aligned256(workspace))
         return LUDAX_E_INVALID;
     return device_error(lx::net_estimate(net->n, params, packed, d, n, estimate, workspace, stream));
+}
+
+int ludax_net_guided_step(const ludax_net *net, const float *params, const void *packed, const ludax_game *game,
+                          ludax_state *state, uint64_t seed, int64_t game_id_base, const int64_t *game_id,
+                          int8_t *reward, uint8_t *terminal, int64_t n, void *workspace, hipStream_t stream)
+{
+    if (net == nullptr || game == nullptr || n < 0 || n > MAX_ENVS) return LUDAX_E_INVALID;
+    if (net->n != 11 || game->desc.rows != 11 || game->desc.cols != 11 ||
+        (game->desc.kind != LUDAX_HEX && game->desc.kind != LUDAX_GOMOKU))
+        return LUDAX_E_UNSUPPORTED;
+    if (n == 0) return LUDAX_OK;
+    lx::DevState d;
+    int rc = check_state(state, &d);
+    if (rc) return rc;
+    if (params == nullptr || packed == nullptr || !aligned16(packed) || reward == nullptr || terminal == nullptr ||
+        workspace == nullptr || !aligned256(workspace))
+        return LUDAX_E_INVALID;
+    return device_error(lx::net_guided_step(net->n, params, packed, d, game->desc.kind, n, game->max_plies, seed,
+                                            game_id_base, game_id, reward, terminal, workspace, stream));
 }
 
 const char *ludax_strerror(int code)

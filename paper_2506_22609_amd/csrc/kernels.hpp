@@ -26,6 +26,7 @@
 #include <type_traits>
 
 #include "games.hpp"
+#include "hexaux.hpp"
 #include "ludax_internal.hpp"
 
 namespace lx {
@@ -187,6 +188,61 @@ __global__ __launch_bounds__(BLOCK) void k_mask(DevState st, int64_t n, uint8_t 
     stage_out(reinterpret_cast<int8_t *>(mask) + e0 * G::A, nb * G::A, lds);
 }
 
+// The action of one ply of a RUNNING env with legal placements m: the
+// caller's (MODE 0), the uniform-random one of a3 (MODE 1), or the policy
+// draw from the softmax of the env's logits (lg: its row, in action order)
+// over the legal placements (MODE 2).  `legal` reports whether the action
+// may be applied, `is_pass` whether it is Reversi's PASS.
+template <class G, int MODE>
+__device__ __forceinline__ int choose_action(const typename G::M &m, int ply, int64_t ec,
+                                             const int32_t *__restrict__ action, const float *lg,
+                                             uint32_t key0, uint32_t key1, int64_t gid_base,
+                                             const int64_t *__restrict__ gid, bool &legal, bool &is_pass)
+{
+    int a = 0;
+    if constexpr (MODE >= 1) {
+        // the ply's word of the game's Philox stream
+        const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
+        const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
+        const int r = ply & 3;
+        const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
+        const int np = popcount(m);
+        is_pass = G::HAS_PASS && np == 0;
+        legal = np > 0 || is_pass; // a hand-edited board may leave no action
+        if constexpr (MODE == 1) {
+            // uniform: the k-th legal action, k = (w * n_legal) >> 32
+            if (np > 0) a = G::action_of(select_bit(m, (int)__umulhi(w, (uint32_t)np)));
+        } else {
+            // softmax of the logits over the legal placements (float32,
+            // in increasing action order): the first action whose running
+            // sum of exp(logit - max) exceeds u * total, u = (w >> 8) / 2^24
+            float mx = -3.0e38f;
+            for (int c = 0; c < G::CELLS; ++c)
+                if (test_bit(m, G::bit_of(c))) mx = fmaxf(mx, lg[c]);
+            float tot = 0.f;
+            for (int c = 0; c < G::CELLS; ++c)
+                if (test_bit(m, G::bit_of(c))) tot += expf(lg[c] - mx);
+            const float thr = (float)(w >> 8) * 0x1p-24f * tot;
+            float run = 0.f;
+            int pick = -1, lastc = -1;
+            for (int c = 0; c < G::CELLS; ++c)
+                if (test_bit(m, G::bit_of(c))) {
+                    run += expf(lg[c] - mx);
+                    lastc = c;
+                    if (pick < 0 && run > thr) pick = c;
+                }
+            if (np > 0) a = pick >= 0 ? pick : lastc;
+        }
+        if (is_pass) a = G::A - 1;
+    } else {
+        a = action[ec];
+        is_pass = G::HAS_PASS && a == G::A - 1;
+        if (is_pass) legal = !any(m);
+        else legal = a >= 0 && a < G::CELLS && test_bit(m, G::bit_of(a));
+    }
+    return a;
+}
+
 // ---------------------------------------------------------------------------
 // a4-a6 for one ply: ludax_step (caller-chosen action, MODE 0),
 // ludax_random_step (the uniform-random action of a3, MODE 1) and
@@ -247,47 +303,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
     if (was_running) {
         const typename G::M m = g.placements(me);
         bool legal, is_pass;
-        if constexpr (MODE >= 1) {
-            // the ply's word of the game's Philox stream
-            const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
-            const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
-            const int r = ply & 3;
-            const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
-            const int np = popcount(m);
-            is_pass = G::HAS_PASS && np == 0;
-            legal = np > 0 || is_pass; // a hand-edited board may leave no action
-            if constexpr (MODE == 1) {
-                // uniform: the k-th legal action, k = (w * n_legal) >> 32
-                if (np > 0) a = G::action_of(select_bit(m, (int)__umulhi(w, (uint32_t)np)));
-            } else {
-                // softmax of the logits over the legal placements (float32,
-                // in increasing action order): the first action whose running
-                // sum of exp(logit - max) exceeds u * total, u = (w >> 8) / 2^24
-                const float *lg = logits + ec * G::A;
-                float mx = -3.0e38f;
-                for (int c = 0; c < G::CELLS; ++c)
-                    if (test_bit(m, G::bit_of(c))) mx = fmaxf(mx, lg[c]);
-                float tot = 0.f;
-                for (int c = 0; c < G::CELLS; ++c)
-                    if (test_bit(m, G::bit_of(c))) tot += expf(lg[c] - mx);
-                const float thr = (float)(w >> 8) * 0x1p-24f * tot;
-                float run = 0.f;
-                int pick = -1, lastc = -1;
-                for (int c = 0; c < G::CELLS; ++c)
-                    if (test_bit(m, G::bit_of(c))) {
-                        run += expf(lg[c] - mx);
-                        lastc = c;
-                        if (pick < 0 && run > thr) pick = c;
-                    }
-                if (np > 0) a = pick >= 0 ? pick : lastc;
-            }
-            if (is_pass) a = G::A - 1;
-        } else {
-            a = action[ec];
-            is_pass = G::HAS_PASS && a == G::A - 1;
-            if (is_pass) legal = !any(m);
-            else legal = a >= 0 && a < G::CELLS && test_bit(m, G::bit_of(a));
-        }
+        a = choose_action<G, MODE>(m, ply, ec, action, MODE == 2 ? logits + ec * G::A : nullptr, key0, key1, gid_base,
+                                   gid, legal, is_pass);
         if (!legal) {
             status = ILLEGAL;
         } else {
@@ -354,6 +371,248 @@ __global__ __launch_bounds__(BLOCK) void k_step(DevState st, int64_t n, int max_
         if (valid) write_mask_row<G>(lds + t * G::A, m, pass_legal);
         stage_out(reinterpret_cast<int8_t *>(next_mask) + e0 * G::A, nb * G::A, lds);
     }
+}
+
+// ---------------------------------------------------------------------------
+// The per-ply step of Hex with the aux cache (hexaux.hpp): the same three
+// modes and results as k_step, but a lane reads its env's two bitboards
+// from aux instead of the board, and the end test is a union-find join of
+// the new stone with its same-coloured neighbours.  The board still gets
+// its one-byte delta, the aux its changed stone word, the union-find
+// entries and the tag.  A block with a stale env (tag mismatch) stages its
+// boards and rebuilds those envs' caches first.
+// ---------------------------------------------------------------------------
+template <int N, int MODE>
+__global__ __launch_bounds__(BLOCK) void k_step_hexaux(DevState st, int64_t n, int max_plies,
+                                                       const int32_t *__restrict__ action,
+                                                       const float *__restrict__ logits, uint32_t key0,
+                                                       uint32_t key1, int64_t gid_base,
+                                                       const int64_t *__restrict__ gid,
+                                                       int8_t *__restrict__ reward,
+                                                       uint8_t *__restrict__ terminal,
+                                                       uint8_t *__restrict__ next_mask)
+{
+    using G = Hex<N>;
+    using X = HexAux<N>;
+    constexpr int NW = X::NWC;
+    // LDS only for the next mask's coalesced rows (dynamic: 0 bytes when no
+    // mask is asked for, so the per-ply loop keeps its occupancy)
+    extern __shared__ __align__(16) int8_t lds_mask[];
+    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
+    const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
+    const int t = threadIdx.x;
+    const int64_t e = e0 + t;
+    const bool valid = t < nb;
+    const int64_t ec = valid ? e : e0;
+    int status = valid ? (int)st.status[ec] : ILLEGAL;
+    const bool was_running = status == RUNNING;
+
+    if (!__syncthreads_or(was_running)) {
+        if (valid) {
+            reward[2 * e] = 0;
+            reward[2 * e + 1] = 0;
+            terminal[e] = 1;
+        }
+        if (next_mask != nullptr) {
+            uint8_t *dst = next_mask + e0 * G::A;
+            const int bytes = nb * G::A, full = bytes >> 4;
+            for (int j = t; j < full; j += BLOCK) reinterpret_cast<uint4 *>(dst)[j] = uint4{0u, 0u, 0u, 0u};
+            for (int j = (full << 4) + t; j < bytes; j += BLOCK) dst[j] = 0;
+        }
+        return;
+    }
+
+    uint8_t *ax = st.aux + ec * X::BYTES;
+    uint32_t *stones = reinterpret_cast<uint32_t *>(ax + X::STONES);
+    uint16_t *par = reinterpret_cast<uint16_t *>(ax + X::PARENT);
+    int me = st.to_move[ec], winner = st.winner[ec];
+    int ply = st.ply[ec], last = st.last_action[ec];
+    BB<NW> p1 = bb_zero<NW>(), p2 = bb_zero<NW>();
+    bool stale = false;
+    if (was_running) {
+        stale = *reinterpret_cast<const uint32_t *>(ax) != aux_tag(ply, last);
+        if (stale) {
+            // the state was changed without this cache: rebuild it from the
+            // board (byte reads; a rare path)
+            const int8_t *brow = st.board + ec * G::CELLS;
+            static_for<NW>([&](auto I) {
+                constexpr int i = I;
+#pragma unroll 4
+                for (int j = 0; j < 32 && 32 * i + j < G::CELLS; ++j) {
+                    const int v = brow[32 * i + j];
+                    p1.w[i] |= (v == 1 ? 1u : 0u) << j;
+                    p2.w[i] |= (v == 2 ? 1u : 0u) << j;
+                }
+            });
+            uf_build<N>(par, p1, 1);
+            uf_build<N>(par, p2, 2);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                p1.w[i] = stones[i];
+                p2.w[i] = stones[NW + i];
+            }
+        }
+    }
+    int r1 = 0, r2 = 0, a = 0;
+    bool changed = false;
+    if (was_running) {
+        const BB<NW> m = G::open_cells(p1, p2);
+        bool legal, is_pass;
+        a = choose_action<G, MODE>(m, ply, ec, action, MODE == 2 ? logits + ec * G::A : nullptr, key0, key1, gid_base,
+                                   gid, legal, is_pass);
+        if (!legal) {
+            status = ILLEGAL;
+        } else {
+            const bool me_was1 = me == 1;
+            const bool won = uf_place<N>(par, me_was1 ? p1 : p2, a, me);
+            if (me_was1) p1 = p1 | onehot<NW>(a);
+            else p2 = p2 | onehot<NW>(a);
+            changed = true;
+            ply += 1;
+            last = a;
+            if (won) {
+                status = TERMINAL;
+                winner = me;
+                r1 = me == 1 ? 1 : -1;
+                r2 = -r1;
+            } else {
+                me = 3 - me;
+                if (ply >= max_plies) {
+                    status = TRUNCATED;
+                    winner = -1;
+                }
+            }
+            if (stale) {
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    stones[i] = p1.w[i];
+                    stones[NW + i] = p2.w[i];
+                }
+            } else {
+                // the changed word, selected from registers
+                const BB<NW> &own = me_was1 ? p1 : p2;
+                uint32_t wv = 0u;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) wv |= (i == (a >> 5)) ? own.w[i] : 0u;
+                stones[(me_was1 ? 0 : NW) + (a >> 5)] = wv;
+            }
+            *reinterpret_cast<uint32_t *>(ax) = aux_tag(ply, last);
+        }
+    }
+    if (valid) {
+        if (was_running) {
+            st.to_move[e] = (int8_t)me;
+            st.status[e] = (int8_t)status;
+            st.winner[e] = (int8_t)winner;
+            st.ply[e] = (int16_t)ply;
+            st.last_action[e] = (int16_t)last;
+        }
+        reward[2 * e] = (int8_t)r1;
+        reward[2 * e + 1] = (int8_t)r2;
+        terminal[e] = status != RUNNING ? 1 : 0;
+        if (changed) st.board[e * G::CELLS + a] = (int8_t)(status == TERMINAL ? me : 3 - me);
+    }
+    if (next_mask != nullptr) {
+        BB<NW> m = bb_zero<NW>();
+        const bool running = valid && status == RUNNING;
+        if (running) m = G::open_cells(p1, p2);
+        if (valid) write_mask_row<G>(lds_mask + t * G::A, m, false);
+        stage_out(reinterpret_cast<int8_t *>(next_mask) + e0 * G::A, nb * G::A, lds_mask);
+    }
+}
+
+// The aux caches of envs [0, n) from their boards (ludax_init with aux: the
+// start position; ludax_aux_sync: whatever the boards hold).  One env per
+// lane, 64-env blocks.
+template <int N, bool FROM_BOARD>
+__global__ __launch_bounds__(BLOCK) void k_hexaux_sync(DevState st, int64_t n)
+{
+    using G = Hex<N>;
+    using X = HexAux<N>;
+    constexpr int NW = X::NWC;
+    __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS + STAGE_SLACK];
+    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
+    const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
+    const int t = threadIdx.x;
+    const bool valid = t < nb;
+    const int64_t ec = valid ? e0 + t : e0;
+    BB<NW> p1 = bb_zero<NW>(), p2 = bb_zero<NW>();
+    if constexpr (FROM_BOARD) {
+        stage_in<G::CELLS>(st.board, e0, nb, lds);
+        read_board<G::CELLS, NW>(lds + t * G::CELLS, p1, p2);
+    }
+    if (!valid) return;
+    uint8_t *ax = st.aux + ec * X::BYTES;
+    uint32_t *stones = reinterpret_cast<uint32_t *>(ax + X::STONES);
+    uint16_t *par = reinterpret_cast<uint16_t *>(ax + X::PARENT);
+    if constexpr (FROM_BOARD) {
+        uf_build<N>(par, p1, 1);
+        uf_build<N>(par, p2, 2);
+    }
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        stones[i] = p1.w[i];
+        stones[NW + i] = p2.w[i];
+    }
+    *reinterpret_cast<uint32_t *>(ax) = FROM_BOARD ? aux_tag(st.ply[ec], st.last_action[ec]) : aux_tag(0, -1);
+}
+
+// One ply of ludax_policy_step for env e, run by a single lane that has the
+// env's logits (lg: its row in action order) and board bytes (brow, with
+// readable slack behind it, as in read_board) at hand: the fused guided
+// step of the network, which keeps the logits on chip.  Same draw, rules
+// and outputs as k_step MODE 2; placement games whose ply changes one cell.
+template <class G>
+__device__ __forceinline__ void policy_ply_one(const DevState &st, int64_t e, int max_plies, const float *lg,
+                                               const int8_t *brow, uint32_t key0, uint32_t key1, int64_t gid_base,
+                                               const int64_t *__restrict__ gid, int8_t *__restrict__ reward,
+                                               uint8_t *__restrict__ terminal)
+{
+    static_assert(G::KIND == 3 || G::KIND == 5, "a placement game whose ply changes one cell");
+    int status = st.status[e];
+    int r1 = 0, r2 = 0;
+    if (status == RUNNING) {
+        BB<G::NWC> c1, c2;
+        read_board<G::CELLS, G::NWC>(brow, c1, c2);
+        G g;
+        g.load(c1, c2);
+        int me = st.to_move[e], winner = st.winner[e], passes = st.passes[e], ply = st.ply[e];
+        int last = st.last_action[e];
+        const typename G::M m = g.placements(me);
+        bool legal, is_pass;
+        const int a = choose_action<G, 2>(m, ply, e, nullptr, lg, key0, key1, gid_base, gid, legal, is_pass);
+        if (!legal) {
+            status = ILLEGAL;
+        } else {
+            const int outcome = g.place_step(G::bit_of(a), me, passes);
+            const int mover = me;
+            ply += 1;
+            last = a;
+            if (outcome >= 0) {
+                status = TERMINAL;
+                winner = outcome;
+                r1 = outcome == 1 ? 1 : (outcome == 2 ? -1 : 0);
+                r2 = -r1;
+            } else {
+                me = 3 - me;
+                if (ply >= max_plies) {
+                    status = TRUNCATED;
+                    winner = -1;
+                }
+            }
+            st.board[e * G::CELLS + a] = (int8_t)mover;
+            st.to_move[e] = (int8_t)me;
+            st.winner[e] = (int8_t)winner;
+            st.passes[e] = (int8_t)passes;
+            st.ply[e] = (int16_t)ply;
+            st.last_action[e] = (int16_t)last;
+        }
+        st.status[e] = (int8_t)status;
+    }
+    reward[2 * e] = (int8_t)r1;
+    reward[2 * e + 1] = (int8_t)r2;
+    terminal[e] = status != RUNNING ? 1 : 0;
 }
 
 // One ply of a running game with random word w: legal set, the k-th legal
@@ -999,7 +1258,39 @@ struct Launch {
         int64_t blocks = (work + 255) / 256;
         if (blocks > 65536) blocks = 65536;
         hipLaunchKernelGGL(k_init<G>, dim3((unsigned)blocks), dim3(256), 0, s, st, n);
+        if constexpr (G::KIND == 3) {
+            if (st.aux != nullptr)
+                hipLaunchKernelGGL((k_hexaux_sync<G::H, false>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)),
+                                   dim3(BLOCK), 0, s, st, n);
+        }
         return hipGetLastError();
+    }
+    static hipError_t aux_sync(const DevState &st, int64_t n, hipStream_t s)
+    {
+        if constexpr (G::KIND == 3) {
+            hipLaunchKernelGGL((k_hexaux_sync<G::H, true>), dim3((unsigned)((n + BLOCK - 1) / BLOCK)), dim3(BLOCK),
+                               0, s, st, n);
+            return hipGetLastError();
+        } else {
+            return hipSuccess;
+        }
+    }
+    // the step kernel of MODE: Hex with an aux cache takes k_step_hexaux
+    // (whose LDS, dynamic, holds only the next mask's rows)
+    template <int MODE>
+    static auto step_kernel(const DevState &st)
+    {
+        if constexpr (G::KIND == 3) {
+            if (st.aux != nullptr) return &k_step_hexaux<G::H, MODE>;
+        }
+        return &k_step<G, MODE>;
+    }
+    static unsigned step_lds(const DevState &st, const uint8_t *next_mask)
+    {
+        if constexpr (G::KIND == 3) {
+            if (st.aux != nullptr && next_mask != nullptr) return BLOCK * G::A + STAGE_SLACK;
+        }
+        return 0u;
     }
     static hipError_t mask(const DevState &st, int64_t n, uint8_t *mask, hipStream_t s)
     {
@@ -1011,7 +1302,8 @@ struct Launch {
                            int8_t *reward, uint8_t *terminal, uint8_t *next_mask, hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL((k_step<G, 0>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+        hipLaunchKernelGGL(step_kernel<0>(st), dim3((unsigned)blocks), dim3(BLOCK), step_lds(st, next_mask), s, st, n,
+                           max_plies,
                            action, (const float *)nullptr, 0u, 0u, (int64_t)0, (const int64_t *)nullptr, reward,
                            terminal, next_mask);
         return hipGetLastError();
@@ -1021,7 +1313,7 @@ struct Launch {
                                   hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL((k_step<G, 1>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+        hipLaunchKernelGGL(step_kernel<1>(st), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
                            (const int32_t *)nullptr, (const float *)nullptr, (uint32_t)seed, (uint32_t)(seed >> 32),
                            gid_base, gid, reward, terminal, (uint8_t *)nullptr);
         return hipGetLastError();
@@ -1031,7 +1323,7 @@ struct Launch {
                                   uint8_t *terminal, hipStream_t s)
     {
         const int64_t blocks = (n + BLOCK - 1) / BLOCK;
-        hipLaunchKernelGGL((k_step<G, 2>), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
+        hipLaunchKernelGGL(step_kernel<2>(st), dim3((unsigned)blocks), dim3(BLOCK), 0, s, st, n, max_plies,
                            (const int32_t *)nullptr, logits, (uint32_t)seed, (uint32_t)(seed >> 32), gid_base, gid,
                            reward, terminal, (uint8_t *)nullptr);
         return hipGetLastError();
@@ -1067,8 +1359,12 @@ struct Launch {
     }
     static constexpr GameOps ops()
     {
-        return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step, &playout,
-                       &persist};
+        if constexpr (G::KIND == 3)
+            return GameOps{G::KIND, G::H,        G::W,          G::CELLS, G::A,     &init,           &mask, &step,
+                           &random_step, &policy_step, &playout, &persist, HexAux<G::H>::BYTES, &aux_sync};
+        else
+            return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step,
+                           &playout, &persist, 0, nullptr};
     }
 };
 

@@ -15,6 +15,7 @@ struct DevState {
     int8_t *passes;
     int16_t *ply;
     int16_t *last_action;
+    uint8_t *aux; // the game's per-env cache (Hex: hexaux.hpp), or NULL
 };
 
 // One game kind of a mixed persistent batch (see k_persist_ply /
@@ -44,6 +45,8 @@ struct GameOps {
     hipError_t (*playout)(const DevState &, int64_t, int, uint64_t, int64_t, const int64_t *, int8_t *,
                           uint8_t *, int64_t *, hipStream_t);
     hipError_t (*persist)(const MixedArgs &, int, hipStream_t); // NULL: no mixed batches of this game
+    int aux_bytes;                                               // per-env cache size (0: no cache)
+    hipError_t (*aux_sync)(const DevState &, int64_t, hipStream_t); // NULL when aux_bytes == 0
 };
 
 hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s);
@@ -70,6 +73,11 @@ hipError_t net_loss_grad(int N, const float *params, const void *packed, const i
 // workspace: forward size plus n * (N * N + 1) floats
 hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,
                         float *estimate, void *ws, hipStream_t s);
+// one guided ply (forward, policy draw from the logits on chip, step) of
+// every env; N = 11, kind = Hex or Gomoku
+hipError_t net_guided_step(int N, const float *params, const void *packed, const DevState &st, int kind, int64_t n,
+                           int max_plies, uint64_t seed, int64_t gid_base, const int64_t *gid, int8_t *reward,
+                           uint8_t *terminal, void *ws, hipStream_t s);
 hipError_t net_adam(float *params, const float *grads, float *m, float *v, int step, float lr, float b1, float b2,
                     float eps, void *packed, hipStream_t s);
 

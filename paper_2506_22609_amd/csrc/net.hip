@@ -32,6 +32,7 @@
 
 #include <cmath>
 
+#include "kernels.hpp"
 #include "ludax_internal.hpp"
 
 namespace lx {
@@ -439,6 +440,15 @@ struct FwdArgs {
     // gradients read with their taps.
     const uint16_t *zero16;
     int ring;
+    // MODE 4 (the fused guided step): the policy ply of each board's env,
+    // drawn from the logits on chip (see guided_step below)
+    DevState st;
+    int kind, max_plies;
+    uint32_t key0, key1;
+    int64_t gid_base;
+    const int64_t *gid;
+    int8_t *reward;
+    uint8_t *terminal;
 };
 
 // Cell codes of the fused forward: for each board of a block and each cell
@@ -611,6 +621,38 @@ __device__ __forceinline__ void heads_epilogue(const f32x4 (&acc)[8][NTW], const
     if (lane == 0) a1.value[b] = tanhf(sv / (float)PIX + a1.params[BV_OFF]);
 }
 
+// The policy logits of heads_epilogue, for the fused guided step: the same
+// sums, written to the board's LDS row lg (action order) instead of memory;
+// no value.
+template <int N, int NTW>
+__device__ __forceinline__ void heads_to_lds(const f32x4 (&acc)[8][NTW], const int (&cell_off)[8], unsigned vmask,
+                                             int c0, int64_t b, const FwdArgs &a1, float *lg)
+{
+    static_assert(NTW == 4, "one wave holds all channels of its cells");
+    constexpr int NP = N + 2;
+    const int lane = threadIdx.x & 63, quad = lane >> 4;
+    float wp[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) wp[j] = a1.params[WP_OFF + c0 + j];
+    const float bp = a1.params[BP_OFF];
+    const int me = a1.to_move[b];
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const bool valid = (vmask >> mt) & 1u;
+        float lp = 0.f;
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lp += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wp[4 * nt + k];
+        lp += __shfl_xor(lp, 16);
+        lp += __shfl_xor(lp, 32);
+        if (valid && quad == 0) {
+            const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
+            lg[me == 2 ? c * N + r : r * N + c] = lp + bp;
+        }
+    }
+}
+
 // MODE 2 (forward of the first two layers): each channel half of layer 1's
 // output is computed by the block from its boards (a1) straight into the LDS
 // tile that layer 2 reads, so layer 1's activations never go to memory; x is
@@ -774,6 +816,32 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
                 }
             }
         }
+    }
+    if constexpr (MODE == 4) {
+        // the fused guided step: the logits of each board go to LDS (the
+        // activation tile is free once every wave's products are done), its
+        // board bytes beside them, and one lane per board draws and plays
+        // the policy ply (policy_ply_one)
+        static_assert(NG == 1 && L::NSPLIT == 1, "MODE 4: one wave holds a whole board");
+        constexpr int PIX = L::PIX;
+        static_assert(BPB * (PIX * 4 + PIX + 16) <= BPB * PP * 32 * 2, "logits and boards fit the tile");
+        __syncthreads();
+        float *lg = reinterpret_cast<float *>(xs) + slot * ((PIX + 3) / 4 * 4);
+        int8_t *brow = reinterpret_cast<int8_t *>(xs) + BPB * (PIX + 3) / 4 * 16 + slot * ((PIX + 31) / 16 * 16);
+        if (live) {
+            heads_to_lds<N, NTW>(acc, cell_off, vmask, c0, b, a1, lg);
+            for (int j = lane; j < PIX; j += 64) brow[j] = a1.board[b * PIX + j];
+        }
+        __syncthreads();
+        if (live && lane == 0) {
+            if (a1.kind == 3)
+                policy_ply_one<Hex<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                       a1.reward, a1.terminal);
+            else
+                policy_ply_one<Gomoku<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                          a1.reward, a1.terminal);
+        }
+        return;
     }
     if (!live) return;
 
@@ -1756,6 +1824,43 @@ hipError_t forward_t(const float *params, const uint16_t *packed, const int8_t *
     return hipGetLastError();
 }
 
+// One guided ply of every env: the forward's three kernels, the last one
+// drawing and playing each env's policy ply from its logits on chip
+// (k_conv_lds MODE 4); 11x11 only.
+hipError_t guided_step_t(const float *params, const uint16_t *packed, const DevState &st, int kind, int64_t n,
+                         int max_plies, uint64_t seed, int64_t gid_base, const int64_t *gid, int8_t *reward,
+                         uint8_t *terminal, void *ws, hipStream_t s)
+{
+    constexpr int N = 11;
+    using S = Sizes<N>;
+    Carve cv{static_cast<char *>(ws)};
+    cv.take<uint2>(S::a0(n));
+    uint16_t *ya = cv.take<uint16_t>(S::act(n));
+    uint16_t *yb = cv.take<uint16_t>(S::act(n));
+    using LC = LdsL<N>;
+    const unsigned lb = (unsigned)((n + LC::BPB - 1) / LC::BPB);
+    const uint16_t *z = zero16(packed);
+    const FwdArgs a1{st.board, st.to_move, packed + pf_off(1), params + b_off(1), nullptr, nullptr, nullptr, z, 0};
+    const FwdArgs a3{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, z, 0};
+    FwdArgs ah{st.board, st.to_move, nullptr, nullptr, params, nullptr, nullptr, z, 0};
+    ah.st = st;
+    ah.kind = kind;
+    ah.max_plies = max_plies;
+    ah.key0 = (uint32_t)seed;
+    ah.key1 = (uint32_t)(seed >> 32);
+    ah.gid_base = gid_base;
+    ah.gid = gid;
+    ah.reward = reward;
+    ah.terminal = terminal;
+    hipLaunchKernelGGL((k_conv_lds<N, 2>), dim3(lb), dim3(LC::THREADS), 0, s, (const uint16_t *)nullptr,
+                       packed + pf_off(2), params + b_off(2), (const uint16_t *)nullptr, ya, n, a1);
+    hipLaunchKernelGGL((k_conv_lds<N, 0>), dim3(lb), dim3(LC::THREADS), 0, s, ya, packed + pf_off(3),
+                       params + b_off(3), (const uint16_t *)nullptr, yb, n, a3);
+    hipLaunchKernelGGL((k_conv_lds<N, 4>), dim3(lb), dim3(LC::THREADS), 0, s, yb, packed + pf_off(4),
+                       params + b_off(4), (const uint16_t *)nullptr, (uint16_t *)nullptr, n, ah);
+    return hipGetLastError();
+}
+
 template <int N>
 hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
                        const int16_t *action, const float *z, int64_t n, float beta, float *loss, float *grads,
@@ -1873,6 +1978,15 @@ hipError_t net_loss_grad(int N, const float *params, const void *packed, const i
     const uint16_t *pk = static_cast<const uint16_t *>(packed);
     return N == 11 ? net::loss_grad_t<11>(params, pk, board, to_move, action, z, n, beta, loss, grads, ws, s)
                    : net::loss_grad_t<19>(params, pk, board, to_move, action, z, n, beta, loss, grads, ws, s);
+}
+
+hipError_t net_guided_step(int N, const float *params, const void *packed, const DevState &st, int kind, int64_t n,
+                           int max_plies, uint64_t seed, int64_t gid_base, const int64_t *gid, int8_t *reward,
+                           uint8_t *terminal, void *ws, hipStream_t s)
+{
+    if (N != 11) return hipErrorInvalidValue;
+    return net::guided_step_t(params, static_cast<const uint16_t *>(packed), st, kind, n, max_plies, seed, gid_base,
+                              gid, reward, terminal, ws, s);
 }
 
 hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,

@@ -23,12 +23,13 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 # every symbol the public header declares
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
            "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_policy_step", "ludax_playout",
-           "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy", "ludax_mixed_set_slots",
-           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_autotune",
-           "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
+           "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
+           "ludax_mixed_set_slots",
+           "ludax_mixed_get_slots", "ludax_mixed_playout",
+           "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
            "ludax_net_max_batch",
            "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
-           "ludax_net_estimate", "ludax_strerror", "ludax_last_device_error")
+           "ludax_net_estimate", "ludax_net_guided_step", "ludax_strerror", "ludax_last_device_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -77,6 +78,7 @@ def _load():
             L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
                                         vp]
             L.ludax_state_stats.argtypes = [vp, P(_State), ctypes.c_int32, vp, i64, vp]
+            L.ludax_aux_sync.argtypes = [vp, P(_State), i64, vp]
             L.ludax_mixed_create.argtypes = [vp, i32, P(vp)]
             L.ludax_mixed_destroy.argtypes = [vp]
             L.ludax_mixed_set_slots.argtypes = [vp, vp]
@@ -95,6 +97,8 @@ def _load():
             L.ludax_net_loss_grad.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, f32, vp, vp, vp, vp]
             L.ludax_net_adam.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, vp, vp]
             L.ludax_net_estimate.argtypes = [vp, vp, vp, P(_State), i64, vp, vp, vp]
+            L.ludax_net_guided_step.argtypes = [vp, vp, vp, vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, i64,
+                                                vp, vp]
             L.ludax_strerror.argtypes = [ctypes.c_int]
             L.ludax_strerror.restype = ctypes.c_char_p
             L.ludax_last_device_error.argtypes = []
@@ -102,13 +106,13 @@ def _load():
             for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
                          "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_random_step",
                          "ludax_policy_step", "ludax_playout",
-                         "ludax_state_stats", "ludax_mixed_create", "ludax_mixed_destroy",
+                         "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
                          "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
-                         "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy",
-                         "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
+                         "ludax_mixed_autotune", "ludax_net_create",
+                         "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
                          "ludax_net_pack",
                          "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
-                         "ludax_net_estimate"):
+                         "ludax_net_estimate", "ludax_net_guided_step"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -174,12 +178,17 @@ class Game:
 
 
 class State:
-    """Device structure-of-arrays state of n environments."""
+    """Device structure-of-arrays state of n environments.  aux=True also
+    allocates the game's per-env cache (Hex; see ludax_state.aux), which
+    every call on this state then passes."""
 
     FIELDS = ("board", "to_move", "status", "winner", "passes", "ply", "last_action")
 
-    def __init__(self, game: Game, n: int, device="cuda"):
+    def __init__(self, game: Game, n: int, device="cuda", aux: bool = False):
         self.n, self.cells = n, game.cells
+        self.aux = None
+        if aux and game.aux_bytes > 0:
+            self.aux = torch.empty((n, game.aux_bytes), dtype=torch.uint8, device=device)
         self.board = torch.empty((n, game.cells), dtype=torch.int8, device=device)
         self.to_move = torch.empty(n, dtype=torch.int8, device=device)
         self.status = torch.empty(n, dtype=torch.int8, device=device)
@@ -192,23 +201,30 @@ class State:
         # the checked C view is kept while the same field tensors, at the
         # same addresses, are in place (every call passes it)
         ts = [getattr(self, f) for f in self.FIELDS]
-        key = tuple(t.data_ptr() for t in ts)
+        aux = self.__dict__.get("aux")
+        key = tuple(t.data_ptr() for t in ts) + (0 if aux is None else aux.data_ptr(),)
         hit = self.__dict__.get("_cview")
-        if hit is not None and hit[0] == key and all(a is b for a, b in zip(hit[1], ts)):
+        if hit is not None and hit[0] == key and all(a is b for a, b in zip(hit[1], ts)) and hit[3] is aux:
             return hit[2]
         for f, t in zip(self.FIELDS, ts):
             if not t.is_contiguous() or t.device.type != "cuda":
                 raise ValueError(f"state.{f} must be a contiguous device tensor")
         if key[0] % 16:
             raise ValueError("state.board must be 16-byte aligned")
-        view = _State(*[ctypes.c_void_p(p) for p in key], None)
-        self._cview = (key, ts, view)
+        if aux is not None:
+            if aux.dtype != torch.uint8 or not aux.is_contiguous() or aux.device.type != "cuda" or key[-1] % 16:
+                raise ValueError("state.aux must be a contiguous, 16-byte aligned uint8 device tensor")
+        view = _State(*[ctypes.c_void_p(p) for p in key[:-1]], None if aux is None else ctypes.c_void_p(key[-1]))
+        self._cview = (key, ts, view, aux)
         return view
 
     @classmethod
-    def from_tensors(cls, game: Game, **fields) -> "State":
+    def from_tensors(cls, game: Game, aux=None, **fields) -> "State":
         s = cls.__new__(cls)
         s.cells = game.cells
+        s.aux = aux
+        if aux is not None:
+            _need(aux, torch.uint8, (fields["board"].shape[0], game.aux_bytes), "aux")
         s.n = fields["board"].shape[0]
         dt = {"board": torch.int8, "to_move": torch.int8, "status": torch.int8,
               "winner": torch.int8, "passes": torch.int8, "ply": torch.int16,
@@ -223,6 +239,7 @@ class State:
     def clone(self) -> "State":
         s = State.__new__(State)
         s.n, s.cells = self.n, self.cells
+        s.aux = None if self.aux is None else self.aux.clone()
         for f in self.FIELDS:
             setattr(s, f, getattr(self, f).clone())
         return s
@@ -234,6 +251,12 @@ class State:
 def init(game: Game, state: State, stream=None):
     _check(_load().ludax_init(game.handle, ctypes.byref(state._c()), state.n, _stream(stream)),
            "ludax_init")
+
+
+def aux_sync(game: Game, state: State, stream=None):
+    """Rebuild state.aux from the boards (see ludax_aux_sync)."""
+    _check(_load().ludax_aux_sync(game.handle, ctypes.byref(state._c()), state.n, _stream(stream)),
+           "ludax_aux_sync")
 
 
 def legal_mask(game: Game, state: State, out: torch.Tensor | None = None, stream=None):
@@ -521,6 +544,27 @@ class Net:
                                           ctypes.byref(state._c()), n, _ptr(out), _ptr(ws),
                                           _stream(stream)), "ludax_net_estimate")
         return out
+
+    def guided_step(self, game: "Game", state: "State", seed: int, game_id_base: int = 0, game_id=None,
+                    reward=None, terminal=None, stream=None):
+        """One network-guided ply of every env (ludax_net_guided_step): the
+        forward pass and the policy draw and step, the logits kept on chip."""
+        n = state.n
+        dev = state.board.device
+        if reward is None:
+            reward = torch.empty((n, 2), dtype=torch.int8, device=dev)
+        if terminal is None:
+            terminal = torch.empty(n, dtype=torch.uint8, device=dev)
+        _need(reward, torch.int8, (n, 2), "reward")
+        _need(terminal, torch.uint8, (n,), "terminal")
+        if game_id is not None:
+            _need(game_id, torch.int64, (n,), "game_id")
+        ws = self.workspace(n)
+        _check(_load().ludax_net_guided_step(self._h, _ptr(self.params), _ptr(self.packed), game.handle,
+                                             ctypes.byref(state._c()), ctypes.c_uint64(seed & (2**64 - 1)),
+                                             game_id_base, _ptr(game_id), _ptr(reward), _ptr(terminal), n,
+                                             _ptr(ws), _stream(stream)), "ludax_net_guided_step")
+        return reward, terminal
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -47,6 +47,9 @@ MORE_GAMES = (YAVALATH9_65536, PENTE19_65536, WOLF_SHEEP_65536, DRAUGHTS_65536, 
 HEX19_524288 = Batch("hex19x19_n524288", HEX, 19, 19, 524288)
 GOMOKU19_524288 = Batch("gomoku19x19_n524288", GOMOKU, 19, 19, 524288)
 LARGE_BATCHES = (HEX19_524288, GOMOKU19_524288)
+# the per-ply step's state above the 256 MB Infinity Cache: 1,048,576 Hex
+# 19x19 envs (378.5 MB of boards), so every ply streams the boards from HBM
+HEX19_1M = Batch("hex19x19_n1048576", HEX, 19, 19, 1048576)
 
 
 def game_id_base(step: int, batch: Batch) -> int:

@@ -1,0 +1,180 @@
+"""GPU parity of Hex's per-ply step with the aux component cache
+(union-find over the stones, bitboards of both players; ludax_state.aux)
+against the oracle, whose end test is a breadth-first search of the whole
+board: every field after every ply, with illegal and out-of-range actions,
+mid-game states brought in through ludax_aux_sync, caches made stale by
+calls without aux (rebuilt from the board by the step), policy steps, and
+the result of a whole per-ply loop."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from tests.gpu_util import FIELDS, assert_same_state, from_device, pair, random_states
+
+pytestmark = pytest.mark.gpu
+
+ludax = pytest.importorskip("paper_2506_22609_amd.ludax")
+
+SIZES = [1, 2, 3, 5, 8, 11, 13, 19]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def to_device_aux(game, s):
+    t = {f: torch.from_numpy(np.ascontiguousarray(getattr(s, f))).cuda() for f in FIELDS}
+    aux = torch.zeros((s.n, game.aux_bytes), dtype=torch.uint8, device="cuda")
+    d = ludax.State.from_tensors(game, aux=aux, **t)
+    ludax.aux_sync(game, d)
+    return d
+
+
+def _oracle_random_step(og, s, seed, gid):
+    m = ref.legal_mask(og, s)
+    a = np.zeros(s.n, np.int32)
+    for i in range(s.n):
+        idx = np.flatnonzero(m[i])
+        if idx.size and s.status[i] == ref.RUNNING:
+            w = ref.draw(seed, int(gid[i]), int(s.ply[i]))
+            a[i] = idx[(w * idx.size) >> 32]
+    rew, term, _ = ref.step(og, s, a, want_mask=False)
+    return rew, term
+
+
+def test_aux_bytes():
+    for N in SIZES:
+        g = ludax.Game(ref.HEX, N, N)
+        nwc = (N * N + 31) // 32
+        assert g.aux_bytes == (16 + 8 * nwc + 2 * N * N + 15) // 16 * 16
+    assert ludax.Game(ref.GOMOKU, 15, 15).aux_bytes == 0
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_step_sequences_with_aux(N):
+    """ludax_step with the cache from ludax_init, mostly legal actions and
+    some illegal or out of range ones, the next mask on; every field after
+    every ply."""
+    og, dg = pair(ref.HEX, N, N)
+    rng = np.random.default_rng(100 + N)
+    n = 200
+    s = ref.init(og, n)
+    d = ludax.State(dg, n, aux=True)
+    assert d.aux is not None
+    ludax.init(dg, d)
+    for p in range(og.cells + 3):
+        m = ref.legal_mask(og, s)
+        a = np.zeros(n, np.int32)
+        for i in range(n):
+            r = rng.random()
+            idx = np.flatnonzero(m[i])
+            if r < 0.01:
+                a[i] = -1 - int(rng.integers(0, 5))
+            elif r < 0.02:
+                a[i] = og.num_actions + int(rng.integers(0, 5))
+            elif r < 0.03 or idx.size == 0:
+                a[i] = int(rng.integers(0, og.num_actions))
+            else:
+                a[i] = idx[rng.integers(0, idx.size)]
+        rew, term, nm = ref.step(og, s, a)
+        grew, gterm, gnm = ludax.step(dg, d, torch.from_numpy(a).cuda())
+        assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
+        assert np.array_equal(term, gterm.cpu().numpy()), f"terminal at ply {p}"
+        assert np.array_equal(nm, gnm.cpu().numpy()), f"next mask at ply {p}"
+        assert_same_state(s, from_device(d), f"ply {p}")
+        if (s.status != ref.RUNNING).all():
+            break
+
+
+@pytest.mark.parametrize("N", SIZES)
+def test_random_step_sequences_with_synced_aux(N):
+    """Mid-game states (ended blocks, ILLEGAL envs, a ragged tail) copied
+    to the device, the cache rebuilt by ludax_aux_sync, then
+    ludax_random_step with explicit game ids until every game has ended."""
+    og, dg = pair(ref.HEX, N, N)
+    rng = np.random.default_rng(200 + N)
+    n = 333
+    s = random_states(og, n, min(og.cells, 40), rng)
+    s.status[:128] = ref.ILLEGAL
+    s.status[200::13] = ref.ILLEGAL
+    gid = rng.integers(0, 2**62, size=n, dtype=np.int64)
+    d = to_device_aux(dg, s)
+    dgid = torch.from_numpy(gid).cuda()
+    seed = 0x0F1E_2D3C_4B5A_6978 + N
+    for p in range(og.cells + 3):
+        rew, term = _oracle_random_step(og, s, seed, gid)
+        grew, gterm = ludax.random_step(dg, d, seed, game_id=dgid)
+        assert np.array_equal(rew, grew.cpu().numpy()), f"reward at ply {p}"
+        assert np.array_equal(term, gterm.cpu().numpy()), f"terminal at ply {p}"
+        assert_same_state(s, from_device(d), f"random step {p}")
+        if (s.status != ref.RUNNING).all():
+            break
+    assert (s.status != ref.RUNNING).all()
+
+
+@pytest.mark.parametrize("N", [5, 11, 19])
+def test_stale_cache_is_rebuilt(N):
+    """Plies played without the cache (aux = NULL) leave it stale; the next
+    step with it finds the (ply, last action) changed, rebuilds those envs'
+    caches from the board, and the loop still ends every game exactly as
+    the oracle's playout of the same ids.  Half of the envs are stepped
+    without the cache, so blocks mix stale and current envs."""
+    og, dg = pair(ref.HEX, N, N)
+    n = 400
+    s = ref.init(og, n)
+    _, _, stats = ref.playout(og, s, 9, 77, threads=8)
+    d = ludax.State(dg, n, aux=True)
+    ludax.init(dg, d)
+    plain = ludax.State.from_tensors(dg, **{f: getattr(d, f)[: n // 2] for f in FIELDS})
+    for k in range(og.cells + 3):
+        if k % 5 == 2:
+            ludax.random_step(dg, plain, 9, 77)  # the first half moves on without the cache
+        _, term = ludax.random_step(dg, d, 9, 77)
+        if bool(term.all()):
+            break
+    assert_same_state(s, from_device(d), "stale caches")
+
+
+@pytest.mark.parametrize("N,n", [(11, 517), (19, 150), (13, 64)])
+def test_random_step_loop_with_aux_equals_playout(N, n):
+    og, dg = pair(ref.HEX, N, N)
+    s = ref.init(og, n)
+    _, _, stats = ref.playout(og, s, 5, 1000, threads=8)
+    d = ludax.State(dg, n, aux=True)
+    ludax.init(dg, d)
+    st = torch.zeros(4, dtype=torch.int64, device="cuda")
+    ludax.state_stats(dg, d, -1, st)
+    for _ in range(og.cells + 3):
+        _, term = ludax.random_step(dg, d, 5, 1000)
+        if bool(term.all()):
+            break
+    ludax.state_stats(dg, d, +1, st)
+    assert_same_state(s, from_device(d), "random-step loop with aux")
+    assert np.array_equal(stats, st.cpu().numpy())
+
+
+@pytest.mark.parametrize("N", [11, 19])
+def test_policy_step_with_aux_equals_without(N):
+    """ludax_policy_step with and without the cache on the same states and
+    logits (the draw itself is checked against the oracle in
+    test_gpu_parity.py): identical states, rewards and terminal flags at
+    every ply."""
+    _, dg = pair(ref.HEX, N, N)
+    og = ref.Game(ref.HEX, N, N)
+    rng = np.random.default_rng(300 + N)
+    n = 260
+    s = random_states(og, n, 15, rng)
+    a_state = to_device_aux(dg, s)
+    b_state = ludax.State.from_tensors(dg, **{f: getattr(a_state, f).clone() for f in FIELDS})
+    for p in range(og.cells + 3):
+        lg = torch.from_numpy((rng.standard_normal((n, og.num_actions)) * 2.0).astype(np.float32)).cuda()
+        ra, ta = ludax.policy_step(dg, a_state, lg, 11, 5)
+        rb, tb = ludax.policy_step(dg, b_state, lg, 11, 5)
+        assert torch.equal(ra, rb) and torch.equal(ta, tb), p
+        for f in FIELDS:
+            assert torch.equal(getattr(a_state, f), getattr(b_state, f)), (p, f)
+        if bool(ta.all()):
+            break

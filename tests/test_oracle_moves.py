@@ -1,5 +1,5 @@
 """Pins of the oracle's movement games (Sec. 3.2 move mechanic: step and
-hop; App. B English Draughts listing; App. C rule texts): Wolf and Sheep
+hop; App. A English Draughts listing; App. C rule texts): Wolf and Sheep
 and English Draughts, 8 x 8, action = src * 64 + dst.
 
 Independent pins: move counts worked out by hand (Wolf and Sheep), the
