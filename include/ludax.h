@@ -318,6 +318,21 @@ int ludax_mixed_playout(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int6
                         int8_t *winner, int16_t *plies, int16_t *last_action, int64_t *stats,
                         uint32_t *workspace, hipStream_t stream);
 
+/* ludax_mixed_playout without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  The queue counters (one 32-bit word per
+ * kind, at most 8 words = 32 bytes) live in a static device array of the
+ * library, one copy per GPU, held until the process ends; the call looks up
+ * its device address once per device and allocates nothing.  Every call on
+ * one GPU shares those words: the call clears them (with a small kernel, no
+ * memset) before its kernels use them, and calls that overlap in time on
+ * one GPU (several streams or host threads) race and give wrong results.
+ * Arguments and results as in ludax_mixed_playout; returns LUDAX_E_INVALID
+ * for more kinds than scratch words (never, with the 8-kind limit). */
+int ludax_mixed_playout_noalloc(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int64_t n_games,
+                                int8_t *winner, int16_t *plies, int16_t *last_action, int64_t *stats,
+                                hipStream_t stream);
+
 /* The slot autotuner: times each kind alone at total_slots / n_kinds lanes
  * to estimate its work, then times whole batches under candidate splits of
  * total_slots (equal, proportional to the work, to its square root, and

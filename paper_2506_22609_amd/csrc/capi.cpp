@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -437,6 +438,59 @@ int ludax_mixed_playout(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t 
     if (rc) return rc;
     if (n_games == 0) return LUDAX_OK;
     return mixed_run(m, m->slots, 0xFFu, seed, id_base, n_games, winner, plies, last_action, stats, workspace,
+                     stream);
+}
+
+// ---------------------------------------------------------------------------
+// ludax_mixed_playout_noalloc: the queue counters (one 32-bit word per kind)
+// live in this file-scope device array instead of a caller workspace.  Each
+// GPU holds its own copy; its device address is looked up once per device
+// (host code never passes the array's name to a kernel: on the host that
+// name is only a stand-in for the symbol, not a device address).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int SCRATCH_WORDS = MAX_KINDS;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) uint32_t scratch[SCRATCH_WORDS];
+
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+int scratch_for_current_device(uint32_t **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_error(e);
+    if (dev < 0 || dev >= MAX_DEVICES) return LUDAX_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_error(e);
+        g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return LUDAX_OK;
+}
+
+} // namespace
+
+int ludax_mixed_playout_noalloc(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t n_games, int8_t *winner,
+                                int16_t *plies, int16_t *last_action, int64_t *stats, hipStream_t stream)
+{
+    // any non-null pointer passes mixed_args_ok's workspace test; the real
+    // counters are the device's scratch words
+    uint32_t dummy = 0;
+    int rc = mixed_args_ok(m, id_base, n_games, winner, plies, last_action, &dummy);
+    if (rc) return rc;
+    if (m->n > SCRATCH_WORDS) return LUDAX_E_INVALID;
+    if (n_games == 0) return LUDAX_OK;
+    uint32_t *counters = nullptr;
+    rc = scratch_for_current_device(&counters);
+    if (rc) return rc;
+    return mixed_run(m, m->slots, 0xFFu, seed, id_base, n_games, winner, plies, last_action, stats, counters,
                      stream);
 }
 

@@ -25,7 +25,7 @@ EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_
            "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_policy_step", "ludax_playout",
            "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
            "ludax_mixed_set_slots",
-           "ludax_mixed_get_slots", "ludax_mixed_playout",
+           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_playout_noalloc",
            "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
            "ludax_net_max_batch",
            "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
@@ -84,6 +84,7 @@ def _load():
             L.ludax_mixed_set_slots.argtypes = [vp, vp]
             L.ludax_mixed_get_slots.argtypes = [vp, vp]
             L.ludax_mixed_playout.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp, vp]
+            L.ludax_mixed_playout_noalloc.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp]
             L.ludax_mixed_autotune.argtypes = [vp, ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp,
                                                P(ctypes.c_float)]
             f32 = ctypes.c_float
@@ -108,7 +109,7 @@ def _load():
                          "ludax_policy_step", "ludax_playout",
                          "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
                          "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
-                         "ludax_mixed_autotune", "ludax_net_create",
+                         "ludax_mixed_playout_noalloc", "ludax_mixed_autotune", "ludax_net_create",
                          "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
                          "ludax_net_pack",
                          "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
@@ -418,6 +419,21 @@ class Mixed:
         _check(_load().ludax_mixed_playout(self._h, ctypes.c_uint64(seed & (2**64 - 1)), id_base, n_games,
                                            w, p, l, _ptr(stats), ws, _stream(stream)),
                "ludax_mixed_playout")
+        return out, stats
+
+    def playout_noalloc(self, seed: int, id_base: int, n_games: int, out: MixedResult | None = None,
+                        stats=True, stream=None):
+        """ludax_mixed_playout_noalloc: as playout, with the queue counters in
+        the library's static device words instead of out.workspace."""
+        out = self._check_out(n_games, out)
+        if stats is True:
+            stats = torch.zeros((self.n_kinds, 4), dtype=torch.int64, device=out.winner.device)
+        if stats is not None:
+            _need(stats, torch.int64, (self.n_kinds, 4), "stats")
+        w, p, l, _ = out._ptrs()
+        _check(_load().ludax_mixed_playout_noalloc(self._h, ctypes.c_uint64(seed & (2**64 - 1)), id_base,
+                                                   n_games, w, p, l, _ptr(stats), _stream(stream)),
+               "ludax_mixed_playout_noalloc")
         return out, stats
 
     def autotune(self, seed: int, id_base: int, n_games: int, total_slots: int,

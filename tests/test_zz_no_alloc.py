@@ -1,0 +1,42 @@
+"""ludax_mixed_playout_noalloc (queue counters in the library's static
+device words, no workspace argument) against ludax_mixed_playout (caller
+workspace) through the C ABI: byte-identical winners, lengths, last actions
+and counters on two calls in a row, the second with fewer games and another
+id base, so the second call must clear what the first left in the shared
+words."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+
+pytestmark = pytest.mark.gpu
+
+ludax = pytest.importorskip("paper_2506_22609_amd.ludax")
+
+MIX4 = [(ref.REVERSI, 8, 8), (ref.GOMOKU, 15, 15), (ref.HEX, 11, 11), (ref.CONNECT_FOUR, 6, 7)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_noalloc_equals_workspace_playout_twice():
+    games = [ludax.Game(kind, r, c) for kind, r, c in MIX4]
+    m = ludax.Mixed(games)
+    m.slots = [256, 256, 128, 128]
+    for seed, id_base, n_games in ((5, 0, 20000), (6, 12345, 3001)):
+        print(f"noalloc: seed {seed} id_base {id_base} n_games {n_games}", flush=True)
+        ref_out, ref_stats = m.playout(seed, id_base, n_games)
+        out, stats = m.playout_noalloc(seed, id_base, n_games)
+        torch.cuda.synchronize()
+        for f in ("winner", "plies", "last_action"):
+            assert torch.equal(getattr(out, f), getattr(ref_out, f)), f
+        assert torch.equal(stats, ref_stats)
+        # every game was played: plies >= 1, and the counters add up to the games
+        assert int(out.plies.min()) >= 1
+        st = stats.cpu().numpy()
+        assert st[:, 1:].sum() == n_games
+        assert st[:, 0].sum() == int(out.plies.to(torch.int64).sum())
