@@ -644,6 +644,50 @@ def _learned_section(seed: int, train_games: int, steps: int):
     return out
 
 
+def _hbm_probe(seed: int):
+    """A short fixed sequence for hardware-counter runs (rocprofv3 --pmc):
+    one plain device copy of 1 GiB (the known-size reference of the byte
+    counters), one headline step (Connect Four and Hex 11x11 playouts of
+    65536 envs), and the per-ply loop over 1,048,576 Hex 19x19 envs (361
+    ludax_random_step launches) without and then with the component cache.
+    Prints the env-steps of each part, which the counters are divided by."""
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    out = {}
+    src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    out["copy_bytes"] = 1 << 30
+    for b in W.BENCH_BATCHES:
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        s = ludax.State(g, b.n)
+        ludax.init(g, s)
+        _, _, st = ludax.playout(g, s, seed, 0)
+        out[b.name] = {"env_steps": int(st[0].item())}
+        del s
+    b = W.HEX19_1M
+    g = ludax.Game(b.kind, b.rows, b.cols)
+    for aux in (False, True):
+        s = ludax.State(g, b.n, aux=aux)
+        r = torch.empty((b.n, 2), dtype=torch.int8, device="cuda")
+        t = torch.empty(b.n, dtype=torch.uint8, device="cuda")
+        st = torch.zeros(4, dtype=torch.int64, device="cuda")
+        ludax.init(g, s)
+        ludax.state_stats(g, s, -1, st)
+        for _ in range(g.max_plies):
+            ludax.random_step(g, s, seed, 7 * b.n, reward=r, terminal=t)
+        ludax.state_stats(g, s, +1, st)
+        torch.cuda.synchronize()
+        out[b.name + ("_aux" if aux else "")] = {"env_steps": int(st[0].item()), "launches": g.max_plies}
+        del s
+        torch.cuda.synchronize()
+    print(json.dumps({"hbm_probe": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -672,6 +716,8 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, one plain device copy of this many MiB "
                          "(a known-size reference for HBM byte counters under a profiler)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="run only the short fixed sequence for hardware-counter runs and print its env-steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} asked for more): the playouts are independent "
@@ -687,6 +733,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.hbm_probe:
+        _hbm_probe(args.seed)
+        return
     batches = W.BENCH_BATCHES
     dominant = W.HEX11_65536.name
     games = [ludax.Game(b.kind, b.rows, b.cols) for b in batches]
