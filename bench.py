@@ -20,7 +20,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,17 +32,18 @@ sys.path.insert(0, ROOT)
 # this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt).  Peak:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (the fp64
 # vector rate 78.6 TFLOP/s counts an FMA as two operations).
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 279, "hex11x11_n65536": 179}
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 272, "hex11x11_n65536": 177}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes of one Hex playout launch: FETCH_SIZE and WRITE_SIZE scaled by
-# a 256 MiB copy (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
-HEX_TRAFFIC_BYTES = 19.93e6
+# a 1 GiB device copy in the same profiled run
+# (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
+HEX_TRAFFIC_BYTES = 11.92e6
 HBM_PEAK_GBS = 8000.0
 # DRAM bytes (read + written) per env-step of the per-ply loop, from the
 # FETCH_SIZE / WRITE_SIZE counters of every ludax_random_step dispatch of one
 # loop, each scaled by what the counter reads for a 1 GiB device copy in the
 # same profiled run (profiles/random_step_hex19_n1048576_hbm_bytes.txt).
-DRAM_BYTES_PER_ENV_STEP = {}
+DRAM_BYTES_PER_ENV_STEP = {"hex19x19_n1048576": 407.1 + 43.9, "hex19x19_n1048576_aux": 292.7 + 155.4}
 
 
 def _cpu_model() -> str:
@@ -446,11 +446,13 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
                 torch.cuda.synchronize()
                 timings[name] = time.perf_counter() - t0
             timings[name + "_mse"] = ((est[:sub] - tr) ** 2).mean().item()
-        k = max(1, math.ceil(timings["plain_full_playout_mse"] / timings["value_budgeted_mse"]))
+        k, mse_k, pps = _averaged_playouts_at_error(g, held, tr, timings["value_budgeted_mse"], base, seed + 970,
+                                                    5 * 10**9)
         res["guided"][b.name] = {
             "fixed_value_error": {"mse": timings["value_budgeted_mse"], "plain_playouts_averaged": k,
-                                  "plain_positions_per_s": n / timings["plain_full_playout"] / k,
-                                  "guided_positions_per_s": n / timings["value_budgeted"]},
+                                  "plain_average_mse": mse_k, "plain_positions_per_s": pps,
+                                  "guided_positions_per_s": n / timings["value_budgeted"],
+                                  "note": "k measured, as in the learned section"},
             "positions": n, "train_samples": n_train, "train_steps": train_steps, "train_s": t_train,
             "hbm_budget_bytes": budget, "admitted_chunk": net.max_batch(budget),
             "plain_full_playout": {"playouts_per_s": n / timings["plain_full_playout"],
@@ -532,6 +534,33 @@ def _more_games_section(seed: int, reps: int):
     return out
 
 
+def _averaged_playouts_at_error(g, held, tr, target_mse: float, base, seed: int, id_base: int):
+    """Plain random playouts at a fixed value error, measured: average k full
+    random playouts per held-out position (new game ids for each), k = 1,
+    2, ..., judging each average against the 256-playout mean tr, until its
+    squared error is no larger than target_mse (at most 128); then time k
+    playouts of every position of base.  Returns (k, the k-average's
+    squared error, positions per second)."""
+    import torch
+    from paper_2506_22609_amd import learn, ludax
+
+    acc = torch.zeros(held.n, dtype=torch.float32, device="cuda")
+    k, mse_k = 0, float("inf")
+    while k < 128 and mse_k > target_mse:
+        s = held.clone()
+        ludax.playout(g, s, seed, id_base + k * held.n, stats=None)
+        acc += learn.outcome_p1(s)
+        k += 1
+        mse_k = ((acc / k - tr) ** 2).mean().item()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(k):
+        s = base.clone()
+        ludax.playout(g, s, seed + 1, id_base + (128 + j) * base.n, stats=None)
+    torch.cuda.synchronize()
+    return k, mse_k, base.n / (time.perf_counter() - t0)
+
+
 def _learned_section(seed: int, train_games: int, steps: int):
     """The learned policy/value network on Hex 11x11: samples from random
     playouts, training by the library's own forward/backward/Adam kernels,
@@ -585,6 +614,13 @@ def _learned_section(seed: int, train_games: int, steps: int):
         return learn.cutoff_estimate(g, net, s, 20, seed + 500, 4 * 10**9)
 
     def guided(s):
+        # the fused guided step: forward, policy draw and ply, logits on chip
+        for _ in range(20):
+            net.guided_step(g, s, seed + 600, 5 * 10**9, reward=r, terminal=t)
+        return net.estimate(s)
+
+    def guided_unfused(s):
+        # the same plies through memory: forward to logits, then the policy step
         for _ in range(20):
             logits, _ = net.forward(s.board, s.to_move)
             ludax.policy_step(g, s, logits, seed + 600, 5 * 10**9, reward=r, terminal=t)
@@ -597,31 +633,35 @@ def _learned_section(seed: int, train_games: int, steps: int):
            "train_tflops": 3 * 4096 * flops_fwd / (t_train / steps) / 1e12,
            "value_loss_first_last": [float(lv[:50, 0].mean()), float(lv[-50:, 0].mean())],
            "methods": {}}
+    import statistics
     for name, fn in (("plain_full_playout", plain), ("value_only", value_only),
-                     ("random20_value_cutoff", cutoff), ("policy20_value_cutoff", guided)):
+                     ("random20_value_cutoff", cutoff), ("policy20_value_cutoff", guided),
+                     ("policy20_value_cutoff_unfused", guided_unfused)):
         s = base.clone()
         fn(s)
         torch.cuda.synchronize()
         ts = []
-        for _ in range(3):
+        for _ in range(5):
             s = base.clone()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             est = fn(s)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
-        el = min(ts)
+        el = statistics.median(ts)
         mse = ((est[:sub] - tr) ** 2).mean().item()
         out["methods"][name] = {"playouts_per_s": n / el, "ms_per_65536": el * 1e3 * 65536 / n,
-                                "mse_vs_256_playout_mean": mse}
-    # at a fixed value error: how many full random playouts one position
-    # needs, averaged, to match the value's squared error (one playout's
-    # error is the outcome variance, an average of k divides it by k)
-    pm, vm = out["methods"]["plain_full_playout"], out["methods"]["value_only"]
-    k = max(1, math.ceil(pm["mse_vs_256_playout_mean"] / vm["mse_vs_256_playout_mean"]))
+                                "mse_vs_256_playout_mean": mse, "timing": "median of 5"}
+    # at a fixed value error: the number of averaged full random playouts
+    # that matches the value's squared error, measured
+    vm = out["methods"]["value_only"]
+    k, mse_k, pps = _averaged_playouts_at_error(g, held, tr, vm["mse_vs_256_playout_mean"], base, seed + 800,
+                                                7 * 10**9)
     out["fixed_value_error"] = {"mse": vm["mse_vs_256_playout_mean"], "plain_playouts_averaged": k,
-                                "plain_positions_per_s": pm["playouts_per_s"] / k,
-                                "guided_positions_per_s": vm["playouts_per_s"]}
+                                "plain_average_mse": mse_k, "plain_positions_per_s": pps,
+                                "guided_positions_per_s": vm["playouts_per_s"],
+                                "note": "k measured: the smallest number of averaged full random playouts "
+                                        "whose squared error is no larger than the value's"}
     # the value forward alone, as a fraction of the bf16 MFMA peak
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -160,7 +160,7 @@ typedef struct {
                              (see above), 0 otherwise */
     int16_t *ply;         /* [n] plies applied since the start */
     int16_t *last_action; /* [n] last applied action, -1 before the first */
-    void    *aux;         /* NULL, or [n][aux_bytes] device bytes (16-byte aligned) of a
+    void    *aux;         /* NULL, or [n][aux_bytes] device bytes (128-byte aligned) of a
                              library-private per-env cache; see "aux" below */
 } ludax_state;
 
@@ -186,7 +186,7 @@ int ludax_game_create(const ludax_game_desc *desc, ludax_game **out);
 int ludax_game_destroy(ludax_game *game);
 
 /* Shapes of a game: cells = rows*cols, num_actions = A, aux_bytes per env
- * (Hex: the size of its component cache, a multiple of 16; 0 for the other
+ * (Hex: the size of its component cache, a multiple of 128; 0 for the other
  * games), max_plies after resolving 0 to the natural bound.  Any output
  * pointer may be NULL. */
 int ludax_game_info(const ludax_game *game, int32_t *cells, int32_t *num_actions,
@@ -431,6 +431,20 @@ int ludax_net_estimate(const ludax_net *net, const float *params, const void *pa
 int ludax_net_guided_step(const ludax_net *net, const float *params, const void *packed, const ludax_game *game,
                           ludax_state *state, uint64_t seed, int64_t game_id_base, const int64_t *game_id,
                           int8_t *reward, uint8_t *terminal, int64_t n, void *workspace, hipStream_t stream);
+
+/* Network-guided playouts with a value cutoff, in one kernel (Sec. 7's
+ * learned policy as the move proposal and its value as the cutoff):
+ * `plies` times ludax_net_guided_step for every env (an env stops when its
+ * game ends), then ludax_net_estimate of the resulting states, with the
+ * same results bit for bit -- the states, and estimate [n] float32 (the
+ * outcome for player 1 of an ended game, the network's value mapped to
+ * player 1 for a running one, 0 for any other status).  A block keeps its
+ * four boards and their activations on chip for all plies; the logits never
+ * leave it and no workspace is needed.  Supported: the 11x11 net with Hex
+ * or Gomoku 11x11 (else LUDAX_E_UNSUPPORTED); plies >= 0. */
+int ludax_net_guided_playout(const ludax_net *net, const float *params, const void *packed, const ludax_game *game,
+                             ludax_state *state, int32_t plies, uint64_t seed, int64_t game_id_base,
+                             const int64_t *game_id, float *estimate, int64_t n, hipStream_t stream);
 
 /* Text of a return code; never NULL. */
 const char *ludax_strerror(int code);

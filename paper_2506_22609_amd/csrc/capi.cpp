@@ -72,7 +72,7 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 // Common checks of a state argument; fills the device view.  aux is kept
 // only for a game with a per-env cache (aux_bytes > 0), and must then be
-// 16-byte aligned.
+// 128-byte aligned (each env's row starts a cache line).
 int check_state(const ludax_state *s, lx::DevState *d, int aux_bytes = 0)
 {
     if (s == nullptr || s->board == nullptr || s->to_move == nullptr || s->status == nullptr ||
@@ -87,7 +87,7 @@ int check_state(const ludax_state *s, lx::DevState *d, int aux_bytes = 0)
     d->ply = s->ply;
     d->last_action = s->last_action;
     d->aux = aux_bytes > 0 ? static_cast<uint8_t *>(s->aux) : nullptr;
-    if (d->aux != nullptr && !aligned16(d->aux)) return LUDAX_E_INVALID;
+    if (d->aux != nullptr && (reinterpret_cast<uintptr_t>(d->aux) & 127u) != 0) return LUDAX_E_INVALID;
     return LUDAX_OK;
 }
 
@@ -683,6 +683,23 @@ int ludax_net_guided_step(const ludax_net *net, const float *params, const void 
         return LUDAX_E_INVALID;
     return device_error(lx::net_guided_step(net->n, params, packed, d, game->desc.kind, n, game->max_plies, seed,
                                             game_id_base, game_id, reward, terminal, workspace, stream));
+}
+
+int ludax_net_guided_playout(const ludax_net *net, const float *params, const void *packed, const ludax_game *game,
+                             ludax_state *state, int32_t plies, uint64_t seed, int64_t game_id_base,
+                             const int64_t *game_id, float *estimate, int64_t n, hipStream_t stream)
+{
+    if (net == nullptr || game == nullptr || n < 0 || n > MAX_ENVS || plies < 0) return LUDAX_E_INVALID;
+    if (net->n != 11 || game->desc.rows != 11 || game->desc.cols != 11 ||
+        (game->desc.kind != LUDAX_HEX && game->desc.kind != LUDAX_GOMOKU))
+        return LUDAX_E_UNSUPPORTED;
+    if (n == 0) return LUDAX_OK;
+    lx::DevState d;
+    int rc = check_state(state, &d);
+    if (rc) return rc;
+    if (params == nullptr || packed == nullptr || !aligned16(packed) || estimate == nullptr) return LUDAX_E_INVALID;
+    return device_error(lx::net_guided_playout(params, packed, d, game->desc.kind, n, game->max_plies, plies, seed,
+                                               game_id_base, game_id, estimate, stream));
 }
 
 const char *ludax_strerror(int code)

@@ -10,11 +10,12 @@
 // six neighbours of the same colour with a union-find, so the end test is a
 // few parent reads instead of a flood.
 //
-// Per environment, AUX_BYTES bytes (a multiple of 16):
+// Per environment, BYTES bytes (a multiple of 128, rows 128-byte aligned,
+// so that the part every ply reads is one 128-byte cache line):
 //   [0, 4)              tag: the (ply, last_action) the cache belongs to
 //   [16, 16 + 4 NWC)    player 1's stones, bit c = cell c
-//   [.., 16 + 8 NWC)    player 2's stones
-//   [16 + 8 NWC, ..)    uint16 parent[c] for every occupied cell c: a root
+//   [.., 16 + 8 NWC)    player 2's stones (16 + 8 NWC <= 128 up to 19x19)
+//   [128, 128 + 2 N^2)  uint16 parent[c] for every occupied cell c: a root
 //                       holds ROOT | side flags of its component (bit 0: it
 //                       touches its owner's first side, bit 1: the far
 //                       side), any other cell the index of its parent.
@@ -31,8 +32,9 @@ namespace lx {
 template <int N>
 struct HexAux {
     static constexpr int CELLS = N * N, NWC = (CELLS + 31) / 32;
-    static constexpr int STONES = 16, PARENT = 16 + 8 * NWC;
-    static constexpr int BYTES = (PARENT + 2 * CELLS + 15) / 16 * 16;
+    static constexpr int STONES = 16, PARENT = 128;
+    static constexpr int BYTES = PARENT + (2 * CELLS + 127) / 128 * 128;
+    static_assert(STONES + 8 * NWC <= PARENT, "tag and stones share one cache line");
     static constexpr uint16_t ROOT = 0x8000u;
 };
 
@@ -51,60 +53,67 @@ __device__ __forceinline__ uint16_t hex_sides(int b, int p)
     return (uint16_t)((k == 0 ? 1u : 0u) | (k == N - 1 ? 2u : 0u));
 }
 
-// Root of x's component (x occupied), halving the path on the way: every
-// visited cell is pointed at its grandparent.  *re receives the root's entry.
-__device__ __forceinline__ int uf_find(uint16_t *par, int x, uint16_t *re)
-{
-    uint16_t e = par[x];
-    while (!(e & HexAux<1>::ROOT)) {
-        const uint16_t ep = par[e];
-        if (ep & HexAux<1>::ROOT) {
-            *re = ep;
-            return e;
-        }
-        par[x] = ep;
-        x = ep;
-        e = par[x];
-    }
-    *re = e;
-    return x;
-}
-
 // Place player me's stone on cell b, whose stones before the move are
 // `own`: join b to the components of its same-coloured neighbours and
-// return whether the joined component touches both of me's sides.
+// return whether the joined component touches both of me's sides.  The
+// neighbours' roots are found together: their parent entries are loaded at
+// once, then each chain climbs one level per round (independent loads in
+// flight together instead of one find after another).  The other roots
+// are linked under the first neighbour's root r0, and every neighbour and
+// b itself point straight at r0 (their entries share b's cache lines), so
+// chains stay short.
 template <int N>
 __device__ __forceinline__ bool uf_place(uint16_t *par, const BB<HexAux<N>::NWC> &own, int b, int me)
 {
     constexpr uint16_t ROOT = HexAux<N>::ROOT;
     const int r = b / N, c = b - (b / N) * N;
-    uint16_t flags = hex_sides<N>(b, me), f0 = 0;
-    int r0 = -1;
     // the six neighbours (r-1,c), (r-1,c+1), (r,c-1), (r,c+1), (r+1,c-1), (r+1,c)
     const int nb[6] = {b - N, b - N + 1, b - 1, b + 1, b + N - 1, b + N};
     const bool ok[6] = {r > 0, r > 0 && c < N - 1, c > 0, c < N - 1, r < N - 1 && c > 0, r < N - 1};
+    bool in[6];
+    int x[6];
+    uint16_t e[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        if (!ok[k]) continue;
-        const int q = nb[k];
-        if (!test_bit(own, q)) continue;
-        uint16_t e;
-        const int root = uf_find(par, q, &e);
-        if (r0 < 0) {
-            r0 = root;
-            f0 = e & 3u;
-            flags |= f0;
-        } else if (root != r0) {
-            par[root] = (uint16_t)r0;
-            flags |= e & 3u;
-        }
+        in[k] = ok[k] && test_bit(own, nb[k]);
+        x[k] = nb[k];
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] = in[k] ? par[x[k]] : ROOT;
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) more |= !(e[k] & ROOT);
+        if (!more) break;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            if (!(e[k] & ROOT)) {
+                x[k] = e[k];
+                e[k] = par[x[k]];
+            }
+    }
+    uint16_t flags = hex_sides<N>(b, me), f0 = 0;
+    int r0 = -1;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        if (in[k]) {
+            flags |= e[k] & 3u;
+            if (r0 < 0) {
+                r0 = x[k];
+                f0 = e[k] & 3u;
+            }
+        }
     if (r0 < 0) {
         par[b] = (uint16_t)(ROOT | flags);
-    } else {
-        par[b] = (uint16_t)r0;
-        if (flags != f0) par[r0] = (uint16_t)(ROOT | flags);
+        return flags == 3u;
     }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (in[k] && x[k] != r0) par[x[k]] = (uint16_t)r0;   // another component's root
+        if (in[k] && nb[k] != r0) par[nb[k]] = (uint16_t)r0; // the neighbour itself
+    }
+    par[b] = (uint16_t)r0;
+    if (flags != f0) par[r0] = (uint16_t)(ROOT | flags);
     return flags == 3u;
 }
 

@@ -430,8 +430,16 @@ __global__ __launch_bounds__(BLOCK) void k_step_hexaux(DevState st, int64_t n, i
     BB<NW> p1 = bb_zero<NW>(), p2 = bb_zero<NW>();
     bool stale = false;
     if (was_running) {
+        // the tag and the stones in one round of loads
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            p1.w[i] = stones[i];
+            p2.w[i] = stones[NW + i];
+        }
         stale = *reinterpret_cast<const uint32_t *>(ax) != aux_tag(ply, last);
         if (stale) {
+            p1 = bb_zero<NW>();
+            p2 = bb_zero<NW>();
             // the state was changed without this cache: rebuild it from the
             // board (byte reads; a rare path)
             const int8_t *brow = st.board + ec * G::CELLS;
@@ -446,12 +454,6 @@ __global__ __launch_bounds__(BLOCK) void k_step_hexaux(DevState st, int64_t n, i
             });
             uf_build<N>(par, p1, 1);
             uf_build<N>(par, p2, 2);
-        } else {
-#pragma unroll
-            for (int i = 0; i < NW; ++i) {
-                p1.w[i] = stones[i];
-                p2.w[i] = stones[NW + i];
-            }
         }
     }
     int r1 = 0, r2 = 0, a = 0;
@@ -558,37 +560,82 @@ __global__ __launch_bounds__(BLOCK) void k_hexaux_sync(DevState st, int64_t n)
     *reinterpret_cast<uint32_t *>(ax) = FROM_BOARD ? aux_tag(st.ply[ec], st.last_action[ec]) : aux_tag(0, -1);
 }
 
+// The draw of ludax_policy_step when the exponentials are already at hand:
+// ex[c] = exp(logit[c] - max over the legal cells) for every legal cell c
+// (computed once per cell by the lanes of a wave), legal cells the empty
+// ones of the board row brow.  The same float32 sums in the same order as
+// choose_action MODE 2, so the same action; -1 when no cell is empty.
+template <int CELLS>
+__device__ __forceinline__ int draw_from_exps(const float *ex, const int8_t *brow, uint32_t w)
+{
+    float tot = 0.f;
+    int np = 0;
+    for (int c = 0; c < CELLS; ++c)
+        if (brow[c] == 0) {
+            tot += ex[c];
+            ++np;
+        }
+    if (np == 0) return -1;
+    const float thr = (float)(w >> 8) * 0x1p-24f * tot;
+    float run = 0.f;
+    int pick = -1, lastc = -1;
+    for (int c = 0; c < CELLS; ++c)
+        if (brow[c] == 0) {
+            run += ex[c];
+            lastc = c;
+            if (pick < 0 && run > thr) pick = c;
+        }
+    return pick >= 0 ? pick : lastc;
+}
+
+// The exponentials of draw_from_exps for one board, by all 64 lanes of its
+// wave: the maximum logit over the empty cells (a wave reduction, exact in
+// any order), then exp(logit - max) of each empty cell into ex.
+template <int CELLS>
+__device__ __forceinline__ void wave_exps(const float *lg, const int8_t *brow, float *ex)
+{
+    const int lane = threadIdx.x & 63;
+    float mx = -3.0e38f;
+    for (int c = lane; c < CELLS; c += 64)
+        if (brow[c] == 0) mx = fmaxf(mx, lg[c]);
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
+    for (int c = lane; c < CELLS; c += 64) ex[c] = brow[c] == 0 ? expf(lg[c] - mx) : 0.f;
+}
+
 // One ply of ludax_policy_step for env e, run by a single lane that has the
-// env's logits (lg: its row in action order) and board bytes (brow, with
+// env's exponentials (ex, see wave_exps) and board bytes (brow, with
 // readable slack behind it, as in read_board) at hand: the fused guided
-// step of the network, which keeps the logits on chip.  Same draw, rules
-// and outputs as k_step MODE 2; placement games whose ply changes one cell.
+// steps of the network, which keep the logits on chip.  Same draw, rules
+// and state as k_step MODE 2 for the placement games whose legal actions
+// are the empty cells and whose ply changes one cell (Hex, Gomoku).
+// reward / terminal may be NULL.  Returns the cell played, or -1.
 template <class G>
-__device__ __forceinline__ void policy_ply_one(const DevState &st, int64_t e, int max_plies, const float *lg,
+__device__ __forceinline__ int policy_ply_exps(const DevState &st, int64_t e, int max_plies, const float *ex,
                                                const int8_t *brow, uint32_t key0, uint32_t key1, int64_t gid_base,
                                                const int64_t *__restrict__ gid, int8_t *__restrict__ reward,
                                                uint8_t *__restrict__ terminal)
 {
-    static_assert(G::KIND == 3 || G::KIND == 5, "a placement game whose ply changes one cell");
+    static_assert(G::KIND == 3 || G::KIND == 5, "legal actions = empty cells, one cell per ply");
     int status = st.status[e];
-    int r1 = 0, r2 = 0;
+    int r1 = 0, r2 = 0, played = -1;
     if (status == RUNNING) {
-        BB<G::NWC> c1, c2;
-        read_board<G::CELLS, G::NWC>(brow, c1, c2);
-        G g;
-        g.load(c1, c2);
         int me = st.to_move[e], winner = st.winner[e], passes = st.passes[e], ply = st.ply[e];
-        int last = st.last_action[e];
-        const typename G::M m = g.placements(me);
-        bool legal, is_pass;
-        const int a = choose_action<G, 2>(m, ply, e, nullptr, lg, key0, key1, gid_base, gid, legal, is_pass);
-        if (!legal) {
+        const uint64_t id = (uint64_t)(gid != nullptr ? gid[e] : gid_base + e);
+        const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
+        const int r = ply & 3;
+        const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
+        const int a = draw_from_exps<G::CELLS>(ex, brow, w);
+        if (a < 0) {
             status = ILLEGAL;
         } else {
+            BB<G::NWC> c1, c2;
+            read_board<G::CELLS, G::NWC>(brow, c1, c2);
+            G g;
+            g.load(c1, c2);
             const int outcome = g.place_step(G::bit_of(a), me, passes);
             const int mover = me;
             ply += 1;
-            last = a;
             if (outcome >= 0) {
                 status = TERMINAL;
                 winner = outcome;
@@ -606,13 +653,17 @@ __device__ __forceinline__ void policy_ply_one(const DevState &st, int64_t e, in
             st.winner[e] = (int8_t)winner;
             st.passes[e] = (int8_t)passes;
             st.ply[e] = (int16_t)ply;
-            st.last_action[e] = (int16_t)last;
+            st.last_action[e] = (int16_t)a;
+            played = a;
         }
         st.status[e] = (int8_t)status;
     }
-    reward[2 * e] = (int8_t)r1;
-    reward[2 * e + 1] = (int8_t)r2;
-    terminal[e] = status != RUNNING ? 1 : 0;
+    if (reward != nullptr) {
+        reward[2 * e] = (int8_t)r1;
+        reward[2 * e + 1] = (int8_t)r2;
+    }
+    if (terminal != nullptr) terminal[e] = status != RUNNING ? 1 : 0;
+    return played;
 }
 
 // One ply of a running game with random word w: legal set, the k-th legal
@@ -659,6 +710,20 @@ __device__ __forceinline__ bool random_ply(G &g, int &me, int &passes, int &ply,
 // ---------------------------------------------------------------------------
 // a2-a8 fused: uniform-random playout to the end of every game
 // ---------------------------------------------------------------------------
+// Start position of a lane (Reversi: the four discs; the rest: empty).
+template <class G>
+__device__ __forceinline__ void start_position(G &g)
+{
+    if constexpr (G::KIND == 4) {
+        // player 1 on E4 (row 3, col 4) and D5 (row 4, col 3); player 2 on D4 and E5
+        g.p1 = onehot<G::NWI>(3 * 8 + 4) | onehot<G::NWI>(4 * 8 + 3);
+        g.p2 = onehot<G::NWI>(3 * 8 + 3) | onehot<G::NWI>(4 * 8 + 4);
+    } else {
+        g.p1 = bb_zero<G::NWI>();
+        g.p2 = bb_zero<G::NWI>();
+    }
+}
+
 template <class G>
 __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int max_plies,
                                                    uint32_t key0, uint32_t key1, int64_t gid_base,
@@ -669,18 +734,24 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
     __shared__ __align__(16) int8_t lds[BLOCK * G::CELLS + STAGE_SLACK];
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
-    stage_in<G::CELLS>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
 
     const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
-    BB<G::NWC> c1, c2;
-    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-    G g;
-    g.load(c1, c2);
     int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
     int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    G g;
+    // a block whose envs are all RUNNING at ply 0 holds start positions (the
+    // ply counts the plies applied since ludax_init): its boards are not read
+    if (__syncthreads_and(!valid || (status == RUNNING && ply == 0))) {
+        start_position(g);
+    } else {
+        stage_in<G::CELLS>(st.board, e0, nb, lds);
+        BB<G::NWC> c1, c2;
+        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
+        g.load(c1, c2);
+    }
     const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
     const bool was_running = valid && status == RUNNING;
     if (was_running) g.prepare();
@@ -1001,18 +1072,25 @@ __global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, 
 
     const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
-    stage_in<G::CELLS>(st.board, e0, nb, lds);
     const int t = threadIdx.x;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
 
     const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
-    BB<G::NWC> c1, c2;
-    read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-    const M b1 = G::from_canon(c1), b2 = G::from_canon(c2);
     int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
     int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
     const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
+    // a block whose envs are all RUNNING at ply 0 holds start positions
+    // (empty boards for these games; the ply counts the plies applied since
+    // ludax_init): its boards are not read
+    M b1 = bb_zero<G::NWI>(), b2 = bb_zero<G::NWI>();
+    if (!__syncthreads_and(!valid || (status == RUNNING && ply == 0))) {
+        stage_in<G::CELLS>(st.board, e0, nb, lds);
+        BB<G::NWC> c1, c2;
+        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
+        b1 = G::from_canon(c1);
+        b2 = G::from_canon(c2);
+    }
     __syncthreads(); // the staging area becomes the move list
 
     const bool run = valid && status == RUNNING;
@@ -1055,20 +1133,6 @@ __global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, 
 // (one atomic per 64 games) and writes each game's winner (-1 if
 // truncated), ply count and last action at its global index.
 // ---------------------------------------------------------------------------
-
-// Start position of a lane (Reversi: the four discs; the rest: empty).
-template <class G>
-__device__ __forceinline__ void start_position(G &g)
-{
-    if constexpr (G::KIND == 4) {
-        // player 1 on E4 (row 3, col 4) and D5 (row 4, col 3); player 2 on D4 and E5
-        g.p1 = onehot<G::NWI>(3 * 8 + 4) | onehot<G::NWI>(4 * 8 + 3);
-        g.p2 = onehot<G::NWI>(3 * 8 + 3) | onehot<G::NWI>(4 * 8 + 4);
-    } else {
-        g.p1 = bb_zero<G::NWI>();
-        g.p2 = bb_zero<G::NWI>();
-    }
-}
 
 // next chunk of 64 games of this kind for the calling wave (wave-uniform)
 __device__ __forceinline__ int64_t next_chunk(unsigned int *counter)

@@ -78,6 +78,11 @@ hipError_t net_estimate(int N, const float *params, const void *packed, const De
 hipError_t net_guided_step(int N, const float *params, const void *packed, const DevState &st, int kind, int64_t n,
                            int max_plies, uint64_t seed, int64_t gid_base, const int64_t *gid, int8_t *reward,
                            uint8_t *terminal, void *ws, hipStream_t s);
+// `plies` guided plies of every env (11x11, Hex or Gomoku) in one kernel,
+// then estimate [n] as net_estimate gives it; no workspace
+hipError_t net_guided_playout(const float *params, const void *packed, const DevState &st, int kind, int64_t n,
+                              int max_plies, int plies, uint64_t seed, int64_t gid_base, const int64_t *gid,
+                              float *estimate, hipStream_t s);
 hipError_t net_adam(float *params, const float *grads, float *m, float *v, int step, float lr, float b1, float b2,
                     float eps, void *packed, hipStream_t s);
 

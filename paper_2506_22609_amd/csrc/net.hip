@@ -824,22 +824,26 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         // the policy ply (policy_ply_one)
         static_assert(NG == 1 && L::NSPLIT == 1, "MODE 4: one wave holds a whole board");
         constexpr int PIX = L::PIX;
-        static_assert(BPB * (PIX * 4 + PIX + 16) <= BPB * PP * 32 * 2, "logits and boards fit the tile");
         __syncthreads();
-        float *lg = reinterpret_cast<float *>(xs) + slot * ((PIX + 3) / 4 * 4);
-        int8_t *brow = reinterpret_cast<int8_t *>(xs) + BPB * (PIX + 3) / 4 * 16 + slot * ((PIX + 31) / 16 * 16);
+        constexpr int LGS = (PIX + 3) / 4 * 4, BRS = (PIX + 31) / 16 * 16;
+        float *lg = reinterpret_cast<float *>(xs) + slot * LGS;
+        float *ex = reinterpret_cast<float *>(xs) + BPB * LGS + slot * LGS;
+        int8_t *brow = reinterpret_cast<int8_t *>(xs) + 2 * BPB * LGS * 4 + slot * BRS;
+        static_assert(2 * BPB * LGS * 4 + BPB * BRS <= BPB * PP * 32 * 2, "logits, exponentials and boards fit the tile");
         if (live) {
             heads_to_lds<N, NTW>(acc, cell_off, vmask, c0, b, a1, lg);
             for (int j = lane; j < PIX; j += 64) brow[j] = a1.board[b * PIX + j];
         }
         __syncthreads();
+        if (live) wave_exps<PIX>(lg, brow, ex);
+        __syncthreads();
         if (live && lane == 0) {
             if (a1.kind == 3)
-                policy_ply_one<Hex<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
-                                       a1.reward, a1.terminal);
+                policy_ply_exps<Hex<N>>(a1.st, b, a1.max_plies, ex, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                        a1.reward, a1.terminal);
             else
-                policy_ply_one<Gomoku<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
-                                          a1.reward, a1.terminal);
+                policy_ply_exps<Gomoku<N>>(a1.st, b, a1.max_plies, ex, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                           a1.reward, a1.terminal);
         }
         return;
     }
@@ -858,6 +862,298 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         if (!((vmask >> mt) & 1u)) continue;
         const int64_t o = (int64_t)(cell_off[mt] + NP + 1) * C + c0; // the cell: one row and column in
         store_cell<NTW, MODE == 1 ? 1 : 0>(acc[mt], MODE == 1 ? mb + o : nullptr, ob + o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The whole 11x11 forward in one persistent kernel, the activations never
+// leaving the chip.  A block (one per CU: 4 waves, one per board) walks
+// 4-board groups; a group's activations of both channel halves stay in LDS
+// (86.5 KB) through all four layers, each layer's weights are staged half
+// by half (37.9 KB, from L2), and layer 4 goes through the heads in
+// registers.  Per layer a wave keeps its board's 64 channels x 8 cell tiles
+// in accumulators; after the last half's products (and a barrier) it
+// writes bf16(relu) back over the layer's input.  The layer-by-layer kernels
+// write every activation to memory and read it back (37 KB per board and
+// layer); this one moves the boards in and the heads out.
+//   MODE 0: logits and values to memory (ludax_net_forward's results).
+//   MODE 1: `plies` guided plies of every env, then the value cutoff: after
+//           layer 4 each board's logits go to LDS and the board's first lane
+//           draws and plays the policy ply (the board row and the side to
+//           move stay in LDS between plies); after the last ply one more
+//           forward gives estimate[b] (ludax_net_estimate's mapping).
+// ---------------------------------------------------------------------------
+struct FusedArgs {
+    const float *params;
+    const uint16_t *packed;
+    int64_t n;
+    // MODE 0
+    const int8_t *board, *to_move;
+    float *logits, *value;
+    // MODE 1
+    DevState st;
+    int kind, max_plies, plies;
+    uint32_t key0, key1;
+    int64_t gid_base;
+    const int64_t *gid;
+    float *estimate;
+};
+
+// One lane's guided ply in k_fwd11 MODE 1 (policy_ply_exps for the game).
+__device__ __forceinline__ int fused_ply(const FusedArgs &fa, int64_t b, const float *ex, const int8_t *brow)
+{
+    return fa.kind == 3 ? policy_ply_exps<Hex<11>>(fa.st, b, fa.max_plies, ex, brow, fa.key0, fa.key1, fa.gid_base,
+                                                   fa.gid, nullptr, nullptr)
+                        : policy_ply_exps<Gomoku<11>>(fa.st, b, fa.max_plies, ex, brow, fa.key0, fa.key1, fa.gid_base,
+                                                      fa.gid, nullptr, nullptr);
+}
+
+constexpr int FUSED_BLOCKS_PER_CU = 1;
+
+template <int MODE>
+__global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
+{
+    constexpr int N = 11;
+    using L = LdsL<N>;
+    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, BPB = L::BPB, WS = L::WS, NTW = 4;
+    static_assert(L::NG == 1 && L::NSPLIT == 1 && L::MT == 8 && BPB == 4 && L::THREADS == 256, "one wave per board");
+    __shared__ __align__(16) uint16_t ws[C * WS];
+    __shared__ __align__(16) uint16_t xa[2][BPB * PP * 32];
+    __shared__ __align__(16) int8_t brow[BPB][144];
+    __shared__ uint8_t cc[BPB * PP];
+    __shared__ float lgs[BPB][124], exs[BPB][124];
+    __shared__ int tm[BPB], alive[BPB];
+
+    const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6, row = lane & 15, quad = lane >> 4;
+    const int c0 = 16 * quad; // this lane's output channels c0 .. c0 + 15
+    int cell_off[8];
+    unsigned vmask = 0;
+#pragma unroll
+    for (int mt = 0; mt < 8; ++mt) {
+        const int e = tile_entry<N>(mt, row);
+        cell_off[mt] = entry_q(e);
+        vmask |= (e >= 0 ? 1u : 0u) << mt;
+    }
+    // the rings of both halves' tiles stay zero: only interior cells are written
+    for (int j = threadIdx.x; j < 2 * BPB * 4 * (NP - 1) * 4; j += 256) {
+        const int hh = j / (BPB * 4 * (NP - 1) * 4), r0 = j % (BPB * 4 * (NP - 1) * 4);
+        const int bb = r0 / (4 * (NP - 1) * 4), r = r0 % (4 * (NP - 1) * 4);
+        const int q = ring_cell<NP>(r >> 2);
+        *reinterpret_cast<uint4 *>(xa[hh] + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
+    }
+    const float *params = fa.params;
+    const uint16_t *packed = fa.packed;
+    const int64_t n = fa.n;
+    FwdArgs a1{};
+    a1.w1 = packed + pf_off(1);
+    a1.b1 = params + b_off(1);
+
+    for (int64_t b0 = (int64_t)blockIdx.x * BPB; b0 < n; b0 += (int64_t)gridDim.x * BPB) {
+        const int64_t b = b0 + slot;
+        const bool live = b < n;
+        __syncthreads(); // the previous group is done with brow, tm and alive
+        // the group's boards and sides to move
+        for (int j = threadIdx.x; j < BPB * PIX; j += 256) {
+            const int bb = j / PIX, c = j % PIX;
+            const int8_t *src = MODE == 0 ? fa.board : fa.st.board;
+            brow[bb][c] = b0 + bb < n ? src[(b0 + bb) * PIX + c] : (int8_t)0;
+        }
+        if (threadIdx.x < BPB) {
+            const int64_t bt = b0 + threadIdx.x;
+            const int8_t *tmv = MODE == 0 ? fa.to_move : fa.st.to_move;
+            tm[threadIdx.x] = bt < n ? (int)tmv[bt] : 1;
+            alive[threadIdx.x] = bt < n && (MODE == 0 || fa.st.status[bt] == 0);
+        }
+        const int rounds = MODE == 0 ? 1 : fa.plies + 1;
+        for (int ply = 0; ply < rounds; ++ply) {
+            __syncthreads(); // brow / tm / alive of the previous ply are written
+            const bool last = ply == rounds - 1;
+            if constexpr (MODE == 1) {
+                // no env of the group running and no value left to compute
+                if (!last && !(alive[0] | alive[1] | alive[2] | alive[3])) continue;
+            }
+            // cell codes (the encoder's planes in the mover's frame) from the board rows
+            for (int j = threadIdx.x; j < BPB * PP; j += 256) {
+                const int bb = j / PP, q = j % PP, rr = q / NP - 1, c = q % NP - 1;
+                const bool in = b0 + bb < n && (unsigned)rr < (unsigned)N && (unsigned)c < (unsigned)N;
+                const int me = tm[bb];
+                const int x = in ? (int)brow[bb][me == 2 ? c * N + rr : rr * N + c] : -1;
+                cc[j] = (uint8_t)(x < 0 ? 3 : (x == me ? 0 : (x == 0 ? 2 : 1)));
+            }
+            __syncthreads();
+            layer1_half<L>(a1, 0, b0, n, cc, xa[0]);
+            layer1_half<L>(a1, 1, b0, n, cc, xa[1]);
+            f32x4 acc[8][NTW];
+#pragma unroll 1
+            for (int l = 2; l <= 4; ++l) {
+                const uint16_t *w = packed + pf_off(l);
+                const float *bias = params + b_off(l);
+#pragma unroll
+                for (int nt = 0; nt < NTW; ++nt) {
+                    const f32x4 bv = {bias[c0 + 4 * nt], bias[c0 + 4 * nt + 1], bias[c0 + 4 * nt + 2],
+                                      bias[c0 + 4 * nt + 3]};
+#pragma unroll
+                    for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = bv;
+                }
+                for (int h = 0; h < 2; ++h) {
+                    __syncthreads(); // ws is free; the layer's input is written
+                    {
+                        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+                        constexpr int WCH = C * (WS / 8);
+                        for (int base = wid * 64; base < WCH; base += 4 * 64) {
+                            const int i = base + lane, srow = i / (WS / 8), col = i % (WS / 8);
+                            const int o = w_channel<NTW>(srow), t = col < 36 ? col >> 2 : 0, c8 = col < 36 ? col & 3 : 0;
+                            if (i < WCH)
+                                __builtin_amdgcn_global_load_lds(
+                                    (glb_void *)(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8),
+                                    (lds_void *)(ws + base * 8), 16, 0, 0);
+                        }
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
+                    if (!live) continue;
+                    const uint16_t *xb = xa[h] + slot * PP * 32;
+                    auto frag_b = [&](int t, bf16x8 (&bf)[NTW]) {
+#pragma unroll
+                        for (int nt = 0; nt < NTW; ++nt)
+                            bf[nt] = as_bf16x8(
+                                *reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * WS + t * 32 + quad * 8));
+                    };
+                    auto frag_a = [&](int t, bf16x8 (&af)[8]) {
+                        const int toff = (t / 3) * NP + (t % 3);
+#pragma unroll
+                        for (int mt = 0; mt < 8; ++mt) {
+                            const int q = cell_off[mt] + toff;
+                            af[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
+                        }
+                    };
+                    bf16x8 bcur[NTW], acur[8], bnxt[NTW], anxt[8];
+                    frag_b(0, bcur);
+                    frag_a(0, acur);
+#pragma unroll
+                    for (int t = 0; t < 9; ++t) {
+                        if (t + 1 < 9) {
+                            frag_b(t + 1, bnxt);
+                            frag_a(t + 1, anxt);
+                        }
+#pragma unroll
+                        for (int mt = 0; mt < 8; ++mt)
+#pragma unroll
+                            for (int nt = 0; nt < NTW; ++nt)
+                                acc[mt][nt] =
+                                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(bcur[nt], acur[mt], acc[mt][nt], 0, 0, 0);
+                        if (t + 1 < 9) {
+#pragma unroll
+                            for (int nt = 0; nt < NTW; ++nt) bcur[nt] = bnxt[nt];
+#pragma unroll
+                            for (int mt = 0; mt < 8; ++mt) acur[mt] = anxt[mt];
+                        }
+                    }
+                }
+                if (l < 4) {
+                    __syncthreads(); // every wave is done reading the layer's input
+                    if (live) {
+                        // bf16(relu) of channels c0 .. c0 + 15 of each cell over the input: half
+                        // quad / 2, 16-byte chunks 2 (quad & 1) and 2 (quad & 1) + 1
+                        uint16_t *xo = xa[quad >> 1] + slot * PP * 32;
+#pragma unroll
+                        for (int mt = 0; mt < 8; ++mt) {
+                            if (!((vmask >> mt) & 1u)) continue;
+                            const int q = cell_off[mt] + NP + 1;
+#pragma unroll
+                            for (int k8 = 0; k8 < 2; ++k8) {
+                                uint32_t wv[4];
+#pragma unroll
+                                for (int j = 0; j < 4; ++j) {
+                                    const int i0 = 8 * k8 + 2 * j, i1 = i0 + 1;
+                                    const float v0 = fmaxf(acc[mt][i0 >> 2][i0 & 3], 0.f);
+                                    const float v1 = fmaxf(acc[mt][i1 >> 2][i1 & 3], 0.f);
+                                    wv[j] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                                }
+                                const int c8 = 2 * (quad & 1) + k8;
+                                *reinterpret_cast<uint4 *>(xo + q * 32 + ((c8 + (q >> 2)) & 3) * 8) =
+                                    uint4{wv[0], wv[1], wv[2], wv[3]};
+                            }
+                        }
+                    }
+                }
+            }
+            // the heads on layer 4's accumulators
+            if constexpr (MODE == 0) {
+                if (live) {
+                    FwdArgs ah{};
+                    ah.to_move = fa.to_move;
+                    ah.params = params;
+                    ah.logits = fa.logits;
+                    ah.value = fa.value;
+                    heads_epilogue<N, NTW>(acc, cell_off, vmask, c0, b, ah);
+                }
+            } else {
+                const int me = tm[slot];
+                if (!last) {
+                    if (live) {
+                        // the policy logits (action order) of the board into LDS
+                        const float bp = params[BP_OFF];
+                        float wp[16];
+#pragma unroll
+                        for (int j = 0; j < 16; ++j) wp[j] = params[WP_OFF + c0 + j];
+#pragma unroll
+                        for (int mt = 0; mt < 8; ++mt) {
+                            float lp = 0.f;
+#pragma unroll
+                            for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+                                for (int k = 0; k < 4; ++k)
+                                    lp += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wp[4 * nt + k];
+                            lp += __shfl_xor(lp, 16);
+                            lp += __shfl_xor(lp, 32);
+                            if (((vmask >> mt) & 1u) && quad == 0) {
+                                const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
+                                lgs[slot][me == 2 ? c * N + r : r * N + c] = lp + bp;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    if (live) wave_exps<PIX>(lgs[slot], brow[slot], exs[slot]);
+                    __syncthreads();
+                    if (live && lane == 0) {
+                        const int mover = me;
+                        const int a = fused_ply(fa, b, exs[slot], brow[slot]);
+                        if (a >= 0) {
+                            brow[slot][a] = (int8_t)mover;
+                            tm[slot] = fa.st.to_move[b];
+                        }
+                        alive[slot] = fa.st.status[b] == 0;
+                    }
+                } else if (live) {
+                    // the value cutoff: the network's value for RUNNING envs (for
+                    // player 1), the outcome of ended ones
+                    float sv = 0.f;
+                    float wv[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) wv[j] = params[WV_OFF + c0 + j];
+#pragma unroll
+                    for (int mt = 0; mt < 8; ++mt) {
+                        float lv = 0.f;
+#pragma unroll
+                        for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) lv += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wv[4 * nt + k];
+                        lv += __shfl_xor(lv, 16);
+                        lv += __shfl_xor(lv, 32);
+                        if ((vmask >> mt) & 1u) sv += lv;
+                    }
+#pragma unroll
+                    for (int sft = 8; sft >= 1; sft >>= 1) sv += __shfl_xor(sv, sft);
+                    if (lane == 0) {
+                        const float v = tanhf(sv / (float)PIX + params[BV_OFF]);
+                        const int stt = fa.st.status[b], wn = fa.st.winner[b];
+                        fa.estimate[b] = stt == 1 ? (wn == 1 ? 1.f : (wn == 2 ? -1.f : 0.f))
+                                                  : (stt == 0 ? (me == 1 ? v : -v) : 0.f);
+                    }
+                }
+            }
+        }
     }
 }
 
@@ -1861,6 +2157,43 @@ hipError_t guided_step_t(const float *params, const uint16_t *packed, const DevS
     return hipGetLastError();
 }
 
+int cu_count()
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+unsigned fused_grid(int64_t n)
+{
+    const int64_t groups = (n + LdsL<11>::BPB - 1) / LdsL<11>::BPB;
+    const int64_t cap = (int64_t)cu_count() * FUSED_BLOCKS_PER_CU;
+    return (unsigned)(groups < cap ? groups : cap);
+}
+
+// The 11x11 forward as one kernel (k_fwd11 MODE 0).
+hipError_t forward_fused11(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
+                           int64_t n, float *logits, float *value, hipStream_t s)
+{
+    FusedArgs fa{};
+    fa.params = params;
+    fa.packed = packed;
+    fa.n = n;
+    fa.board = board;
+    fa.to_move = to_move;
+    fa.logits = logits;
+    fa.value = value;
+    hipLaunchKernelGGL(k_fwd11<0>, dim3(fused_grid(n)), dim3(256), 0, s, fa);
+    return hipGetLastError();
+}
+
 template <int N>
 hipError_t loss_grad_t(const float *params, const uint16_t *packed, const int8_t *board, const int8_t *to_move,
                        const int16_t *action, const float *z, int64_t n, float beta, float *loss, float *grads,
@@ -1987,6 +2320,27 @@ hipError_t net_guided_step(int N, const float *params, const void *packed, const
     if (N != 11) return hipErrorInvalidValue;
     return net::guided_step_t(params, static_cast<const uint16_t *>(packed), st, kind, n, max_plies, seed, gid_base,
                               gid, reward, terminal, ws, s);
+}
+
+hipError_t net_guided_playout(const float *params, const void *packed, const DevState &st, int kind, int64_t n,
+                              int max_plies, int plies, uint64_t seed, int64_t gid_base, const int64_t *gid,
+                              float *estimate, hipStream_t s)
+{
+    net::FusedArgs fa{};
+    fa.params = params;
+    fa.packed = static_cast<const uint16_t *>(packed);
+    fa.n = n;
+    fa.st = st;
+    fa.kind = kind;
+    fa.max_plies = max_plies;
+    fa.plies = plies;
+    fa.key0 = (uint32_t)seed;
+    fa.key1 = (uint32_t)(seed >> 32);
+    fa.gid_base = gid_base;
+    fa.gid = gid;
+    fa.estimate = estimate;
+    hipLaunchKernelGGL(net::k_fwd11<1>, dim3(net::fused_grid(n)), dim3(256), 0, s, fa);
+    return hipGetLastError();
 }
 
 hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,

@@ -29,7 +29,8 @@ EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_
            "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
            "ludax_net_max_batch",
            "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
-           "ludax_net_estimate", "ludax_net_guided_step", "ludax_strerror", "ludax_last_device_error")
+           "ludax_net_estimate", "ludax_net_guided_step", "ludax_net_guided_playout", "ludax_strerror",
+           "ludax_last_device_error")
 
 _lock = threading.Lock()
 _lib = None
@@ -100,6 +101,8 @@ def _load():
             L.ludax_net_estimate.argtypes = [vp, vp, vp, P(_State), i64, vp, vp, vp]
             L.ludax_net_guided_step.argtypes = [vp, vp, vp, vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, i64,
                                                 vp, vp]
+            L.ludax_net_guided_playout.argtypes = [vp, vp, vp, vp, P(_State), i32, ctypes.c_uint64, i64, vp, vp,
+                                                   i64, vp]
             L.ludax_strerror.argtypes = [ctypes.c_int]
             L.ludax_strerror.restype = ctypes.c_char_p
             L.ludax_last_device_error.argtypes = []
@@ -113,7 +116,7 @@ def _load():
                          "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
                          "ludax_net_pack",
                          "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
-                         "ludax_net_estimate", "ludax_net_guided_step"):
+                         "ludax_net_estimate", "ludax_net_guided_step", "ludax_net_guided_playout"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
     return _lib
@@ -213,8 +216,8 @@ class State:
         if key[0] % 16:
             raise ValueError("state.board must be 16-byte aligned")
         if aux is not None:
-            if aux.dtype != torch.uint8 or not aux.is_contiguous() or aux.device.type != "cuda" or key[-1] % 16:
-                raise ValueError("state.aux must be a contiguous, 16-byte aligned uint8 device tensor")
+            if aux.dtype != torch.uint8 or not aux.is_contiguous() or aux.device.type != "cuda" or key[-1] % 128:
+                raise ValueError("state.aux must be a contiguous, 128-byte aligned uint8 device tensor")
         view = _State(*[ctypes.c_void_p(p) for p in key[:-1]], None if aux is None else ctypes.c_void_p(key[-1]))
         self._cview = (key, ts, view, aux)
         return view
@@ -581,6 +584,22 @@ class Net:
                                              game_id_base, _ptr(game_id), _ptr(reward), _ptr(terminal), n,
                                              _ptr(ws), _stream(stream)), "ludax_net_guided_step")
         return reward, terminal
+
+    def guided_playout(self, game: "Game", state: "State", plies: int, seed: int, game_id_base: int = 0,
+                       game_id=None, out=None, stream=None):
+        """`plies` network-guided plies of every env, then the value cutoff,
+        in one kernel (ludax_net_guided_playout); returns estimate [n]."""
+        n = state.n
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=state.board.device)
+        _need(out, torch.float32, (n,), "estimate")
+        if game_id is not None:
+            _need(game_id, torch.int64, (n,), "game_id")
+        _check(_load().ludax_net_guided_playout(self._h, _ptr(self.params), _ptr(self.packed), game.handle,
+                                                ctypes.byref(state._c()), plies, ctypes.c_uint64(seed & (2**64 - 1)),
+                                                game_id_base, _ptr(game_id), _ptr(out), n, _stream(stream)),
+               "ludax_net_guided_playout")
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -55,11 +55,10 @@ def test_game_create_and_info():
         assert L.ludax_game_info(h, ctypes.byref(cells), ctypes.byref(A), ctypes.byref(aux),
                                  ctypes.byref(mp)) == 0
         assert (cells.value, A.value, mp.value) == exp
-        # Hex keeps its component cache in aux: a header of 16 bytes, both
-        # players' stones (4 bytes per 32 cells each), a 2-byte parent per
-        # cell, rounded up to 16 bytes; the other games have none
-        nwc = (cells.value + 31) // 32
-        assert aux.value == ((16 + 8 * nwc + 2 * cells.value + 15) // 16 * 16 if k == 3 else 0)
+        # Hex keeps its component cache in aux: one 128-byte line for the tag
+        # and both players' stones, then a 2-byte parent per cell rounded up
+        # to whole lines; the other games have none
+        assert aux.value == (128 + (2 * cells.value + 127) // 128 * 128 if k == 3 else 0)
         assert L.ludax_game_destroy(h) == 0
     rc, h = _create(2, 6, 7, 10)
     mp = ctypes.c_int32()
@@ -77,7 +76,7 @@ def test_aux_argument_checks_need_no_gpu():
     rc, hex11 = _create(3, 11, 11)
     rc2, gomoku = _create(5, 15, 15)
     assert rc == 0 and rc2 == 0
-    odd_aux = ludax._State(*([16] * 7), 24)
+    odd_aux = ludax._State(*([16] * 7), 64)
     no_aux = ludax._State(*([16] * 7), None)
     assert L.ludax_init(hex11, ctypes.byref(odd_aux), 5, None) == ludax.E_INVALID
     assert L.ludax_random_step(hex11, ctypes.byref(odd_aux), 1, 0, None, vp(16), vp(16), 5, None) == ludax.E_INVALID

@@ -118,3 +118,54 @@ def test_guided_step_rejects_unsupported():
     ludax.init(g19, s19)
     with pytest.raises(ludax.LudaxError):
         net19.guided_step(g19, s19, 1)
+
+
+@pytest.mark.parametrize("kind,plies", [(ref.HEX, 20), (ref.GOMOKU, 7), (ref.HEX, 0)],
+                         ids=["hex11-20", "gomoku11-7", "hex11-0"])
+def test_guided_playout_equals_steps_then_estimate(kind, plies):
+    """ludax_net_guided_playout (one kernel: every ply's forward pass, draw
+    and step on chip, then the value cutoff) against `plies` calls of
+    ludax_net_forward + ludax_policy_step and then ludax_net_estimate:
+    identical states and estimates bit for bit, with ended and ILLEGAL envs,
+    a ragged last 4-board group and explicit game ids."""
+    og, dg = pair(kind, 11, 11)
+    rng = np.random.default_rng(90 + kind + plies)
+    n = 2051
+    s = random_states(og, n, 60, rng)
+    s.status[:300:7] = ref.ILLEGAL
+    a = to_device(dg, s)
+    b = ludax.State.from_tensors(dg, **{f: getattr(a, f).clone() for f in FIELDS})
+    gid = torch.from_numpy(rng.integers(0, 2**62, size=n, dtype=np.int64)).cuda()
+    net = ludax.Net(11, 11, params=torch.from_numpy(init_net_params(23)).cuda())
+    seed = 0x5EED
+    est_a = net.guided_playout(dg, a, plies, seed, game_id=gid)
+    for _ in range(plies):
+        logits, _ = net.forward(b.board, b.to_move)
+        ludax.policy_step(dg, b, logits, seed, game_id=gid)
+    est_b = net.estimate(b)
+    for f in FIELDS:
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+    assert torch.equal(est_a, est_b)
+    st = a.status.cpu().numpy()
+    assert (st == ref.TERMINAL).any() or plies < 10
+
+
+def test_guided_playout_value_matches_oracle():
+    """With no plies the guided playout is the value cutoff of the given
+    positions: against the float64 oracle network (relative L2 1e-3) on
+    running envs, the exact outcome on ended ones."""
+    og, dg = pair(ref.HEX, 11, 11)
+    rng = np.random.default_rng(95)
+    n = 203
+    s = random_states(og, n, 80, rng)
+    d = to_device(dg, s)
+    p = init_net_params(24)
+    net = ludax.Net(11, 11, params=torch.from_numpy(p).cuda())
+    est = net.guided_playout(dg, d, 0, 1).cpu().numpy()
+    v = R.forward(p.astype(np.float64), s.board, s.to_move, 11)["value"]
+    exp = np.where(s.status == ref.TERMINAL, np.where(s.winner == 1, 1.0, np.where(s.winner == 2, -1.0, 0.0)),
+                   np.where(s.status == ref.RUNNING, np.where(s.to_move == 1, v, -v), 0.0))
+    run = s.status == ref.RUNNING
+    assert np.array_equal(est[~run], exp[~run])
+    err = np.linalg.norm(est[run] - exp[run]) / np.linalg.norm(exp[run])
+    assert err < 1e-3, err

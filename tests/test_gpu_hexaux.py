@@ -48,8 +48,7 @@ def _oracle_random_step(og, s, seed, gid):
 def test_aux_bytes():
     for N in SIZES:
         g = ludax.Game(ref.HEX, N, N)
-        nwc = (N * N + 31) // 32
-        assert g.aux_bytes == (16 + 8 * nwc + 2 * N * N + 15) // 16 * 16
+        assert g.aux_bytes == 128 + (2 * N * N + 127) // 128 * 128
     assert ludax.Game(ref.GOMOKU, 15, 15).aux_bytes == 0
 
 
