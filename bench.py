@@ -139,6 +139,26 @@ def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: i
     return out
 
 
+def _mixed_equal_split_ms(m, kinds: int, total: int, seed: int, n: int, out, reps: int = 3) -> float:
+    """Median event-timed batch of the mixed handle under the equal slot
+    split (the plan before autotuning)."""
+    import statistics
+
+    import torch
+
+    m.slots = [total // kinds // 64 * 64] * kinds
+    m.playout(seed, 0, n, out=out, stats=None)
+    ts = []
+    for k in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        m.playout(seed, 0, n, out=out, stats=None)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
 def _mixed_section(seed: int, steps: int, warmup: int):
     """Mixed persistent batch (Reversi 8x8, Gomoku 15x15, Hex 11x11,
     Connect Four 6x7; game id g has kind g mod 4): 4 x 262144 game ids
@@ -154,6 +174,7 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     m = ludax.Mixed(games)
     n = mb.n_games
     out = ludax.MixedResult(n, len(games))
+    equal_ms = _mixed_equal_split_ms(m, len(games), mb.slots, seed, n, out)
     tune_ms = m.autotune(seed, 0, n, mb.slots, out=out)
     stats = torch.zeros((len(games), 4), dtype=torch.int64, device="cuda")
     side = torch.cuda.Stream()
@@ -206,7 +227,7 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     return {
         "workload": f"{mb.name}: {n} game ids, kind = id mod 4 "
                     f"({', '.join(b.name for b in mb.kinds)}), {mb.slots} slots with refill",
-        "slots_per_kind": m.slots, "autotuned_ms": tune_ms,
+        "slots_per_kind": m.slots, "autotuned_ms": tune_ms, "equal_split_ms": equal_ms,
         "mixed_graph_env_steps_per_s": g_steps / g_el,
         "mixed_graph_ms_per_batch": g_el / steps * 1e3,
         "mixed_eager_env_steps_per_s": e_steps / e_el,
@@ -390,6 +411,7 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
     n_games = sum(b.n for b in kinds)
     m = ludax.Mixed(games)
     out = ludax.MixedResult(n_games, len(games))
+    equal_ms = _mixed_equal_split_ms(m, len(games), 262144, seed, n_games, out)
     tune_ms = m.autotune(seed, 0, n_games, 262144, out=out)
     stats = torch.zeros((len(games), 4), dtype=torch.int64, device="cuda")
     m.playout(seed, 0, n_games, out=out, stats=stats)
@@ -401,7 +423,8 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
     torch.cuda.synchronize()
     mixed_el = (time.perf_counter() - t0) / reps
     res = {"workload": f"{n_games} game ids, kind = id mod 2 (hex19x19, gomoku19x19)",
-           "mixed": {"slots_per_kind": m.slots, "autotuned_ms": tune_ms, "ms_per_batch": mixed_el * 1e3,
+           "mixed": {"slots_per_kind": m.slots, "autotuned_ms": tune_ms, "equal_split_ms": equal_ms,
+                     "ms_per_batch": mixed_el * 1e3,
                      "env_steps_per_s": int(stats[:, 0].sum()) / reps / mixed_el,
                      "playouts_per_s": n_games / mixed_el,
                      "per_kind_env_steps_per_batch": [int(x) // reps for x in stats[:, 0].tolist()]},
@@ -446,6 +469,17 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
                 torch.cuda.synchronize()
                 timings[name] = time.perf_counter() - t0
             timings[name + "_mse"] = ((est[:sub] - tr) ** 2).mean().item()
+        # network-guided playouts: 20 plies proposed by the policy (forward +
+        # policy step per ply) for both sides, then the value cutoff, in chunks
+        # admitted by the same HBM budget
+        s = base.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est = learn.guided_budgeted(g, net, s, 20, budget, seed + 980, 6 * 10**9)
+        torch.cuda.synchronize()
+        timings["policy20_budgeted"] = time.perf_counter() - t0
+        timings["policy20_budgeted_mse"] = ((est[:sub] - tr) ** 2).mean().item()
+        del s
         k, mse_k, pps = _averaged_playouts_at_error(g, held, tr, timings["value_budgeted_mse"], base, seed + 970,
                                                     5 * 10**9)
         res["guided"][b.name] = {
@@ -458,7 +492,10 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
             "plain_full_playout": {"playouts_per_s": n / timings["plain_full_playout"],
                                    "mse_vs_256_playout_mean": timings["plain_full_playout_mse"]},
             "value_budgeted": {"playouts_per_s": n / timings["value_budgeted"],
-                               "mse_vs_256_playout_mean": timings["value_budgeted_mse"]}}
+                               "mse_vs_256_playout_mean": timings["value_budgeted_mse"]},
+            "policy20_value_cutoff_budgeted": {"playouts_per_s": n / timings["policy20_budgeted"],
+                                               "mse_vs_256_playout_mean": timings["policy20_budgeted_mse"],
+                                               "chunk": learn.guided_chunk(net, budget, g.cells)}}
         del base, held, net
         torch.cuda.synchronize()
     return res

@@ -334,11 +334,17 @@ int ludax_mixed_playout_noalloc(ludax_mixed *mixed, uint64_t seed, int64_t id_ba
                                 hipStream_t stream);
 
 /* The slot autotuner: times each kind alone at total_slots / n_kinds lanes
- * to estimate its work, then times whole batches under candidate splits of
- * total_slots (equal, proportional to the work, to its square root, and
- * the proportional split with the largest kind's share moved by +-25 %)
- * and keeps the fastest as the handle's plan.  Runs real batches with the
- * given arguments (outputs are overwritten) and SYNCHRONISES the stream.
+ * (its work) and at half and twice that (how its time scales with its
+ * lanes: T(S) ~ T(S0) (S / S0)^-beta, beta = 1 for a kind that turns every
+ * lane into speed, near 0 for one bound by its longest games), then times
+ * whole batches under candidate splits of total_slots: equal, proportional
+ * to the work, to its square root, the proportional split with the
+ * largest kind's share moved by +-25 %, and the occupancy plan that brings
+ * every kind's fitted time to a common value with the lanes adding up to
+ * total_slots (and that plan with the flattest-scaling kind's share moved
+ * by +-25 %); keeps the fastest as the handle's plan
+ * (ludax_mixed_get_slots reads it).  Runs real batches with the given
+ * arguments (outputs are overwritten) and SYNCHRONISES the stream.
  * *best_ms (may be NULL) receives the chosen plan's time. */
 int ludax_mixed_autotune(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int64_t n_games,
                          int32_t total_slots, int8_t *winner, int16_t *plies, int16_t *last_action,

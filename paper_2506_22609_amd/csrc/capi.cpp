@@ -502,17 +502,39 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
     if (rc) return rc;
     if (n_games == 0 || total_slots < 64 * m->n) return LUDAX_E_INVALID;
     const int n = m->n;
-    // 1. each kind alone at an equal share: its work in lane-milliseconds
+    // 1. each kind alone at an equal share: its work in lane-milliseconds;
+    //    and at half and twice that share, for how its time scales with its
+    //    lanes (a kind bound by its longest games, or already filling the
+    //    chip, gains little from more)
     int32_t eq[MAX_KINDS];
-    double w[MAX_KINDS], root[MAX_KINDS];
+    double w[MAX_KINDS], root[MAX_KINDS], t_eq[MAX_KINDS], beta[MAX_KINDS];
     const double ones[MAX_KINDS] = {1, 1, 1, 1, 1, 1, 1, 1};
     split(ones, n, total_slots, eq);
     for (int k = 0; k < n; ++k) {
         float ms = 0.f;
         rc = timed_run(m, eq, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream, &ms);
         if (rc) return rc;
+        t_eq[k] = ms;
         w[k] = (double)ms * eq[k];
         root[k] = std::sqrt(w[k]);
+        double slope = 0.0;
+        int fits = 0;
+        for (double f : {0.5, 2.0}) {
+            int32_t alt[MAX_KINDS];
+            for (int j = 0; j < n; ++j) alt[j] = eq[j];
+            alt[k] = std::max<int32_t>(64, std::min<int32_t>((int32_t)(eq[k] * f) / 64 * 64, 1 << 24));
+            if (alt[k] == eq[k]) continue;
+            float ms2 = 0.f;
+            rc = timed_run(m, alt, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream,
+                           &ms2);
+            if (rc) return rc;
+            if (ms > 0.f && ms2 > 0.f) {
+                slope += -std::log((double)ms2 / ms) / std::log((double)alt[k] / eq[k]);
+                ++fits;
+            }
+        }
+        // T_k(S) ~ t_eq (S / eq)^(-beta): beta = 1 for perfect scaling
+        beta[k] = std::max(0.05, std::min(1.5, fits ? slope / fits : 1.0));
     }
     // 2. candidate splits of the whole batch
     std::vector<std::vector<int32_t>> plans;
@@ -531,6 +553,33 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
         double v[MAX_KINDS];
         for (int k = 0; k < n; ++k) v[k] = k == big ? w[k] * f : w[k];
         add(v);
+    }
+    // the occupancy plan: the kinds run side by side and the batch ends with
+    // the slowest, so give each kind the lanes that bring its fitted time to
+    // a common T, with T such that the lanes add up to total_slots (bisection
+    // on log T); and the same plan with the slowest-scaling kind's share
+    // moved by -25 % and +25 %
+    {
+        double lo = 1e-6, hi = 1e6;
+        double occ[MAX_KINDS];
+        for (int it = 0; it < 100; ++it) {
+            const double T = std::sqrt(lo * hi);
+            double sum = 0.0;
+            for (int k = 0; k < n; ++k) sum += eq[k] * std::pow(t_eq[k] / T, 1.0 / beta[k]);
+            if (sum > total_slots) lo = T;
+            else hi = T;
+        }
+        const double T = std::sqrt(lo * hi);
+        for (int k = 0; k < n; ++k) occ[k] = eq[k] * std::pow(t_eq[k] / T, 1.0 / beta[k]);
+        add(occ);
+        int flat = 0;
+        for (int k = 1; k < n; ++k)
+            if (beta[k] < beta[flat]) flat = k;
+        for (double f : {0.75, 1.25}) {
+            double v[MAX_KINDS];
+            for (int k = 0; k < n; ++k) v[k] = k == flat ? occ[k] * f : occ[k];
+            add(v);
+        }
     }
     // 3. keep the fastest (a warm-up run first)
     float best = 0.f;

@@ -560,72 +560,75 @@ __global__ __launch_bounds__(BLOCK) void k_hexaux_sync(DevState st, int64_t n)
     *reinterpret_cast<uint32_t *>(ax) = FROM_BOARD ? aux_tag(st.ply[ec], st.last_action[ec]) : aux_tag(0, -1);
 }
 
-// The draw of ludax_policy_step when the exponentials are already at hand:
-// ex[c] = exp(logit[c] - max over the legal cells) for every legal cell c
-// (computed once per cell by the lanes of a wave), legal cells the empty
-// ones of the board row brow.  The same float32 sums in the same order as
-// choose_action MODE 2, so the same action; -1 when no cell is empty.
+// The draw of ludax_policy_step for one board by the 64 lanes of a wave
+// (lg: its logits in action order, brow: its board bytes; cells <= 128, two
+// per lane, the legal actions the empty cells).  The same float32 values in
+// the same order as choose_action MODE 2: the maximum over the legal cells
+// (a wave reduction, exact in any order), exp(logit - max) per cell, the
+// running sum in increasing cell order (one uniform add per legal cell,
+// the sum so far recorded at that cell's lane), the threshold u * total;
+// the first legal cell whose running sum exceeds it, by a ballot (the last
+// legal cell if none).  Uniform result; -1 when no cell is empty.
 template <int CELLS>
-__device__ __forceinline__ int draw_from_exps(const float *ex, const int8_t *brow, uint32_t w)
+__device__ __forceinline__ int wave_policy_draw(const float *lg, const int8_t *brow, uint32_t w)
 {
-    float tot = 0.f;
-    int np = 0;
-    for (int c = 0; c < CELLS; ++c)
-        if (brow[c] == 0) {
-            tot += ex[c];
-            ++np;
-        }
-    if (np == 0) return -1;
-    const float thr = (float)(w >> 8) * 0x1p-24f * tot;
-    float run = 0.f;
-    int pick = -1, lastc = -1;
-    for (int c = 0; c < CELLS; ++c)
-        if (brow[c] == 0) {
-            run += ex[c];
-            lastc = c;
-            if (pick < 0 && run > thr) pick = c;
-        }
-    return pick >= 0 ? pick : lastc;
-}
-
-// The exponentials of draw_from_exps for one board, by all 64 lanes of its
-// wave: the maximum logit over the empty cells (a wave reduction, exact in
-// any order), then exp(logit - max) of each empty cell into ex.
-template <int CELLS>
-__device__ __forceinline__ void wave_exps(const float *lg, const int8_t *brow, float *ex)
-{
+    static_assert(CELLS <= 128, "two cells per lane");
     const int lane = threadIdx.x & 63;
-    float mx = -3.0e38f;
-    for (int c = lane; c < CELLS; c += 64)
-        if (brow[c] == 0) mx = fmaxf(mx, lg[c]);
+    const bool l0 = lane < CELLS && brow[lane] == 0;
+    const bool l1 = lane + 64 < CELLS && brow[lane + 64] == 0;
+    const float g0 = l0 ? lg[lane] : -3.0e38f, g1 = l1 ? lg[lane + 64] : -3.0e38f;
+    float mx = fmaxf(-3.0e38f, fmaxf(g0, g1));
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) mx = fmaxf(mx, __shfl_xor(mx, s));
-    for (int c = lane; c < CELLS; c += 64) ex[c] = brow[c] == 0 ? expf(lg[c] - mx) : 0.f;
+    for (int sft = 32; sft >= 1; sft >>= 1) mx = fmaxf(mx, __shfl_xor(mx, sft));
+    const float e0 = l0 ? expf(g0 - mx) : 0.f, e1 = l1 ? expf(g1 - mx) : 0.f;
+    const uint64_t m0 = __ballot(l0), m1 = __ballot(l1);
+    if ((m0 | m1) == 0) return -1;
+    float run = 0.f, r0 = 0.f, r1 = 0.f;
+    for (int c = 0; c < CELLS; ++c) {
+        const bool hi = c >= 64;
+        const int k = hi ? c - 64 : c;
+        if (((hi ? m1 : m0) >> k) & 1u) {
+            const float ec = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hi ? e1 : e0), k));
+            run += ec;
+            if (lane == k) {
+                if (hi) r1 = run;
+                else r0 = run;
+            }
+        }
+    }
+    const float thr = (float)(w >> 8) * 0x1p-24f * run;
+    const uint64_t h0 = __ballot(l0 && r0 > thr), h1 = __ballot(l1 && r1 > thr);
+    if (h0) return __builtin_ctzll(h0);
+    if (h1) return 64 + __builtin_ctzll(h1);
+    return m1 ? 64 + 63 - __builtin_clzll(m1) : 63 - __builtin_clzll(m0);
 }
 
-// One ply of ludax_policy_step for env e, run by a single lane that has the
-// env's exponentials (ex, see wave_exps) and board bytes (brow, with
-// readable slack behind it, as in read_board) at hand: the fused guided
-// steps of the network, which keep the logits on chip.  Same draw, rules
+// One ply of ludax_policy_step for env e by the 64 lanes of a wave (every
+// lane computes the same values; lane 0 writes): the fused guided steps of
+// the network, which keep the logits (lg) and the board bytes (brow, with
+// readable slack behind it, as in read_board) on chip.  Same draw, rules
 // and state as k_step MODE 2 for the placement games whose legal actions
 // are the empty cells and whose ply changes one cell (Hex, Gomoku).
-// reward / terminal may be NULL.  Returns the cell played, or -1.
+// reward / terminal may be NULL.  Returns the cell played (-1 if none), and
+// the env's side to move and whether it still runs after the ply.
 template <class G>
-__device__ __forceinline__ int policy_ply_exps(const DevState &st, int64_t e, int max_plies, const float *ex,
+__device__ __forceinline__ int wave_policy_ply(const DevState &st, int64_t e, int max_plies, const float *lg,
                                                const int8_t *brow, uint32_t key0, uint32_t key1, int64_t gid_base,
                                                const int64_t *__restrict__ gid, int8_t *__restrict__ reward,
-                                               uint8_t *__restrict__ terminal)
+                                               uint8_t *__restrict__ terminal, int &to_move, bool &running)
 {
     static_assert(G::KIND == 3 || G::KIND == 5, "legal actions = empty cells, one cell per ply");
+    const int lane = threadIdx.x & 63;
     int status = st.status[e];
+    int me = st.to_move[e];
     int r1 = 0, r2 = 0, played = -1;
     if (status == RUNNING) {
-        int me = st.to_move[e], winner = st.winner[e], passes = st.passes[e], ply = st.ply[e];
+        int winner = st.winner[e], passes = st.passes[e], ply = st.ply[e];
         const uint64_t id = (uint64_t)(gid != nullptr ? gid[e] : gid_base + e);
         const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
         const int r = ply & 3;
         const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
-        const int a = draw_from_exps<G::CELLS>(ex, brow, w);
+        const int a = wave_policy_draw<G::CELLS>(lg, brow, w);
         if (a < 0) {
             status = ILLEGAL;
         } else {
@@ -648,21 +651,27 @@ __device__ __forceinline__ int policy_ply_exps(const DevState &st, int64_t e, in
                     winner = -1;
                 }
             }
-            st.board[e * G::CELLS + a] = (int8_t)mover;
-            st.to_move[e] = (int8_t)me;
-            st.winner[e] = (int8_t)winner;
-            st.passes[e] = (int8_t)passes;
-            st.ply[e] = (int16_t)ply;
-            st.last_action[e] = (int16_t)a;
+            if (lane == 0) {
+                st.board[e * G::CELLS + a] = (int8_t)mover;
+                st.to_move[e] = (int8_t)me;
+                st.winner[e] = (int8_t)winner;
+                st.passes[e] = (int8_t)passes;
+                st.ply[e] = (int16_t)ply;
+                st.last_action[e] = (int16_t)a;
+            }
             played = a;
         }
-        st.status[e] = (int8_t)status;
+        if (lane == 0) st.status[e] = (int8_t)status;
     }
-    if (reward != nullptr) {
-        reward[2 * e] = (int8_t)r1;
-        reward[2 * e + 1] = (int8_t)r2;
+    if (lane == 0) {
+        if (reward != nullptr) {
+            reward[2 * e] = (int8_t)r1;
+            reward[2 * e + 1] = (int8_t)r2;
+        }
+        if (terminal != nullptr) terminal[e] = status != RUNNING ? 1 : 0;
     }
-    if (terminal != nullptr) terminal[e] = status != RUNNING ? 1 : 0;
+    to_move = me;
+    running = status == RUNNING;
     return played;
 }
 

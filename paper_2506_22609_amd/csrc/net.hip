@@ -827,23 +827,22 @@ __global__ __launch_bounds__(LdsL<N>::THREADS, 2) void k_conv_lds(const uint16_t
         __syncthreads();
         constexpr int LGS = (PIX + 3) / 4 * 4, BRS = (PIX + 31) / 16 * 16;
         float *lg = reinterpret_cast<float *>(xs) + slot * LGS;
-        float *ex = reinterpret_cast<float *>(xs) + BPB * LGS + slot * LGS;
-        int8_t *brow = reinterpret_cast<int8_t *>(xs) + 2 * BPB * LGS * 4 + slot * BRS;
-        static_assert(2 * BPB * LGS * 4 + BPB * BRS <= BPB * PP * 32 * 2, "logits, exponentials and boards fit the tile");
+        int8_t *brow = reinterpret_cast<int8_t *>(xs) + BPB * LGS * 4 + slot * BRS;
+        static_assert(BPB * LGS * 4 + BPB * BRS <= BPB * PP * 32 * 2, "logits and boards fit the tile");
         if (live) {
             heads_to_lds<N, NTW>(acc, cell_off, vmask, c0, b, a1, lg);
             for (int j = lane; j < PIX; j += 64) brow[j] = a1.board[b * PIX + j];
         }
         __syncthreads();
-        if (live) wave_exps<PIX>(lg, brow, ex);
-        __syncthreads();
-        if (live && lane == 0) {
+        if (live) {
+            int tmv;
+            bool run;
             if (a1.kind == 3)
-                policy_ply_exps<Hex<N>>(a1.st, b, a1.max_plies, ex, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
-                                        a1.reward, a1.terminal);
+                wave_policy_ply<Hex<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                        a1.reward, a1.terminal, tmv, run);
             else
-                policy_ply_exps<Gomoku<N>>(a1.st, b, a1.max_plies, ex, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
-                                           a1.reward, a1.terminal);
+                wave_policy_ply<Gomoku<N>>(a1.st, b, a1.max_plies, lg, brow, a1.key0, a1.key1, a1.gid_base, a1.gid,
+                                           a1.reward, a1.terminal, tmv, run);
         }
         return;
     }
@@ -899,47 +898,112 @@ struct FusedArgs {
     float *estimate;
 };
 
-// One lane's guided ply in k_fwd11 MODE 1 (policy_ply_exps for the game).
-__device__ __forceinline__ int fused_ply(const FusedArgs &fa, int64_t b, const float *ex, const int8_t *brow)
+// One guided ply of a board whose env state lives in LDS for the whole
+// group (k_fwd11 MODE 1), by the 64 lanes of its wave: sc = {status, side
+// to move, winner, passes, ply, last action}, brow = its board bytes, lg =
+// its logits.  The draw and the rules are those of wave_policy_ply; lane 0
+// updates sc and brow.  Returns the cell played, or -1.
+template <class G>
+__device__ __forceinline__ int lds_policy_ply(int *sc, uint64_t id, int max_plies, const float *lg, int8_t *brow,
+                                              uint32_t key0, uint32_t key1)
 {
-    return fa.kind == 3 ? policy_ply_exps<Hex<11>>(fa.st, b, fa.max_plies, ex, brow, fa.key0, fa.key1, fa.gid_base,
-                                                   fa.gid, nullptr, nullptr)
-                        : policy_ply_exps<Gomoku<11>>(fa.st, b, fa.max_plies, ex, brow, fa.key0, fa.key1, fa.gid_base,
-                                                      fa.gid, nullptr, nullptr);
+    const int lane = threadIdx.x & 63;
+    int status = sc[0];
+    if (status != RUNNING) return -1;
+    int me = sc[1], winner = sc[2], passes = sc[3], ply = sc[4];
+    const Philox4 f = philox4x32_10((uint32_t)ply >> 2, (uint32_t)id, (uint32_t)(id >> 32), 0u, key0, key1);
+    const int r = ply & 3;
+    const uint32_t w = r == 0 ? f.v[0] : (r == 1 ? f.v[1] : (r == 2 ? f.v[2] : f.v[3]));
+    const int a = wave_policy_draw<G::CELLS>(lg, brow, w);
+    if (a < 0) {
+        if (lane == 0) sc[0] = ILLEGAL;
+        return -1;
+    }
+    BB<G::NWC> c1, c2;
+    read_board<G::CELLS, G::NWC>(brow, c1, c2);
+    G g;
+    g.load(c1, c2);
+    const int outcome = g.place_step(G::bit_of(a), me, passes);
+    const int mover = me;
+    ply += 1;
+    if (outcome >= 0) {
+        status = TERMINAL;
+        winner = outcome;
+    } else {
+        me = 3 - me;
+        if (ply >= max_plies) {
+            status = TRUNCATED;
+            winner = -1;
+        }
+    }
+    if (lane == 0) {
+        brow[a] = (int8_t)mover;
+        sc[0] = status;
+        sc[1] = me;
+        sc[2] = winner;
+        sc[3] = passes;
+        sc[4] = ply;
+        sc[5] = a;
+    }
+    return a;
 }
 
 constexpr int FUSED_BLOCKS_PER_CU = 1;
 
-template <int MODE>
-__global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
+// Geometry of the fused 11x11 forward: 4 boards per block, two waves per
+// board (cell tiles 0-3 and 4-7), 8 waves.
+struct Fused11 {
+    static constexpr int SIDE = 11, NP = 13, PP = NP * NP, PIX = 121, MT = 8, BPB = 4, THREADS = 512;
+    static constexpr int WS = 9 * 32 + 8;
+};
+
+// Stage weight half i (layer 2 + i / 2, input channels 32 (i % 2) ..) of
+// the packed forward weights into an LDS buffer of [64][WS] rows, in the
+// row permutation of w_channel (memory to LDS directly, the block's waves
+// sharing the 37 chunks of each row).
+__device__ __forceinline__ void stage_weight_half(const uint16_t *packed, int i, uint16_t *dst)
 {
-    constexpr int N = 11;
-    using L = LdsL<N>;
-    constexpr int NP = L::NP, PP = L::PP, PIX = L::PIX, BPB = L::BPB, WS = L::WS, NTW = 4;
-    static_assert(L::NG == 1 && L::NSPLIT == 1 && L::MT == 8 && BPB == 4 && L::THREADS == 256, "one wave per board");
-    __shared__ __align__(16) uint16_t ws[C * WS];
+    constexpr int WS = Fused11::WS, WCH = C * (WS / 8), NWAVES = Fused11::THREADS / 64;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint16_t *w = packed + pf_off(2 + i / 2);
+    const int h = i % 2;
+    for (int base = wid * 64; base < WCH; base += NWAVES * 64) {
+        const int j = base + lane, srow = j / (WS / 8), col = j % (WS / 8);
+        const int o = w_channel<4>(srow), t = col < 36 ? col >> 2 : 0, c8 = col < 36 ? col & 3 : 0;
+        if (j < WCH)
+            __builtin_amdgcn_global_load_lds((glb_void *)(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8),
+                                             (lds_void *)(dst + base * 8), 16, 0, 0);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(512, 1) void k_fwd11(FusedArgs fa)
+{
+    using L = Fused11;
+    constexpr int N = L::SIDE, NP = L::NP, PP = L::PP, PIX = L::PIX, BPB = L::BPB, WS = L::WS, NTW = 4, TPW = 4;
+    constexpr int NT = L::THREADS;
+    // two weight buffers: half i + 1 is staged while half i is multiplied
+    __shared__ __align__(16) uint16_t ws[2][C * WS];
     __shared__ __align__(16) uint16_t xa[2][BPB * PP * 32];
     __shared__ __align__(16) int8_t brow[BPB][144];
     __shared__ uint8_t cc[BPB * PP];
-    __shared__ float lgs[BPB][124], exs[BPB][124];
-    __shared__ int tm[BPB], alive[BPB];
+    // each board's env state for the group: status, side to move, winner,
+    // passes, ply, last action (MODE 0: only the side to move)
+    __shared__ int scal[BPB][6];
 
-    const int lane = threadIdx.x & 63, slot = threadIdx.x >> 6, row = lane & 15, quad = lane >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, slot = wave >> 1, g = wave & 1;
+    const int row = lane & 15, quad = lane >> 4;
     const int c0 = 16 * quad; // this lane's output channels c0 .. c0 + 15
-    int cell_off[8];
-    unsigned vmask = 0;
+    // this wave's cell tiles 4 g .. 4 g + 3; vmask8: which of all 8 tiles have a cell in this lane's row
+    int cell_off[TPW];
+    unsigned vmask = 0, vmask8 = 0;
 #pragma unroll
-    for (int mt = 0; mt < 8; ++mt) {
-        const int e = tile_entry<N>(mt, row);
+    for (int mt = 0; mt < 8; ++mt) vmask8 |= (tile_entry<N>(mt, row) >= 0 ? 1u : 0u) << mt;
+#pragma unroll
+    for (int mt = 0; mt < TPW; ++mt) {
+        const int e = tile_entry<N>(TPW * g + mt, row);
         cell_off[mt] = entry_q(e);
         vmask |= (e >= 0 ? 1u : 0u) << mt;
-    }
-    // the rings of both halves' tiles stay zero: only interior cells are written
-    for (int j = threadIdx.x; j < 2 * BPB * 4 * (NP - 1) * 4; j += 256) {
-        const int hh = j / (BPB * 4 * (NP - 1) * 4), r0 = j % (BPB * 4 * (NP - 1) * 4);
-        const int bb = r0 / (4 * (NP - 1) * 4), r = r0 % (4 * (NP - 1) * 4);
-        const int q = ring_cell<NP>(r >> 2);
-        *reinterpret_cast<uint4 *>(xa[hh] + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
     }
     const float *params = fa.params;
     const uint16_t *packed = fa.packed;
@@ -947,87 +1011,106 @@ __global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
     FwdArgs a1{};
     a1.w1 = packed + pf_off(1);
     a1.b1 = params + b_off(1);
+    // the heads' scratch borrows the start of the first tile once every
+    // wave's products are done: per board 128 logits and the value partials
+    // of its 8 tiles x 16 rows; so the rings, zero in
+    // every layer's input, are re-zeroed at the start of each round
+    float *hs = reinterpret_cast<float *>(xa[0]);
+    float *lgs = hs, *vps = hs + BPB * 128;
+    auto zero_rings = [&]() {
+        for (int j = threadIdx.x; j < 2 * BPB * 4 * (NP - 1) * 4; j += NT) {
+            const int hh = j / (BPB * 4 * (NP - 1) * 4), r0 = j % (BPB * 4 * (NP - 1) * 4);
+            const int bb = r0 / (4 * (NP - 1) * 4), r = r0 % (4 * (NP - 1) * 4);
+            const int q = ring_cell<NP>(r >> 2);
+            *reinterpret_cast<uint4 *>(xa[hh] + (bb * PP + q) * 32 + (r & 3) * 8) = uint4{0u, 0u, 0u, 0u};
+        }
+    };
+    stage_weight_half(packed, 0, ws[0]);
 
-    for (int64_t b0 = (int64_t)blockIdx.x * BPB; b0 < n; b0 += (int64_t)gridDim.x * BPB) {
+    const int64_t stride = (int64_t)gridDim.x * BPB;
+    for (int64_t b0 = (int64_t)blockIdx.x * BPB; b0 < n; b0 += stride) {
         const int64_t b = b0 + slot;
         const bool live = b < n;
-        __syncthreads(); // the previous group is done with brow, tm and alive
-        // the group's boards and sides to move
-        for (int j = threadIdx.x; j < BPB * PIX; j += 256) {
+        __syncthreads(); // the previous group is done with brow and scal
+        for (int j = threadIdx.x; j < BPB * PIX; j += NT) {
             const int bb = j / PIX, c = j % PIX;
             const int8_t *src = MODE == 0 ? fa.board : fa.st.board;
             brow[bb][c] = b0 + bb < n ? src[(b0 + bb) * PIX + c] : (int8_t)0;
         }
         if (threadIdx.x < BPB) {
             const int64_t bt = b0 + threadIdx.x;
-            const int8_t *tmv = MODE == 0 ? fa.to_move : fa.st.to_move;
-            tm[threadIdx.x] = bt < n ? (int)tmv[bt] : 1;
-            alive[threadIdx.x] = bt < n && (MODE == 0 || fa.st.status[bt] == 0);
+            const bool in = bt < n;
+            int *sc = scal[threadIdx.x];
+            if constexpr (MODE == 0) {
+                sc[0] = ILLEGAL;
+                sc[1] = in ? (int)fa.to_move[bt] : 1;
+            } else {
+                sc[0] = in ? (int)fa.st.status[bt] : ILLEGAL;
+                sc[1] = in ? (int)fa.st.to_move[bt] : 1;
+                sc[2] = in ? (int)fa.st.winner[bt] : -1;
+                sc[3] = in ? (int)fa.st.passes[bt] : 0;
+                sc[4] = in ? (int)fa.st.ply[bt] : 0;
+                sc[5] = in ? (int)fa.st.last_action[bt] : -1;
+            }
         }
         const int rounds = MODE == 0 ? 1 : fa.plies + 1;
         for (int ply = 0; ply < rounds; ++ply) {
-            __syncthreads(); // brow / tm / alive of the previous ply are written
+            __syncthreads(); // brow / scal of the previous ply are written
             const bool last = ply == rounds - 1;
             if constexpr (MODE == 1) {
                 // no env of the group running and no value left to compute
-                if (!last && !(alive[0] | alive[1] | alive[2] | alive[3])) continue;
+                if (!last && scal[0][0] != 0 && scal[1][0] != 0 && scal[2][0] != 0 && scal[3][0] != 0) continue;
             }
-            // cell codes (the encoder's planes in the mover's frame) from the board rows
-            for (int j = threadIdx.x; j < BPB * PP; j += 256) {
+            // is another round coming (this group's next ply or a next group)?
+            const bool more = !last || b0 + stride < n;
+            for (int j = threadIdx.x; j < BPB * PP; j += NT) {
                 const int bb = j / PP, q = j % PP, rr = q / NP - 1, c = q % NP - 1;
                 const bool in = b0 + bb < n && (unsigned)rr < (unsigned)N && (unsigned)c < (unsigned)N;
-                const int me = tm[bb];
+                const int me = scal[bb][1];
                 const int x = in ? (int)brow[bb][me == 2 ? c * N + rr : rr * N + c] : -1;
                 cc[j] = (uint8_t)(x < 0 ? 3 : (x == me ? 0 : (x == 0 ? 2 : 1)));
             }
+            zero_rings();
             __syncthreads();
             layer1_half<L>(a1, 0, b0, n, cc, xa[0]);
             layer1_half<L>(a1, 1, b0, n, cc, xa[1]);
-            f32x4 acc[8][NTW];
+            f32x4 acc[TPW][NTW];
 #pragma unroll 1
-            for (int l = 2; l <= 4; ++l) {
-                const uint16_t *w = packed + pf_off(l);
-                const float *bias = params + b_off(l);
+            for (int i = 0; i < 6; ++i) {
+                const int l = 2 + i / 2, h = i % 2;
+                if (h == 0) {
+                    const float *bias = params + b_off(l);
 #pragma unroll
-                for (int nt = 0; nt < NTW; ++nt) {
-                    const f32x4 bv = {bias[c0 + 4 * nt], bias[c0 + 4 * nt + 1], bias[c0 + 4 * nt + 2],
-                                      bias[c0 + 4 * nt + 3]};
+                    for (int nt = 0; nt < NTW; ++nt) {
+                        const f32x4 bv = {bias[c0 + 4 * nt], bias[c0 + 4 * nt + 1], bias[c0 + 4 * nt + 2],
+                                          bias[c0 + 4 * nt + 3]};
 #pragma unroll
-                    for (int mt = 0; mt < 8; ++mt) acc[mt][nt] = bv;
-                }
-                for (int h = 0; h < 2; ++h) {
-                    __syncthreads(); // ws is free; the layer's input is written
-                    {
-                        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-                        constexpr int WCH = C * (WS / 8);
-                        for (int base = wid * 64; base < WCH; base += 4 * 64) {
-                            const int i = base + lane, srow = i / (WS / 8), col = i % (WS / 8);
-                            const int o = w_channel<NTW>(srow), t = col < 36 ? col >> 2 : 0, c8 = col < 36 ? col & 3 : 0;
-                            if (i < WCH)
-                                __builtin_amdgcn_global_load_lds(
-                                    (glb_void *)(w + (int64_t)o * K2 + t * 64 + h * 32 + c8 * 8),
-                                    (lds_void *)(ws + base * 8), 16, 0, 0);
-                        }
+                        for (int mt = 0; mt < TPW; ++mt) acc[mt][nt] = bv;
                     }
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                    if (!live) continue;
+                }
+                // half i has landed (every wave's copies) and half i - 1's buffer is free
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (i < 5) stage_weight_half(packed, i + 1, ws[(i + 1) & 1]);
+                else if (more) stage_weight_half(packed, 0, ws[0]);
+                if (live) {
+                    const uint16_t *wb = ws[i & 1];
                     const uint16_t *xb = xa[h] + slot * PP * 32;
                     auto frag_b = [&](int t, bf16x8 (&bf)[NTW]) {
 #pragma unroll
                         for (int nt = 0; nt < NTW; ++nt)
                             bf[nt] = as_bf16x8(
-                                *reinterpret_cast<const uint4 *>(ws + (nt * 16 + row) * WS + t * 32 + quad * 8));
+                                *reinterpret_cast<const uint4 *>(wb + (nt * 16 + row) * WS + t * 32 + quad * 8));
                     };
-                    auto frag_a = [&](int t, bf16x8 (&af)[8]) {
+                    auto frag_a = [&](int t, bf16x8 (&af)[TPW]) {
                         const int toff = (t / 3) * NP + (t % 3);
 #pragma unroll
-                        for (int mt = 0; mt < 8; ++mt) {
+                        for (int mt = 0; mt < TPW; ++mt) {
                             const int q = cell_off[mt] + toff;
                             af[mt] = as_bf16x8(*reinterpret_cast<const uint4 *>(xb + q * 32 + ((quad + (q >> 2)) & 3) * 8));
                         }
                     };
-                    bf16x8 bcur[NTW], acur[8], bnxt[NTW], anxt[8];
+                    bf16x8 bcur[NTW], acur[TPW], bnxt[NTW], anxt[TPW];
                     frag_b(0, bcur);
                     frag_a(0, acur);
 #pragma unroll
@@ -1037,7 +1120,7 @@ __global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
                             frag_a(t + 1, anxt);
                         }
 #pragma unroll
-                        for (int mt = 0; mt < 8; ++mt)
+                        for (int mt = 0; mt < TPW; ++mt)
 #pragma unroll
                             for (int nt = 0; nt < NTW; ++nt)
                                 acc[mt][nt] =
@@ -1046,18 +1129,18 @@ __global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
 #pragma unroll
                             for (int nt = 0; nt < NTW; ++nt) bcur[nt] = bnxt[nt];
 #pragma unroll
-                            for (int mt = 0; mt < 8; ++mt) acur[mt] = anxt[mt];
+                            for (int mt = 0; mt < TPW; ++mt) acur[mt] = anxt[mt];
                         }
                     }
                 }
-                if (l < 4) {
+                if (h == 1 && l < 4) {
                     __syncthreads(); // every wave is done reading the layer's input
                     if (live) {
                         // bf16(relu) of channels c0 .. c0 + 15 of each cell over the input: half
                         // quad / 2, 16-byte chunks 2 (quad & 1) and 2 (quad & 1) + 1
                         uint16_t *xo = xa[quad >> 1] + slot * PP * 32;
 #pragma unroll
-                        for (int mt = 0; mt < 8; ++mt) {
+                        for (int mt = 0; mt < TPW; ++mt) {
                             if (!((vmask >> mt) & 1u)) continue;
                             const int q = cell_off[mt] + NP + 1;
 #pragma unroll
@@ -1078,83 +1161,96 @@ __global__ __launch_bounds__(256, 1) void k_fwd11(FusedArgs fa)
                     }
                 }
             }
-            // the heads on layer 4's accumulators
-            if constexpr (MODE == 0) {
-                if (live) {
-                    FwdArgs ah{};
-                    ah.to_move = fa.to_move;
-                    ah.params = params;
-                    ah.logits = fa.logits;
-                    ah.value = fa.value;
-                    heads_epilogue<N, NTW>(acc, cell_off, vmask, c0, b, ah);
+            // the heads on layer 4's accumulators (y = the layer's output as it
+            // would be stored): per cell the policy logit, per tile the value
+            // partial of each row; the same sums as heads_epilogue
+            const bool policy = MODE == 0 || !last;
+            const int me = scal[slot][1];
+            __syncthreads(); // the tiles are free: the heads' scratch goes there
+            if (live) {
+                float wp[16], wv[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    wp[j] = params[WP_OFF + c0 + j];
+                    wv[j] = params[WV_OFF + c0 + j];
                 }
-            } else {
-                const int me = tm[slot];
-                if (!last) {
-                    if (live) {
-                        // the policy logits (action order) of the board into LDS
-                        const float bp = params[BP_OFF];
-                        float wp[16];
+                const float bp = params[BP_OFF];
 #pragma unroll
-                        for (int j = 0; j < 16; ++j) wp[j] = params[WP_OFF + c0 + j];
+                for (int mt = 0; mt < TPW; ++mt) {
+                    float lp = 0.f, lv = 0.f;
 #pragma unroll
-                        for (int mt = 0; mt < 8; ++mt) {
-                            float lp = 0.f;
+                    for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-                            for (int nt = 0; nt < NTW; ++nt)
-#pragma unroll
-                                for (int k = 0; k < 4; ++k)
-                                    lp += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wp[4 * nt + k];
-                            lp += __shfl_xor(lp, 16);
-                            lp += __shfl_xor(lp, 32);
-                            if (((vmask >> mt) & 1u) && quad == 0) {
-                                const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
-                                lgs[slot][me == 2 ? c * N + r : r * N + c] = lp + bp;
-                            }
+                        for (int k = 0; k < 4; ++k) {
+                            const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
+                            lp += y * wp[4 * nt + k];
+                            lv += y * wv[4 * nt + k];
                         }
-                    }
-                    __syncthreads();
-                    if (live) wave_exps<PIX>(lgs[slot], brow[slot], exs[slot]);
-                    __syncthreads();
-                    if (live && lane == 0) {
-                        const int mover = me;
-                        const int a = fused_ply(fa, b, exs[slot], brow[slot]);
-                        if (a >= 0) {
-                            brow[slot][a] = (int8_t)mover;
-                            tm[slot] = fa.st.to_move[b];
-                        }
-                        alive[slot] = fa.st.status[b] == 0;
-                    }
-                } else if (live) {
-                    // the value cutoff: the network's value for RUNNING envs (for
-                    // player 1), the outcome of ended ones
-                    float sv = 0.f;
-                    float wv[16];
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) wv[j] = params[WV_OFF + c0 + j];
-#pragma unroll
-                    for (int mt = 0; mt < 8; ++mt) {
-                        float lv = 0.f;
-#pragma unroll
-                        for (int nt = 0; nt < NTW; ++nt)
-#pragma unroll
-                            for (int k = 0; k < 4; ++k) lv += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wv[4 * nt + k];
-                        lv += __shfl_xor(lv, 16);
-                        lv += __shfl_xor(lv, 32);
-                        if ((vmask >> mt) & 1u) sv += lv;
-                    }
-#pragma unroll
-                    for (int sft = 8; sft >= 1; sft >>= 1) sv += __shfl_xor(sv, sft);
-                    if (lane == 0) {
-                        const float v = tanhf(sv / (float)PIX + params[BV_OFF]);
-                        const int stt = fa.st.status[b], wn = fa.st.winner[b];
-                        fa.estimate[b] = stt == 1 ? (wn == 1 ? 1.f : (wn == 2 ? -1.f : 0.f))
-                                                  : (stt == 0 ? (me == 1 ? v : -v) : 0.f);
+                    lp += __shfl_xor(lp, 16);
+                    lp += __shfl_xor(lp, 32);
+                    lv += __shfl_xor(lv, 16);
+                    lv += __shfl_xor(lv, 32);
+                    if (quad == 0) vps[(slot * 8 + TPW * g + mt) * 16 + row] = lv;
+                    if (policy && ((vmask >> mt) & 1u) && quad == 0) {
+                        const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
+                        const int a = me == 2 ? c * N + r : r * N + c;
+                        if (MODE == 0) fa.logits[b * PIX + a] = lp + bp;
+                        else lgs[slot * 128 + a] = lp + bp;
                     }
                 }
             }
+            __syncthreads();
+            // the value: the partials of all 8 tiles in tile order, then over the rows
+            float v = 0.f;
+            if (live && g == 0) {
+                float sv = 0.f;
+#pragma unroll
+                for (int mt = 0; mt < 8; ++mt)
+                    if ((vmask8 >> mt) & 1u) sv += vps[(slot * 8 + mt) * 16 + row];
+#pragma unroll
+                for (int sft = 8; sft >= 1; sft >>= 1) sv += __shfl_xor(sv, sft);
+                v = tanhf(sv / (float)PIX + params[BV_OFF]);
+            }
+            if constexpr (MODE == 0) {
+                if (live && g == 0 && lane == 0) fa.value[b] = v;
+            } else if (last) {
+                if (live && g == 0 && lane == 0) {
+                    // the value cutoff: the network's value for RUNNING envs (for
+                    // player 1), the outcome of ended ones
+                    const int stt = scal[slot][0], wn = scal[slot][2];
+                    fa.estimate[b] = stt == 1 ? (wn == 1 ? 1.f : (wn == 2 ? -1.f : 0.f))
+                                              : (stt == 0 ? (me == 1 ? v : -v) : 0.f);
+                }
+            } else if (live && g == 0) {
+                const uint64_t id = (uint64_t)(fa.gid != nullptr ? fa.gid[b] : fa.gid_base + b);
+                if (fa.kind == 3)
+                    lds_policy_ply<Hex<N>>(scal[slot], id, fa.max_plies, lgs + slot * 128, brow[slot], fa.key0,
+                                           fa.key1);
+                else
+                    lds_policy_ply<Gomoku<N>>(scal[slot], id, fa.max_plies, lgs + slot * 128, brow[slot], fa.key0,
+                                              fa.key1);
+            }
+        }
+        if constexpr (MODE == 1) {
+            // the group's final states back to memory
+            __syncthreads();
+            for (int j = threadIdx.x; j < BPB * PIX; j += NT) {
+                const int bb = j / PIX, c = j % PIX;
+                if (b0 + bb < n) fa.st.board[(b0 + bb) * PIX + c] = brow[bb][c];
+            }
+            if (threadIdx.x < BPB && b0 + threadIdx.x < n) {
+                const int64_t bt = b0 + threadIdx.x;
+                const int *sc = scal[threadIdx.x];
+                fa.st.status[bt] = (int8_t)sc[0];
+                fa.st.to_move[bt] = (int8_t)sc[1];
+                fa.st.winner[bt] = (int8_t)sc[2];
+                fa.st.passes[bt] = (int8_t)sc[3];
+                fa.st.ply[bt] = (int16_t)sc[4];
+                fa.st.last_action[bt] = (int16_t)sc[5];
+            }
         }
     }
+    __builtin_amdgcn_s_waitcnt(0); // no copy to LDS outlives the block
 }
 
 // ---------------------------------------------------------------------------
@@ -1173,10 +1269,12 @@ constexpr int RES_BLOCKS = 256; // one per CU
 // from its cell codes; the next group's board bytes are loaded into
 // registers while the current group is multiplied.
 // MODE 3: the last layer and the heads (see heads_epilogue).  A board's
-// channels and cells are spread over 2 x 3 waves, so each wave adds its
-// per-cell policy partials and its value partial into LDS (float atomics);
-// a finished group is written out after the next group's first barrier
-// (the last one after the loop), and its accumulators are cleared there.
+// channels and cells are spread over 2 x 3 waves: each wave adds its
+// per-cell policy partials into LDS (float atomics: two adds onto zero per
+// logit, the same sum in either order) and writes its value partial to its
+// own LDS slot, the slots summed in a fixed order when the group is written
+// out (after the next group's first barrier, the last one after the loop),
+// so values are reproducible bit for bit; the logit sums are cleared there.
 template <int N, int MODE>
 __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t *__restrict__ x,
                                                                      const uint16_t *__restrict__ w,
@@ -1197,7 +1295,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
     // MODE 3: head weights (wp, wv), the group's logit and value sums
     __shared__ float hw[MODE == 3 ? 2 * C : 1];
     __shared__ float hl[MODE == 3 ? BPB * L::PIX : 1];
-    __shared__ float hv[MODE == 3 ? BPB : 1];
+    __shared__ float hv[MODE == 3 ? BPB * L::NSPLIT * NG : 1];
 
     const int lane = threadIdx.x & 63, wave = (threadIdx.x >> 6) / L::NSPLIT, half = (threadIdx.x >> 6) % L::NSPLIT;
     const int slot = wave / NG, g = wave % NG;
@@ -1249,7 +1347,6 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
         for (int j = threadIdx.x; j < 2 * C; j += THREADS)
             hw[j] = a1.params[(j < C ? WP_OFF : WV_OFF) + (j & (C - 1))];
         for (int j = threadIdx.x; j < BPB * L::PIX; j += THREADS) hl[j] = 0.f;
-        if (threadIdx.x < BPB) hv[threadIdx.x] = 0.f;
     }
     // MODE 3: write out the sums of group pg and clear them (after a barrier)
     auto flush = [&](int64_t pg) {
@@ -1266,8 +1363,9 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
         }
         if (threadIdx.x < BPB) {
             const int64_t bo = pg * BPB + threadIdx.x;
-            if (bo < n) a1.value[bo] = tanhf(hv[threadIdx.x] / (float)PIX + bvv);
-            hv[threadIdx.x] = 0.f;
+            float sv = 0.f;
+            for (int k = 0; k < L::NSPLIT * NG; ++k) sv += hv[threadIdx.x * L::NSPLIT * NG + k];
+            if (bo < n) a1.value[bo] = tanhf(sv / (float)PIX + bvv);
         }
     };
     if constexpr (MODE != 2) {
@@ -1374,7 +1472,7 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
             }
 #pragma unroll
             for (int s2 = 8; s2 >= 1; s2 >>= 1) sv += __shfl_xor(sv, s2); // the 16 rows
-            if (lane == 0) atomicAdd(&hv[slot], sv);
+            if (lane == 0) hv[(slot * L::NSPLIT + half) * NG + g] = sv;
             continue;
         }
         uint16_t *ob = out + b * (int64_t)PP * C;
@@ -2173,7 +2271,7 @@ int cu_count()
 
 unsigned fused_grid(int64_t n)
 {
-    const int64_t groups = (n + LdsL<11>::BPB - 1) / LdsL<11>::BPB;
+    const int64_t groups = (n + Fused11::BPB - 1) / Fused11::BPB;
     const int64_t cap = (int64_t)cu_count() * FUSED_BLOCKS_PER_CU;
     return (unsigned)(groups < cap ? groups : cap);
 }
@@ -2190,7 +2288,7 @@ hipError_t forward_fused11(const float *params, const uint16_t *packed, const in
     fa.to_move = to_move;
     fa.logits = logits;
     fa.value = value;
-    hipLaunchKernelGGL(k_fwd11<0>, dim3(fused_grid(n)), dim3(256), 0, s, fa);
+    hipLaunchKernelGGL(k_fwd11<0>, dim3(fused_grid(n)), dim3(Fused11::THREADS), 0, s, fa);
     return hipGetLastError();
 }
 
@@ -2339,7 +2437,7 @@ hipError_t net_guided_playout(const float *params, const void *packed, const Dev
     fa.gid_base = gid_base;
     fa.gid = gid;
     fa.estimate = estimate;
-    hipLaunchKernelGGL(net::k_fwd11<1>, dim3(net::fused_grid(n)), dim3(256), 0, s, fa);
+    hipLaunchKernelGGL(net::k_fwd11<1>, dim3(net::fused_grid(n)), dim3(net::Fused11::THREADS), 0, s, fa);
     return hipGetLastError();
 }
 

@@ -157,3 +157,49 @@ def estimate_budgeted(game: ludax.Game, net: ludax.Net, s: ludax.State, budget_b
         part = ludax.State.from_tensors(game, **{f: getattr(s, f)[a:b] for f in ludax.State.FIELDS})
         net.estimate(part, out=out[a:b])
     return out
+
+
+def guided_budgeted(game: ludax.Game, net: ludax.Net, s: ludax.State, plies: int, budget_bytes: int, seed: int,
+                    id_base: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Network-guided playouts with a value cutoff over a batch of any size,
+    the network's workspace and logits held to budget_bytes of HBM: the envs
+    are admitted in chunks (whole 64-env workgroups) of the largest batch
+    whose inference workspace plus logits fit, and each chunk plays `plies`
+    guided plies (ludax_net_forward, then ludax_policy_step; game ids
+    id_base + env index, as for one call over the whole batch) before the
+    value cutoff (ludax_net_estimate).  Modifies s; returns the estimates
+    for player 1."""
+    cells = game.cells
+    chunk = guided_chunk(net, budget_bytes, cells)
+    if chunk < 64:
+        raise ValueError("the HBM budget does not hold the workspace of 64 positions")
+    if out is None:
+        out = torch.empty(s.n, dtype=torch.float32, device=s.board.device)
+    logits = torch.empty((chunk, cells), dtype=torch.float32, device=s.board.device)
+    value = torch.empty(chunk, dtype=torch.float32, device=s.board.device)
+    r = torch.empty((chunk, 2), dtype=torch.int8, device=s.board.device)
+    t = torch.empty(chunk, dtype=torch.uint8, device=s.board.device)
+    for a in range(0, s.n, chunk):
+        b = min(s.n, a + chunk)
+        m = b - a
+        part = ludax.State.from_tensors(game, **{f: getattr(s, f)[a:b] for f in ludax.State.FIELDS})
+        for _ in range(plies):
+            net.forward(part.board, part.to_move, logits=logits[:m], value=value[:m])
+            ludax.policy_step(game, part, logits[:m], seed, id_base + a, reward=r[:m], terminal=t[:m])
+        net.estimate(part, out=out[a:b])
+    return out
+
+
+def guided_chunk(net: ludax.Net, budget_bytes: int, cells: int) -> int:
+    """The chunk guided_budgeted admits: the largest whole number of 64-env
+    workgroups whose inference workspace plus logits fit the budget."""
+    k = net.max_batch(budget_bytes)
+    while k > 0 and ludax_ws_plus_logits(net, k, cells) > budget_bytes:
+        k -= max(1, k // 64)
+    return k // 64 * 64
+
+
+def ludax_ws_plus_logits(net: ludax.Net, n: int, cells: int) -> int:
+    """Inference workspace of n positions plus their float32 logits and
+    values (bytes)."""
+    return net.workspace_bytes(n) + n * (cells + 1) * 4

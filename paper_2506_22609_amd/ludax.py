@@ -490,6 +490,13 @@ class Net:
         _check(_load().ludax_net_pack(self._h, _ptr(self.params), _ptr(self.packed), _stream(stream)),
                "ludax_net_pack")
 
+    def workspace_bytes(self, n: int, training: bool = False) -> int:
+        """ludax_net_workspace_bytes: the workspace a batch of n needs."""
+        b = ctypes.c_int64()
+        _check(_load().ludax_net_workspace_bytes(self._h, n, int(training), ctypes.byref(b)),
+               "ludax_net_workspace_bytes")
+        return b.value
+
     def workspace(self, n: int, training: bool = False):
         b = ctypes.c_int64()
         _check(_load().ludax_net_workspace_bytes(self._h, n, int(training), ctypes.byref(b)),

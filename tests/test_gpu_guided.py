@@ -169,3 +169,69 @@ def test_guided_playout_value_matches_oracle():
     assert np.array_equal(est[~run], exp[~run])
     err = np.linalg.norm(est[run] - exp[run]) / np.linalg.norm(exp[run])
     assert err < 1e-3, err
+
+
+@pytest.mark.parametrize("kind", [ref.HEX, ref.GOMOKU], ids=["hex19", "gomoku19"])
+def test_guided_budgeted_19x19(kind):
+    """19x19 network-guided playouts (forward + policy step per ply, then the
+    value cutoff) admitted in chunks under an HBM budget: the same states
+    and estimates bit for bit whatever the chunk size (a budget of 3
+    workgroups' workspace against one chunk for all 300 envs), and, on a
+    sample, the oracle's composition (float64 network, its policy draw, the
+    rules' step), exact except at draws within the logits' float32 error of
+    a boundary (then a neighbouring legal action)."""
+    from paper_2506_22609_amd import learn
+    og, dg = pair(kind, 19, 19)
+    rng = np.random.default_rng(120 + kind)
+    n, plies, seed, base = 300, 3, 77, 5000
+    s = random_states(og, n, 150, rng)
+    p = init_net_params(25)
+    net = ludax.Net(19, 19, params=torch.from_numpy(p).cuda())
+    small = learn.ludax_ws_plus_logits(net, 3 * 64, og.cells) + 1000
+    a = to_device(dg, s)
+    b = ludax.State.from_tensors(dg, **{f: getattr(a, f).clone() for f in FIELDS})
+    ea = learn.guided_budgeted(dg, net, a, plies, small, seed, base)
+    eb = learn.guided_budgeted(dg, net, b, plies, 1 << 40, seed, base)
+    for f in FIELDS:
+        assert torch.equal(getattr(a, f), getattr(b, f)), f
+    assert torch.equal(ea, eb)
+    # the oracle's composition, ply by ply, on the first 12 and the last 12 envs
+    p64 = p.astype(np.float64)
+    near_calls = 0
+    for lo in (0, n - 12):
+        idx = np.arange(lo, lo + 12)
+        so = s.subset(idx)
+        c = to_device(dg, so)
+        for ply in range(plies):
+            glog, _ = net.forward(c.board, c.to_move)
+            glog = glog.cpu().numpy()
+            f = R.forward(p64, so.board, so.to_move, 19, bf16=True)
+            m = ref.legal_mask(og, so)
+            act = np.zeros(len(idx), np.int32)
+            tol = np.full(len(idx), -1.0)
+            for i in np.flatnonzero(so.status == ref.RUNNING):
+                legal = m[i].astype(bool)
+                act[i], margin = R.policy_action(f["logits"][i], legal, ref.draw(seed, base + lo + i, int(so.ply[i])))
+                dmax = float(np.abs(glog[i][legal] - f["logits"][i][legal]).max())
+                if margin < 2.0 * np.expm1(dmax) + 1e-6:
+                    tol[i] = margin
+            before = so.copy()
+            ref.step(og, so, act, want_mask=False)
+            est = learn.guided_budgeted(dg, net, c, 1, small, seed, base + lo)
+            got = from_device(c)
+            for i in np.flatnonzero((tol >= 0) & (got.last_action != so.last_action)):
+                near_calls += 1
+                legal = np.flatnonzero(m[i])
+                k = np.searchsorted(legal, so.last_action[i])
+                assert got.last_action[i] in legal[max(0, k - 1):k + 2]
+                one = before.subset([i])
+                ref.step(og, one, np.array([got.last_action[i]], np.int32), want_mask=False)
+                for fld in ref.State.FIELDS:
+                    getattr(so, fld)[i] = getattr(one, fld)[0]
+            assert_same_state(so, got, f"guided 19x19 ply {ply}")
+        v = R.forward(p64, so.board, so.to_move, 19)["value"]
+        exp = np.where(so.status == ref.TERMINAL, np.where(so.winner == 1, 1.0, np.where(so.winner == 2, -1.0, 0.0)),
+                       np.where(so.status == ref.RUNNING, np.where(so.to_move == 1, v, -v), 0.0))
+        close_rel = np.linalg.norm(est.cpu().numpy() - exp) / max(np.linalg.norm(exp), 1e-30)
+        assert close_rel < 1e-3, close_rel
+    assert near_calls <= 2
