@@ -3,17 +3,18 @@
 
 Workload: single-game batches of 65536 environments each, Connect Four 6x7
 and Hex 11x11 (int8 boards), uniform-random playouts from the start
-position to the end of every game.  One benchmark step = for each batch:
-ludax_init (start positions) + ludax_playout (legal mask, Philox draw,
-k-th legal action, apply, end rules, repeated until every game has ended)
-+ the step/outcome counters (ludax_state_stats before and after, which is
-what ludax_playout's own stats argument runs).  Every step uses fresh game
-ids, so no two steps play the same games.
+position to the end of every game.  One benchmark step = both batches
+reset to the start position and played out (legal mask, Philox draw, k-th
+legal action, apply, end rules, repeated until every game has ended) with
+the step/outcome counters, all in one launch (ludax_playout_batches);
+the same step as six separate launches (ludax_init, ludax_playout,
+ludax_state_stats per batch) is reported beside it.  Every step uses fresh
+game ids, so no two steps play the same games.
 
 Prints one JSON line: env-steps/s over the timed steps (all plies applied
 by all environments / wall time between two device synchronisations), the
-roofline figures of the dominant kernel (the Hex playout kernel, timed
-with events on its own stream) and the CPU oracle's rate on a bounded
+roofline figures of the dominant kernel (the one-grid playout kernel,
+timed with events on its stream) and the CPU oracle's rate on a bounded
 sample of the same workload.
 """
 from __future__ import annotations
@@ -24,21 +25,37 @@ import os
 import sys
 import time
 
+# The mixed persistent batches run one kernel per game kind on a stream of
+# its own, concurrently.  HIP spreads a process's streams over
+# GPU_MAX_HW_QUEUES hardware queues (4 by default) and kernels that share a
+# queue run one after the other, so with torch's streams and two mixed
+# handles alive the kinds would partly serialise (the 1M-game 19x19 mixed
+# batch: 4.2 against 3.0 ms).  Sixteen queues give every stream of this
+# process one of its own; the runtime reads the variable when it starts,
+# before torch is imported.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Integer VALU work per env-step of the playout kernels (lane-operations):
 # SQ_INSTS_VALU x 64 / env-steps of one launch, measured with rocprofv3 on
-# this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt).  Peak:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (the fp64
-# vector rate 78.6 TFLOP/s counts an FMA as two operations).
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 272, "hex11x11_n65536": 177}
+# this workload (profiles/playout_c4_hex11_n65536_sq_counters.txt): the
+# separate Connect Four and Hex kernels, and the one-grid launch of both
+# batches (env-steps of both).  Peak: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3 T lane-ops/s (the fp64 vector rate 78.6 TFLOP/s counts an
+# FMA as two operations).
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 272, "hex11x11_n65536": 176, "group": 188}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# HBM bytes of one Hex playout launch: FETCH_SIZE and WRITE_SIZE scaled by
-# a 1 GiB device copy in the same profiled run
-# (profiles/playout_c4_hex11_n65536_hbm_bytes.txt).
-HEX_TRAFFIC_BYTES = 11.92e6
+# HBM bytes of one launch of the dominant kernel: FETCH_SIZE and WRITE_SIZE
+# scaled by a 1 GiB device copy in the same profiled run
+# (profiles/playout_c4_hex11_n65536_hbm_bytes.txt): 0.40 MB read (no state:
+# the kernel resets the envs itself) and 12.12 MB written (the final
+# states, exactly their algorithmic bytes).
+GROUP_TRAFFIC_BYTES = 12.52e6
 HBM_PEAK_GBS = 8000.0
+EVENT_EVERY = 8
 # DRAM bytes (read + written) per env-step of the per-ply loop, from the
 # FETCH_SIZE / WRITE_SIZE counters of every ludax_random_step dispatch of one
 # loop, each scaled by what the counter reads for a 1 GiB device copy in the
@@ -104,9 +121,10 @@ def _cpu_baseline(batches, budget_s: float):
 
 def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: int = 3, steps: int = 20):
     """The benchmark step repeated per seed: warm-up steps, then `steps`
-    steps each bracketed by events on the stream (both batches: init,
-    playout, counters), fresh game ids every step; per seed the median and
-    standard deviation of the per-step env-steps/s."""
+    steps each bracketed by events on the stream (both batches reset and
+    played out, with their counters, by one launch), fresh game ids every
+    step; per seed the median and standard deviation of the per-step
+    env-steps/s."""
     import statistics
 
     import torch
@@ -114,6 +132,7 @@ def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: i
     from paper_2506_22609_amd import workloads as W
 
     stream = torch.cuda.current_stream()
+    group = ludax.BatchGroup([(g, s, r, t, None) for g, s, r, t in zip(games, states, rewards, terms)])
     out = {}
     for seed in seeds:
         st = torch.zeros((steps, len(batches), 4), dtype=torch.int64, device="cuda")
@@ -122,10 +141,8 @@ def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: i
             rec = k >= warmup
             if rec:
                 evs[k - warmup][0].record(stream)
-            for j, (b, g, s, r, t) in enumerate(zip(batches, games, states, rewards, terms)):
-                ludax.init(g, s, stream=stream)
-                ludax.playout(g, s, seed, W.game_id_base(1000 + k, b), reward=r, terminal=t,
-                              stats=st[k - warmup, j] if rec else None, stream=stream)
+            group.run(seed, [W.game_id_base(1000 + k, b) for b in batches], from_start=True, stream=stream,
+                      stats=[st[k - warmup, j] if rec else None for j in range(len(batches))])
             if rec:
                 evs[k - warmup][1].record(stream)
         torch.cuda.synchronize()
@@ -137,6 +154,47 @@ def _protocol(batches, games, states, rewards, terms, seeds=(1, 2, 3), warmup: i
                               "median_ms_per_step": statistics.median(ms), "std_ms_per_step": statistics.pstdev(ms),
                               "steps": steps, "warmup": warmup}
     return out
+
+
+def _separate_launches(batches, games, states, rewards, terms, seed: int, warmup: int = 3, steps: int = 20):
+    """The same step as separate launches on one stream: per batch
+    ludax_init, ludax_playout (its kernel bracketed by events) and
+    ludax_state_stats(+1), six launches in all (right after ludax_init the
+    counters' (-1) reduction adds zero, so one reduction after the playout
+    gives them).  Reported beside the one-grid step."""
+    import statistics
+
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    stream = torch.cuda.current_stream()
+    st = torch.zeros((len(batches), 4), dtype=torch.int64, device="cuda")
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+          for _ in batches]
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for k in range(warmup + steps):
+        rec = k >= warmup
+        if rec:
+            step_ev[k - warmup][0].record(stream)
+        for j, (b, g, s, r, t) in enumerate(zip(batches, games, states, rewards, terms)):
+            ludax.init(g, s, stream=stream)
+            if rec:
+                ev[j][k - warmup][0].record(stream)
+            ludax.playout(g, s, seed, W.game_id_base(2000 + k, b), reward=r, terminal=t, stats=None, stream=stream)
+            if rec:
+                ev[j][k - warmup][1].record(stream)
+                ludax.state_stats(g, s, +1, st[j], stream=stream)
+        if rec:
+            step_ev[k - warmup][1].record(stream)
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(c) for a, c in step_ev]
+    env_steps = int(st[:, 0].sum().item())
+    return {"median_ms_per_step": statistics.median(ms),
+            "env_steps_per_s": env_steps / (sum(ms) / 1e3),
+            "playout_kernel_ms": {b.name: statistics.median(a.elapsed_time(c) for a, c in ev[j])
+                                  for j, b in enumerate(batches)},
+            "launches_per_step": 6, "steps": steps, "warmup": warmup}
 
 
 def _mixed_equal_split_ms(m, kinds: int, total: int, seed: int, n: int, out, reps: int = 3) -> float:
@@ -647,21 +705,30 @@ def _learned_section(seed: int, train_games: int, steps: int):
     def value_only(s):
         return net.estimate(s)
 
+    def value_one_kernel(s):
+        # the value cutoff with no plies: the whole forward in one kernel
+        return net.guided_playout(g, s, 0, seed + 600, 5 * 10**9)
+
     def cutoff(s):
         return learn.cutoff_estimate(g, net, s, 20, seed + 500, 4 * 10**9)
 
-    def guided(s):
-        # the fused guided step: forward, policy draw and ply, logits on chip
-        for _ in range(20):
-            net.guided_step(g, s, seed + 600, 5 * 10**9, reward=r, terminal=t)
-        return net.estimate(s)
-
     def guided_unfused(s):
-        # the same plies through memory: forward to logits, then the policy step
+        # 20 plies through memory: forward to logits, then the policy step
         for _ in range(20):
             logits, _ = net.forward(s.board, s.to_move)
             ludax.policy_step(g, s, logits, seed + 600, 5 * 10**9, reward=r, terminal=t)
         return net.estimate(s)
+
+    def guided_step(s):
+        # the same plies, each by the forward's kernels with the draw and the
+        # ply in the last one (logits on chip)
+        for _ in range(20):
+            net.guided_step(g, s, seed + 600, 5 * 10**9, reward=r, terminal=t)
+        return net.estimate(s)
+
+    def guided_one_kernel(s):
+        # the same plies and the value cutoff in one persistent kernel
+        return net.guided_playout(g, s, 20, seed + 600, 5 * 10**9)
 
     out = {"workload": f"hex11x11: training on {train_games} random games, {steps} Adam steps of 4096; "
                        f"{n} held-out positions (error measured on {sub} of them against 256 full random "
@@ -672,8 +739,9 @@ def _learned_section(seed: int, train_games: int, steps: int):
            "methods": {}}
     import statistics
     for name, fn in (("plain_full_playout", plain), ("value_only", value_only),
-                     ("random20_value_cutoff", cutoff), ("policy20_value_cutoff", guided),
-                     ("policy20_value_cutoff_unfused", guided_unfused)):
+                     ("value_only_one_kernel", value_one_kernel), ("random20_value_cutoff", cutoff), ("policy20_value_cutoff_unfused", guided_unfused),
+                     ("policy20_value_cutoff_guided_step", guided_step),
+                     ("policy20_value_cutoff_one_kernel", guided_one_kernel)):
         s = base.clone()
         fn(s)
         torch.cuda.synchronize()
@@ -689,6 +757,10 @@ def _learned_section(seed: int, train_games: int, steps: int):
         mse = ((est[:sub] - tr) ** 2).mean().item()
         out["methods"][name] = {"playouts_per_s": n / el, "ms_per_65536": el * 1e3 * 65536 / n,
                                 "mse_vs_256_playout_mean": mse, "timing": "median of 5"}
+    # the three policy-guided paths give the same states and estimates bit for bit
+    best = max(("policy20_value_cutoff_unfused", "policy20_value_cutoff_guided_step",
+                "policy20_value_cutoff_one_kernel"), key=lambda k: out["methods"][k]["playouts_per_s"])
+    out["methods"]["policy20_value_cutoff"] = dict(out["methods"][best], path=best)
     # at a fixed value error: the number of averaged full random playouts
     # that matches the value's squared error, measured
     vm = out["methods"]["value_only"]
@@ -746,6 +818,13 @@ def _hbm_probe(seed: int):
         _, _, st = ludax.playout(g, s, seed, 0)
         out[b.name] = {"env_steps": int(st[0].item())}
         del s
+    # the headline step as bench.py times it: both batches in one launch
+    games = [ludax.Game(b.kind, b.rows, b.cols) for b in W.BENCH_BATCHES]
+    states = [ludax.State(g, b.n) for g, b in zip(games, W.BENCH_BATCHES)]
+    res = ludax.playout_batches([(g, s, 0, None, None, torch.zeros(4, dtype=torch.int64, device="cuda"))
+                                 for g, s in zip(games, states)], seed, from_start=True)
+    out["group"] = {"env_steps": int(sum(r[2][0].item() for r in res))}
+    del states, res
     b = W.HEX19_1M
     g = ludax.Game(b.kind, b.rows, b.cols)
     for aux in (False, True):
@@ -768,8 +847,8 @@ def _hbm_probe(seed: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
@@ -814,36 +893,30 @@ def main():
         _hbm_probe(args.seed)
         return
     batches = W.BENCH_BATCHES
-    dominant = W.HEX11_65536.name
     games = [ludax.Game(b.kind, b.rows, b.cols) for b in batches]
     states = [ludax.State(g, b.n) for g, b in zip(games, batches)]
     rewards = [torch.empty((b.n, 2), dtype=torch.int8, device="cuda") for b in batches]
     terms = [torch.empty(b.n, dtype=torch.uint8, device="cuda") for b in batches]
     stats = [torch.zeros(4, dtype=torch.int64, device="cuda") for _ in batches]
     stream = torch.cuda.current_stream()
-    ev = {b.name: [] for b in batches}
-    timing = {b.name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                       for _ in range(args.steps)] for b in batches}
+    # an event pair costs the stream a few microseconds (10 % of a step), so
+    # every EVENT_EVERY-th timed step is bracketed, not every step
+    sampled = list(range(0, args.steps, EVENT_EVERY))
+    timing = {j: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for j in sampled}
+
+    group = ludax.BatchGroup(list(zip(games, states, rewards, terms, stats)))
 
     def one_step(k: int, record: bool):
-        # ludax_playout(stats=st) adds state_stats(+1) - state_stats(-1)
-        # around the playout kernel; right after ludax_init every env is
-        # RUNNING at ply 0 with no winner, so the (-1) reduction adds zero and
-        # the counters are one reduction after the playout.  The events
-        # bracket the playout kernel alone.  (The two batches on two streams,
-        # so that their kernels overlap, measured slower: each kernel then
-        # runs 35 % longer.)
-        for b, g, s, r, t, st in zip(batches, games, states, rewards, terms, stats):
-            ludax.init(g, s, stream=stream)
-            if record:
-                e0, e1 = timing[b.name][k - args.warmup]
-                e0.record(stream)
-            ludax.playout(g, s, args.seed, W.game_id_base(k, b), reward=r, terminal=t, stats=None,
-                          stream=stream)
-            if record:
-                e1.record(stream)
-                ev[b.name].append((e0, e1))
-            ludax.state_stats(g, s, +1, st, stream=stream)
+        # both batches reset to the start and played out by one kernel
+        # (ludax_playout_batches, from_start), then both batches' counters by
+        # one reduction kernel; the events bracket the call, i.e. these two
+        # kernels
+        ev = timing.get(k - args.warmup) if record else None
+        if ev:
+            ev[0].record(stream)
+        group.run(args.seed, [W.game_id_base(k, b) for b in batches], from_start=True, stream=stream)
+        if ev:
+            ev[1].record(stream)
 
     for k in range(args.warmup):
         one_step(k, False)
@@ -868,24 +941,24 @@ def main():
     total_steps = 0
     for b, st in zip(batches, stats):
         v = st.cpu().tolist()
-        kern_ms = sum(a.elapsed_time(c) for a, c in ev[b.name]) / args.steps
-        per[b.name] = {"env_steps": v[0], "p1_wins": v[1], "p2_wins": v[2], "draws": v[3],
-                       "playout_kernel_ms": kern_ms,
-                       "env_steps_per_s_kernel": v[0] / args.steps / (kern_ms / 1e3)}
+        per[b.name] = {"env_steps": v[0], "p1_wins": v[1], "p2_wins": v[2], "draws": v[3]}
         total_steps += v[0]
     value = total_steps / elapsed
+    kern_ms = sum(a.elapsed_time(c) for a, c in timing.values()) / len(timing)
 
-    d = per[dominant]
-    steps_per_launch = d["env_steps"] / args.steps
-    kern_s = d["playout_kernel_ms"] / 1e3
-    ops = VALU_OPS_PER_STEP[dominant] * steps_per_launch
-    achieved = ops / kern_s / 1e12
+    steps_per_launch = total_steps / args.steps
+    kern_s = kern_ms / 1e3
+    ops_per = VALU_OPS_PER_STEP["group"]
+    achieved = ops_per * steps_per_launch / kern_s / 1e12 if ops_per else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": HEX_TRAFFIC_BYTES,
-                "kernel": f"k_playout_fill<Hex<11>> ({dominant})",
-                "ops_per_env_step": VALU_OPS_PER_STEP[dominant],
+                "frac": achieved / VALU_PEAK_TOPS if achieved else None, "traffic": GROUP_TRAFFIC_BYTES,
+                "kernel": "k_playout_group (connect4_6x7_n65536 + hex11x11_n65536 in one grid)",
+                "kernel_ms": kern_ms,
+                "timed": f"events around ludax_playout_batches (k_playout_group and the counters' k_stats_group) "
+                         f"in {len(timing)} of the {args.steps} timed steps",
+                "ops_per_env_step": ops_per,
                 "env_steps_per_launch": steps_per_launch,
-                "hbm_frac": HEX_TRAFFIC_BYTES / kern_s / 1e9 / HBM_PEAK_GBS}
+                "hbm_frac": GROUP_TRAFFIC_BYTES / kern_s / 1e9 / HBM_PEAK_GBS if GROUP_TRAFFIC_BYTES else None}
 
     out = {
         "metric": "env-steps/s (plain random playouts, single-game batches)",
@@ -905,6 +978,7 @@ def main():
         "roofline": roofline,
     }
     out["protocol"] = _protocol(batches, games, states, rewards, terms)
+    out["separate_launches"] = _separate_launches(batches, games, states, rewards, terms, args.seed)
     sec = set(x for x in args.sections.split(",") if x)
     if args.no_mixed:
         sec.discard("mixed")

@@ -241,6 +241,36 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed,
                   int64_t game_id_base, const int64_t *game_id, int8_t *reward,
                   uint8_t *terminal, int64_t *stats, int64_t n, hipStream_t stream);
 
+/* Several batches played out by one kernel launch (Sec. 6 measures batches
+ * of single games; a step of its benchmark plays several games' batches).
+ * Kernels queued on one stream run one after the other, so batches
+ * launched separately leave the chip to one batch's waves at a time (a
+ * 65536-env batch has one wave per SIMD); in one grid the batches' waves
+ * share the SIMDs.  Each batch's results are exactly those of, in order,
+ * [ludax_init if from_start] and ludax_playout(game, state, seed,
+ * game_id_base, NULL, reward, terminal, stats, n): from_start != 0 resets
+ * every env to its game's start position inside the kernel, so no field of
+ * the state is read.  The group kernel holds the fill-then-resolve games
+ * Tic-Tac-Toe, Connect Four 6x7 and Hex 11x11; a call with any other game
+ * runs the batches one after another (the same kernels as ludax_init and
+ * ludax_playout).  The state's aux cache, if any, is left describing the
+ * final boards (from_start) or as ludax_playout leaves it.
+ * batches: 1 <= n_batches <= 4 host structs; batches must not share device
+ * buffers; the batches' n add up to at most 2^31 - 1; a batch with n = 0
+ * is skipped (its pointers are not checked). */
+typedef struct {
+    const ludax_game *game;
+    ludax_state *state;
+    int64_t n;
+    int64_t game_id_base; /* game id of env i: game_id_base + i */
+    int8_t *reward;       /* [n][2] as ludax_playout */
+    uint8_t *terminal;    /* [n] */
+    int64_t *stats;       /* [4] int64 added to as ludax_playout's, or NULL */
+} ludax_batch;
+
+int ludax_playout_batches(const ludax_batch *batches, int32_t n_batches, uint64_t seed, int32_t from_start,
+                          hipStream_t stream);
+
 /* One ply of the uniform-random policy of ludax_playout for every
  * environment (Sec. 6), with the state left in HBM between calls: a
  * RUNNING env draws the action of its current ply exactly as
@@ -293,7 +323,13 @@ int ludax_aux_sync(const ludax_game *game, ludax_state *state, int64_t n, hipStr
  * a queue (64 games per atomic), so no lane waits for the longest game of
  * a fixed batch.  The kinds' kernels run concurrently on internal streams
  * forked from and joined back into the caller's stream, so the whole call
- * can be captured into a graph and replayed.
+ * can be captured into a graph and replayed.  They overlap only where each
+ * internal stream has a hardware queue of its own: HIP spreads a process's
+ * streams over GPU_MAX_HW_QUEUES queues (4 by default) and kernels sharing
+ * a queue run one after the other, so a process with several mixed handles
+ * or many other streams sets GPU_MAX_HW_QUEUES (up to 32) to at least its
+ * number of streams before the runtime starts (1M-game 19x19 mixed batch:
+ * 4.2 ms with both kinds' streams on one queue, 3.0 ms on two).
  * ------------------------------------------------------------------------ */
 typedef struct ludax_mixed ludax_mixed;
 

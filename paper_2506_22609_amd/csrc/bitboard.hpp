@@ -88,9 +88,11 @@ __device__ __forceinline__ BB<NW> operator~(const BB<NW> &a)
     return r;
 }
 
-// c ? a : b, word by word (a whole-struct select would go through memory)
+// c ? a : b, word by word (a whole-struct select would go through memory;
+// so would a select between the addresses of two boards, which is what
+// reference arguments invite: the boards are taken by value)
 template <int NW>
-__device__ __forceinline__ BB<NW> pick(bool c, const BB<NW> &a, const BB<NW> &b)
+__device__ __forceinline__ BB<NW> pick(bool c, BB<NW> a, BB<NW> b)
 {
     BB<NW> r;
 #pragma unroll

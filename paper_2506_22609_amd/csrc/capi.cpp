@@ -212,6 +212,87 @@ int ludax_playout(const ludax_game *game, ludax_state *state, uint64_t seed, int
                                            terminal, stats, stream));
 }
 
+int ludax_playout_batches(const ludax_batch *batches, int32_t n_batches, uint64_t seed, int32_t from_start,
+                          hipStream_t stream)
+{
+    constexpr int NB = lx::GROUP_MAX;
+    if (batches == nullptr || n_batches < 1 || n_batches > NB) return LUDAX_E_INVALID;
+    lx::DevState d[NB], daux[NB];
+    int64_t total = 0;
+    bool grouped = true;
+    for (int k = 0; k < n_batches; ++k) {
+        const ludax_batch &b = batches[k];
+        if (b.game == nullptr || b.n < 0 || b.n > MAX_ENVS) return LUDAX_E_INVALID;
+        total += b.n;
+        if (b.n == 0) continue;
+        if (b.reward == nullptr || b.terminal == nullptr) return LUDAX_E_INVALID;
+        int rc = check_state(b.state, &d[k]);
+        if (rc == LUDAX_OK) rc = check_state(b.state, &daux[k], b.game->ops->aux_bytes);
+        if (rc) return rc;
+        if (b.game->ops->group_slot < 0) grouped = false;
+    }
+    if (total > MAX_ENVS) return LUDAX_E_INVALID; // one grid of at most 2^31 threads
+    if (total == 0) return LUDAX_OK;
+    hipError_t e = hipSuccess;
+    if (!grouped) {
+        // a game outside the group kernel: the batches one after another
+        for (int k = 0; k < n_batches && e == hipSuccess; ++k) {
+            const ludax_batch &b = batches[k];
+            if (b.n == 0) continue;
+            if (from_start) e = b.game->ops->init(daux[k], b.n, stream);
+            if (e == hipSuccess)
+                e = b.game->ops->playout(d[k], b.n, b.game->max_plies, seed, b.game_id_base, nullptr, b.reward,
+                                         b.terminal, b.stats, stream);
+        }
+        return device_error(e);
+    }
+    // the longest-running games' blocks first (cells as the measure), so
+    // that the shorter batches' waves fill in beside them
+    int order[NB];
+    for (int k = 0; k < n_batches; ++k) order[k] = k;
+    std::stable_sort(order, order + n_batches, [&](int x, int y) {
+        return batches[x].game->ops->cells > batches[y].game->ops->cells;
+    });
+    lx::GroupArgs a = {};
+    lx::DevState ds[NB];
+    int64_t ns[NB], *ss[NB];
+    int m = 0;
+    int64_t blocks = 0;
+    for (int q = 0; q < n_batches; ++q) {
+        const int k = order[q];
+        const ludax_batch &b = batches[k];
+        if (b.n == 0) continue;
+        ds[m] = d[k];
+        ns[m] = b.n;
+        ss[m] = b.stats;
+        a.st[m] = d[k];
+        a.n[m] = b.n;
+        a.gid_base[m] = b.game_id_base;
+        a.reward[m] = b.reward;
+        a.terminal[m] = b.terminal;
+        a.max_plies[m] = b.game->max_plies;
+        a.slot[m] = b.game->ops->group_slot;
+        a.first_block[m] = (int32_t)blocks;
+        blocks += (b.n + 63) / 64;
+        ++m;
+    }
+    for (int k = m; k <= NB; ++k) a.first_block[k] = (int32_t)blocks;
+    a.nb = m;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    // the counters as ludax_playout keeps them: after minus before, both
+    // reductions over all batches in one launch each (from the start
+    // positions the before part is zero and is not launched)
+    if (!from_start) e = lx::launch_stats_group(ds, ns, m, -1, ss, stream);
+    if (e == hipSuccess) e = lx::launch_playout_group(a, from_start != 0, stream);
+    if (e == hipSuccess) e = lx::launch_stats_group(ds, ns, m, +1, ss, stream);
+    // a cache that ludax_init would have reset now describes the final boards
+    for (int k = 0; k < n_batches && e == hipSuccess && from_start; ++k)
+        if (batches[k].n > 0 && daux[k].aux != nullptr)
+            e = batches[k].game->ops->aux_sync(daux[k], batches[k].n, stream);
+    return device_error(e);
+}
+
 int ludax_random_step(const ludax_game *game, ludax_state *state, uint64_t seed, int64_t game_id_base,
                       const int64_t *game_id, int8_t *reward, uint8_t *terminal, int64_t n,
                       hipStream_t stream)

@@ -1063,44 +1063,62 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
     return w;
 }
 
-// Fill-then-resolve playout of a batch of states (Hex, Tic-Tac-Toe,
-// Connect Four).
+// LDS bytes of one block of a fill-then-resolve playout: the boards'
+// staging area and, after it, the move list
 template <class G>
-__global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, int max_plies,
-                                                        uint32_t key0, uint32_t key1, int64_t gid_base,
-                                                        const int64_t *__restrict__ gid,
-                                                        int8_t *__restrict__ reward,
-                                                        uint8_t *__restrict__ terminal)
+constexpr int fill_lds_bytes()
+{
+    constexpr int STAGE = BLOCK * G::CELLS;
+    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(MoveT<G>);
+    return (STAGE > LIST ? STAGE : LIST) + STAGE_SLACK;
+}
+
+// Fill-then-resolve playout of the envs [blk * BLOCK, blk * BLOCK + 64) of
+// a batch of states (Hex, Tic-Tac-Toe, Connect Four); lds holds
+// fill_lds_bytes<G>() bytes.  FROM_START: every env is first reset to the
+// start position as ludax_init sets it (empty board, player 1 to move,
+// RUNNING, ply 0, no last action), so no field of the state is read.
+template <class G, bool FROM_START>
+__device__ __forceinline__ void playout_fill_block(const DevState &st, int64_t n, int max_plies, uint32_t key0,
+                                                   uint32_t key1, int64_t gid_base, const int64_t *__restrict__ gid,
+                                                   int8_t *__restrict__ reward, uint8_t *__restrict__ terminal,
+                                                   int64_t blk, int8_t *lds)
 {
     using M = typename G::M;
     using E = MoveT<G>;
-    constexpr int STAGE = BLOCK * G::CELLS;
-    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(E);
-    __shared__ __align__(16) int8_t lds[(STAGE > LIST ? STAGE : LIST) + STAGE_SLACK];
     E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: internal bit of window ply j
 
-    const int64_t e0 = (int64_t)blockIdx.x * BLOCK;
+    const int64_t e0 = blk * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
     const int t = threadIdx.x;
     const int64_t e = e0 + t;
     const bool valid = t < nb;
 
     const int64_t ec = valid ? e : e0; // lanes past the batch end mirror env e0, then are ignored
-    int me = st.to_move[ec], status = valid ? (int)st.status[ec] : ILLEGAL, winner = st.winner[ec];
-    int passes = st.passes[ec], ply = st.ply[ec], last = st.last_action[ec];
+    int me = 1, status = valid ? RUNNING : ILLEGAL, winner = -1, passes = 0, ply = 0, last = -1;
+    if constexpr (!FROM_START) {
+        me = st.to_move[ec];
+        status = valid ? (int)st.status[ec] : ILLEGAL;
+        winner = st.winner[ec];
+        passes = st.passes[ec];
+        ply = st.ply[ec];
+        last = st.last_action[ec];
+    }
     const uint64_t id = (uint64_t)(gid != nullptr ? gid[ec] : gid_base + ec);
     // a block whose envs are all RUNNING at ply 0 holds start positions
     // (empty boards for these games; the ply counts the plies applied since
     // ludax_init): its boards are not read
     M b1 = bb_zero<G::NWI>(), b2 = bb_zero<G::NWI>();
-    if (!__syncthreads_and(!valid || (status == RUNNING && ply == 0))) {
-        stage_in<G::CELLS>(st.board, e0, nb, lds);
-        BB<G::NWC> c1, c2;
-        read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
-        b1 = G::from_canon(c1);
-        b2 = G::from_canon(c2);
+    if constexpr (!FROM_START) {
+        if (!__syncthreads_and(!valid || (status == RUNNING && ply == 0))) {
+            stage_in<G::CELLS>(st.board, e0, nb, lds);
+            BB<G::NWC> c1, c2;
+            read_board<G::CELLS, G::NWC>(lds + t * G::CELLS, c1, c2);
+            b1 = G::from_canon(c1);
+            b2 = G::from_canon(c2);
+        }
+        __syncthreads(); // the staging area becomes the move list
     }
-    __syncthreads(); // the staging area becomes the move list
 
     const bool run = valid && status == RUNNING;
     const Window<G> w = play_window<G>(b1, b2, run, me, ply, max_plies, (uint32_t)id, (uint32_t)(id >> 32),
@@ -1132,6 +1150,102 @@ __global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, 
         terminal[e] = 1;
     }
     stage_out(st.board + e0 * G::CELLS, nb * G::CELLS, lds);
+}
+
+// Fill-then-resolve playout of a batch of states (Hex, Tic-Tac-Toe,
+// Connect Four).
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_playout_fill(DevState st, int64_t n, int max_plies,
+                                                        uint32_t key0, uint32_t key1, int64_t gid_base,
+                                                        const int64_t *__restrict__ gid,
+                                                        int8_t *__restrict__ reward,
+                                                        uint8_t *__restrict__ terminal)
+{
+    __shared__ __align__(16) int8_t lds[fill_lds_bytes<G>()];
+    playout_fill_block<G, false>(st, n, max_plies, key0, key1, gid_base, gid, reward, terminal, blockIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batch groups: several batches, each of its own game, in one launch.  The
+// group's games are a fixed type list Gs (GroupGames); block b serves batch
+// k for first_block[k] <= b < first_block[k + 1], and runs the body of that
+// batch's game (slot[k], its index in Gs).  Kernels of one stream run one
+// after the other, so separate launches leave the chip to the first
+// batch's waves alone (65536 envs = one wave per SIMD) and the next batch
+// waits for its tail; in one grid the batches' waves share the SIMDs.
+// ---------------------------------------------------------------------------
+template <class... Gs>
+struct GroupGames {
+    static constexpr int LDS = [] {
+        int m = 0;
+        for (int b : {fill_lds_bytes<Gs>()...}) m = b > m ? b : m;
+        return m;
+    }();
+    template <class G>
+    static constexpr int slot_of()
+    {
+        int i = 0, r = -1;
+        for (bool same : {std::is_same_v<G, Gs>...}) {
+            if (same && r < 0) r = i;
+            ++i;
+        }
+        return r;
+    }
+};
+
+// the fill-then-resolve games that share the group kernel
+using PlayoutGroup = GroupGames<TicTacToe, ConnectFour, Hex<11>>;
+
+// field k of a kernel-argument array, k wave-uniform: a chain of selects on
+// constant indices keeps the arguments in scalar registers (an indexed
+// access would copy the array to scratch memory)
+template <class T, int N>
+__device__ __forceinline__ T pick(const T (&v)[N], int k)
+{
+    T r = v[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) r = k == j ? v[j] : r;
+    return r;
+}
+
+__device__ __forceinline__ DevState pick_state(const DevState (&v)[GROUP_MAX], int k)
+{
+    DevState r = v[0];
+#pragma unroll
+    for (int j = 1; j < GROUP_MAX; ++j)
+        if (k == j) r = v[j];
+    return r;
+}
+
+template <bool FROM_START, int I, class G, class... Rest>
+__device__ __forceinline__ void group_body(const GroupArgs &a, int slot, int k, int64_t blk, int8_t *lds)
+{
+    if (slot == I) {
+        playout_fill_block<G, FROM_START>(pick_state(a.st, k), pick(a.n, k), pick(a.max_plies, k), a.key0, a.key1,
+                                          pick(a.gid_base, k), nullptr, pick(a.reward, k), pick(a.terminal, k),
+                                          blk, lds);
+    } else if constexpr (sizeof...(Rest) > 0) {
+        group_body<FROM_START, I + 1, Rest...>(a, slot, k, blk, lds);
+    }
+}
+
+template <bool FROM_START, class... Gs>
+__device__ __forceinline__ void group_run(const GroupArgs &a, GroupGames<Gs...>, int slot, int k, int64_t blk,
+                                          int8_t *lds)
+{
+    group_body<FROM_START, 0, Gs...>(a, slot, k, blk, lds);
+}
+
+template <bool FROM_START, class Group>
+__global__ __launch_bounds__(BLOCK) void k_playout_group(GroupArgs a)
+{
+    __shared__ __align__(16) int8_t lds[Group::LDS];
+    const int b = blockIdx.x;
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < GROUP_MAX; ++j)
+        if (j < a.nb && b >= a.first_block[j]) k = j;
+    group_run<FROM_START>(a, Group{}, pick(a.slot, k), k, (int64_t)(b - pick(a.first_block, k)), lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,11 +1547,13 @@ struct Launch {
     static constexpr GameOps ops()
     {
         if constexpr (G::KIND == 3)
-            return GameOps{G::KIND, G::H,        G::W,          G::CELLS, G::A,     &init,           &mask, &step,
-                           &random_step, &policy_step, &playout, &persist, HexAux<G::H>::BYTES, &aux_sync};
+            return GameOps{G::KIND,     G::H,         G::W,     G::CELLS, G::A,
+                           &init,       &mask,        &step,    &random_step,
+                           &policy_step, &playout,    &persist, HexAux<G::H>::BYTES,
+                           &aux_sync,   PlayoutGroup::slot_of<G>()};
         else
             return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step,
-                           &playout, &persist, 0, nullptr};
+                           &playout, &persist, 0, nullptr, PlayoutGroup::slot_of<G>()};
     }
 };
 

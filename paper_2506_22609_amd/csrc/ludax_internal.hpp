@@ -30,6 +30,27 @@ struct MixedArgs {
     unsigned int *counter;
 };
 
+// A batch group (k_playout_group): batch k of nb is served by blocks
+// [first_block[k], first_block[k + 1]) and played with the group kernel's
+// game slot[k]; game id of env i = gid_base[k] + i.
+constexpr int GROUP_MAX = 4;
+
+struct GroupArgs {
+    DevState st[GROUP_MAX];
+    int64_t n[GROUP_MAX];
+    int64_t gid_base[GROUP_MAX];
+    int8_t *reward[GROUP_MAX];
+    uint8_t *terminal[GROUP_MAX];
+    int32_t max_plies[GROUP_MAX];
+    int32_t slot[GROUP_MAX];
+    int32_t first_block[GROUP_MAX + 1];
+    int32_t nb;
+    uint32_t key0, key1;
+};
+
+// from_start: the envs are reset to the start position inside the kernel
+hipError_t launch_playout_group(const GroupArgs &a, bool from_start, hipStream_t s);
+
 // Kernel entry points of one (game, board size), filled in by the
 // instantiation units.
 struct GameOps {
@@ -47,6 +68,7 @@ struct GameOps {
     hipError_t (*persist)(const MixedArgs &, int, hipStream_t); // NULL: no mixed batches of this game
     int aux_bytes;                                               // per-env cache size (0: no cache)
     hipError_t (*aux_sync)(const DevState &, int64_t, hipStream_t); // NULL when aux_bytes == 0
+    int group_slot; // index in the batch-group kernel's game list, -1 if not in it
 };
 
 hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s);
@@ -56,6 +78,10 @@ hipError_t launch_mixed_stats(const int8_t *winner, const int16_t *plies, int64_
 // Step and outcome counters: stats[0..3] += sign * (sum of ply, number of
 // TERMINAL envs won by player 1, by player 2, drawn) over the n envs.
 hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats, hipStream_t s);
+// the same for nb <= GROUP_MAX batches in one launch: stats[k] gets batch
+// k's counters (batches with stats[k] NULL or n[k] = 0 are skipped)
+hipError_t launch_stats_group(const DevState *st, const int64_t *n, int nb, int sign, int64_t *const *stats,
+                              hipStream_t s);
 
 // The policy/value network (net.hip); N = board side, 11 or 19.
 int64_t net_n_params();

@@ -7,6 +7,8 @@
 // (all four loads in flight at once), a block reduces through wave
 // shuffles and LDS, and adds its totals with four atomics; few blocks keep
 // same-address atomics rare.
+#include <algorithm>
+
 #include "ludax_internal.hpp"
 
 namespace lx {
@@ -25,10 +27,11 @@ __device__ __forceinline__ void tally(int st, int w, int &w1, int &w2, int &d)
     d += term && w == 0;
 }
 
-__global__ __launch_bounds__(SB) void k_stats(const int8_t *__restrict__ status,
-                                              const int8_t *__restrict__ winner,
-                                              const int16_t *__restrict__ ply, int64_t n, int64_t nvec,
-                                              int sign, unsigned long long *__restrict__ stats)
+// The counters of envs [0, n) (the first nvec groups of 16 by vector loads),
+// this block's share of them for blocks blockIdx.x of gridDim.x.
+__device__ __forceinline__ void stats_block(const int8_t *__restrict__ status, const int8_t *__restrict__ winner,
+                                            const int16_t *__restrict__ ply, int64_t n, int64_t nvec, int sign,
+                                            unsigned long long *__restrict__ stats)
 {
     int64_t s = 0;
     int w1 = 0, w2 = 0, d = 0;
@@ -77,7 +80,53 @@ __global__ __launch_bounds__(SB) void k_stats(const int8_t *__restrict__ status,
     }
 }
 
+__global__ __launch_bounds__(SB) void k_stats(const int8_t *__restrict__ status,
+                                              const int8_t *__restrict__ winner,
+                                              const int16_t *__restrict__ ply, int64_t n, int64_t nvec,
+                                              int sign, unsigned long long *__restrict__ stats)
+{
+    stats_block(status, winner, ply, n, nvec, sign, stats);
+}
+
+struct StatsGroup {
+    const int8_t *status[GROUP_MAX];
+    const int8_t *winner[GROUP_MAX];
+    const int16_t *ply[GROUP_MAX];
+    int64_t n[GROUP_MAX], nvec[GROUP_MAX];
+    unsigned long long *stats[GROUP_MAX];
+};
+
+// blockIdx.y = the batch (a launch holds only batches with counters)
+__global__ __launch_bounds__(SB) void k_stats_group(StatsGroup g, int sign)
+{
+    const int k = blockIdx.y;
+    // constant-index selects keep the arguments in scalar registers
+    const int8_t *status = g.status[0], *winner = g.winner[0];
+    const int16_t *ply = g.ply[0];
+    int64_t n = g.n[0], nvec = g.nvec[0];
+    unsigned long long *stats = g.stats[0];
+#pragma unroll
+    for (int j = 1; j < GROUP_MAX; ++j)
+        if (k == j) {
+            status = g.status[j];
+            winner = g.winner[j];
+            ply = g.ply[j];
+            n = g.n[j];
+            nvec = g.nvec[j];
+            stats = g.stats[j];
+        }
+    stats_block(status, winner, ply, n, nvec, sign, stats);
+}
+
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+int64_t stats_blocks(int64_t work)
+{
+    int64_t blocks = (work + SB - 1) / SB;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 128) blocks = 128;
+    return blocks;
+}
 
 } // namespace
 
@@ -87,12 +136,34 @@ hipError_t launch_stats(const DevState &st, int64_t n, int sign, int64_t *stats,
     const int64_t nvec = vec ? n / PER : 0;
     // one group of 16 envs per thread (latency, not bandwidth, is the
     // cost here), at most 128 blocks so that atomics stay few
-    const int64_t work = nvec > 0 ? nvec : n;
-    int64_t blocks = (work + SB - 1) / SB;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 128) blocks = 128;
+    const int64_t blocks = stats_blocks(nvec > 0 ? nvec : n);
     hipLaunchKernelGGL(k_stats, dim3((unsigned)blocks), dim3(SB), 0, s, st.status, st.winner, st.ply, n,
                        nvec, sign, reinterpret_cast<unsigned long long *>(stats));
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_group(const DevState *st, const int64_t *n, int nb, int sign, int64_t *const *stats,
+                              hipStream_t s)
+{
+    if (nb > GROUP_MAX) return hipErrorInvalidValue;
+    StatsGroup g = {};
+    int m = 0;
+    int64_t blocks = 1;
+    for (int k = 0; k < nb; ++k) {
+        if (stats[k] == nullptr || n[k] <= 0) continue;
+        const bool vec = aligned16(st[k].status) && aligned16(st[k].winner) && aligned16(st[k].ply);
+        g.status[m] = st[k].status;
+        g.winner[m] = st[k].winner;
+        g.ply[m] = st[k].ply;
+        g.n[m] = n[k];
+        g.nvec[m] = vec ? n[k] / PER : 0;
+        g.stats[m] = reinterpret_cast<unsigned long long *>(stats[k]);
+        blocks = std::max<int64_t>(blocks, stats_blocks(g.nvec[m] > 0 ? g.nvec[m] : n[k]));
+        ++m;
+    }
+    if (m == 0) return hipSuccess;
+    // a block past a smaller batch's share finds no envs and adds nothing
+    hipLaunchKernelGGL(k_stats_group, dim3((unsigned)blocks, (unsigned)m), dim3(SB), 0, s, g, sign);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libludax.so
 # every symbol the public header declares
 EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_init",
            "ludax_legal_mask", "ludax_step", "ludax_random_step", "ludax_policy_step", "ludax_playout",
+           "ludax_playout_batches",
            "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
            "ludax_mixed_set_slots",
            "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_playout_noalloc",
@@ -57,6 +58,12 @@ class _State(ctypes.Structure):
                 ("last_action", ctypes.c_void_p), ("aux", ctypes.c_void_p)]
 
 
+class _Batch(ctypes.Structure):
+    _fields_ = [("game", ctypes.c_void_p), ("state", ctypes.POINTER(_State)), ("n", ctypes.c_int64),
+                ("game_id_base", ctypes.c_int64), ("reward", ctypes.c_void_p), ("terminal", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
+
+
 def _load():
     global _lib
     with _lock:
@@ -78,6 +85,7 @@ def _load():
             L.ludax_policy_step.argtypes = [vp, P(_State), vp, ctypes.c_uint64, i64, vp, vp, vp, i64, vp]
             L.ludax_playout.argtypes = [vp, P(_State), ctypes.c_uint64, i64, vp, vp, vp, vp, i64,
                                         vp]
+            L.ludax_playout_batches.argtypes = [P(_Batch), i32, ctypes.c_uint64, i32, vp]
             L.ludax_state_stats.argtypes = [vp, P(_State), ctypes.c_int32, vp, i64, vp]
             L.ludax_aux_sync.argtypes = [vp, P(_State), i64, vp]
             L.ludax_mixed_create.argtypes = [vp, i32, P(vp)]
@@ -354,6 +362,81 @@ def playout(game: Game, state: State, seed: int, game_id_base: int = 0, game_id=
                                  _ptr(reward), _ptr(terminal), _ptr(stats), state.n,
                                  _stream(stream)), "ludax_playout")
     return reward, terminal, stats
+
+
+def playout_batches(batches, seed: int, from_start: bool = True, stream=None):
+    """ludax_playout_batches: batches = [(game, state, game_id_base, reward,
+    terminal, stats), ...] (reward / terminal / stats as in playout: None
+    allocates reward and terminal; stats None = no counters).  Returns the
+    (reward, terminal, stats) of every batch."""
+    arr = (_Batch * len(batches))()
+    keep, out = [], []
+    for k, (game, state, base, reward, terminal, stats) in enumerate(batches):
+        dev = state.board.device
+        if reward is None:
+            reward = torch.empty((state.n, 2), dtype=torch.int8, device=dev)
+        if terminal is None:
+            terminal = torch.empty(state.n, dtype=torch.uint8, device=dev)
+        _need(reward, torch.int8, (state.n, 2), "reward")
+        _need(terminal, torch.uint8, (state.n,), "terminal")
+        if stats is not None:
+            _need(stats, torch.int64, (4,), "stats")
+        c = state._c()
+        keep.append(c)
+        arr[k] = _Batch(game.handle, ctypes.pointer(c), state.n, base, reward.data_ptr(), terminal.data_ptr(),
+                        None if stats is None else stats.data_ptr())
+        out.append((reward, terminal, stats))
+    _check(_load().ludax_playout_batches(arr, len(batches), ctypes.c_uint64(seed & (2**64 - 1)),
+                                         1 if from_start else 0, _stream(stream)), "ludax_playout_batches")
+    return out
+
+
+class BatchGroup:
+    """A fixed list of batches for repeated ludax_playout_batches calls:
+    the arguments are checked and marshalled once, and each call only sets
+    the game-id bases (the tensors must stay in place between calls).
+    batches = [(game, state, reward, terminal, stats), ...] with reward,
+    terminal and stats as in playout_batches."""
+
+    def __init__(self, batches):
+        self._items = []
+        self._arr = (_Batch * len(batches))()
+        self._keep = []
+        for k, (game, state, reward, terminal, stats) in enumerate(batches):
+            dev = state.board.device
+            if reward is None:
+                reward = torch.empty((state.n, 2), dtype=torch.int8, device=dev)
+            if terminal is None:
+                terminal = torch.empty(state.n, dtype=torch.uint8, device=dev)
+            _need(reward, torch.int8, (state.n, 2), "reward")
+            _need(terminal, torch.uint8, (state.n,), "terminal")
+            if stats is not None:
+                _need(stats, torch.int64, (4,), "stats")
+            c = state._c()
+            self._keep.append((game, state, c))
+            self._arr[k] = _Batch(game.handle, ctypes.pointer(c), state.n, 0, reward.data_ptr(),
+                                  terminal.data_ptr(), None if stats is None else stats.data_ptr())
+            self._items.append((reward, terminal, stats))
+        self._n = len(batches)
+        self._fn = _load().ludax_playout_batches
+
+    @property
+    def outputs(self):
+        return self._items
+
+    def run(self, seed: int, game_id_bases, from_start: bool = True, stream=None, stats=None):
+        """stats: None keeps the counters given at construction, else one
+        int64[4] tensor (or None) per batch for this call."""
+        arr = self._arr
+        for k, base in enumerate(game_id_bases):
+            arr[k].game_id_base = base
+        if stats is not None:
+            for k, t in enumerate(stats):
+                if t is not None:
+                    _need(t, torch.int64, (4,), "stats")
+                arr[k].stats = None if t is None else t.data_ptr()
+        _check(self._fn(arr, self._n, ctypes.c_uint64(seed & (2**64 - 1)), 1 if from_start else 0,
+                        _stream(stream)), "ludax_playout_batches")
 
 
 def state_stats(game: Game, state: State, sign: int, stats: torch.Tensor, stream=None):

@@ -147,6 +147,36 @@ def test_host_argument_checks_need_no_gpu():
     L.ludax_game_destroy(h)
 
 
+def test_playout_batches_argument_checks_need_no_gpu():
+    L = _lib()
+    rc, h = _create(3, 11, 11)
+    assert rc == 0
+    st = ludax._State(*([16] * 7), None)  # aligned, non-null fake pointers (never dereferenced)
+    odd_board = ludax._State(17, *([16] * 6), None)
+    s = ctypes.c_void_p(0)
+    B = ludax._Batch
+
+    def call(*batches, n_batches=None):
+        arr = (B * max(1, len(batches)))(*batches)
+        return L.ludax_playout_batches(arr, len(batches) if n_batches is None else n_batches, 1, 1, s)
+
+    ok = B(h, ctypes.pointer(st), 64, 0, 16, 16, None)
+    assert L.ludax_playout_batches(None, 1, 1, 1, s) == ludax.E_INVALID
+    assert call(ok, n_batches=0) == ludax.E_INVALID
+    assert call(ok, ok, ok, ok, ok) == ludax.E_INVALID                          # more than 4
+    assert call(B(None, ctypes.pointer(st), 64, 0, 16, 16, None)) == ludax.E_INVALID
+    assert call(B(h, ctypes.pointer(st), -1, 0, 16, 16, None)) == ludax.E_INVALID
+    assert call(B(h, ctypes.pointer(st), 64, 0, None, 16, None)) == ludax.E_INVALID
+    assert call(B(h, ctypes.pointer(st), 64, 0, 16, None, None)) == ludax.E_INVALID
+    assert call(B(h, None, 64, 0, 16, 16, None)) == ludax.E_INVALID
+    assert call(ok, B(h, ctypes.pointer(odd_board), 64, 0, 16, 16, None)) == ludax.E_INVALID
+    big = B(h, ctypes.pointer(st), 2**30, 0, 16, 16, None)
+    assert call(big, big) == ludax.E_INVALID                                    # 2^31 envs in one grid
+    # batches of no envs are skipped unchecked; all empty launches nothing
+    assert call(B(h, None, 0, 0, None, None, None), B(h, None, 0, 0, None, None, None)) == 0
+    L.ludax_game_destroy(h)
+
+
 def test_strerror():
     L = _lib()
     for code in (0, -1, -2, -3, 5):
