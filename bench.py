@@ -232,7 +232,11 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     m = ludax.Mixed(games)
     n = mb.n_games
     out = ludax.MixedResult(n, len(games))
-    equal_ms = _mixed_equal_split_ms(m, len(games), mb.slots, seed, n, out)
+    # the equal split launched as one grid and as a kernel per kind
+    equal_ms = {}
+    for og in (True, False):
+        m.one_grid = og
+        equal_ms["one_grid" if og else "streams"] = _mixed_equal_split_ms(m, len(games), mb.slots, seed, n, out)
     tune_ms = m.autotune(seed, 0, n, mb.slots, out=out)
     stats = torch.zeros((len(games), 4), dtype=torch.int64, device="cuda")
     side = torch.cuda.Stream()
@@ -285,7 +289,7 @@ def _mixed_section(seed: int, steps: int, warmup: int):
     return {
         "workload": f"{mb.name}: {n} game ids, kind = id mod 4 "
                     f"({', '.join(b.name for b in mb.kinds)}), {mb.slots} slots with refill",
-        "slots_per_kind": m.slots, "autotuned_ms": tune_ms, "equal_split_ms": equal_ms,
+        "slots_per_kind": m.slots, "one_grid": m.one_grid, "autotuned_ms": tune_ms, "equal_split_ms": equal_ms,
         "mixed_graph_env_steps_per_s": g_steps / g_el,
         "mixed_graph_ms_per_batch": g_el / steps * 1e3,
         "mixed_eager_env_steps_per_s": e_steps / e_el,

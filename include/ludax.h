@@ -343,6 +343,18 @@ int ludax_mixed_destroy(ludax_mixed *mixed);
 int ludax_mixed_set_slots(ludax_mixed *mixed, const int32_t *slots);
 int ludax_mixed_get_slots(const ludax_mixed *mixed, int32_t *slots);
 
+/* How the kinds are launched.  one_grid = 1: every kind's persistent loop
+ * in one grid (block ranges per kind, one launch on the caller's stream;
+ * the kinds overlap whatever the hardware queues, as long as the grid is
+ * resident at once: at most 4 waves per SIMD, i.e. 262144 slots in all on
+ * 256 CUs).  Only for kinds in the one-grid kernel's list: Tic-Tac-Toe,
+ * Connect Four 6x7, Reversi 8x8, Hex 11x11, Gomoku 15x15
+ * (LUDAX_E_UNSUPPORTED otherwise).  one_grid = 0: one kernel per kind on
+ * the internal streams.  The default is 1 where supported; the autotuner
+ * times both and keeps the faster.  Results do not depend on it. */
+int ludax_mixed_set_one_grid(ludax_mixed *mixed, int32_t one_grid);
+int ludax_mixed_get_one_grid(const ludax_mixed *mixed, int32_t *one_grid);
+
 /* Play every game of the batch to its end.  Device outputs indexed by j:
  * winner [n_games] int8 (0 draw, 1, 2; -1 if truncated at max_plies),
  * plies [n_games] int16 (plies of the game), last_action [n_games] int16.
@@ -378,8 +390,10 @@ int ludax_mixed_playout_noalloc(ludax_mixed *mixed, uint64_t seed, int64_t id_ba
  * largest kind's share moved by +-25 %, and the occupancy plan that brings
  * every kind's fitted time to a common value with the lanes adding up to
  * total_slots (and that plan with the flattest-scaling kind's share moved
- * by +-25 %); keeps the fastest as the handle's plan
- * (ludax_mixed_get_slots reads it).  Runs real batches with the given
+ * by +-25 %), each split launched as one grid (where supported) and as a
+ * kernel per kind; keeps the fastest split and launch as the handle's plan
+ * (ludax_mixed_get_slots and ludax_mixed_get_one_grid read it).  Runs real
+ * batches with the given
  * arguments (outputs are overwritten) and SYNCHRONISES the stream.
  * *best_ms (may be NULL) receives the chosen plan's time. */
 int ludax_mixed_autotune(ludax_mixed *mixed, uint64_t seed, int64_t id_base, int64_t n_games,

@@ -348,6 +348,7 @@ struct ludax_mixed {
     int n;
     const ludax_game *games[8];
     int32_t slots[8];
+    int one_grid; // 1: every kind in one launch (k_persist_group), 0: a kernel per kind on its stream
     hipStream_t streams[8];
     hipEvent_t fork, join[8];
 };
@@ -372,12 +373,51 @@ void kind_range(int64_t id_base, int64_t n_games, int n, int k, int64_t *j0, int
     *count = first < n_games ? (n_games - 1 - first) / n + 1 : 0;
 }
 
-// Enqueue a batch under `slots` for the kinds whose bit is set in `mask`.
+bool one_grid_ok(const ludax_mixed *m)
+{
+    for (int k = 0; k < m->n; ++k)
+        if (m->games[k]->ops->mixed_slot < 0) return false;
+    return true;
+}
+
+// Enqueue a batch under `slots` for the kinds whose bit is set in `mask`,
+// in one grid or as one kernel per kind (one_grid).
 int mixed_run(ludax_mixed *m, const int32_t *slots, unsigned mask, uint64_t seed, int64_t id_base,
               int64_t n_games, int8_t *winner, int16_t *plies, int16_t *last, int64_t *stats,
-              uint32_t *workspace, hipStream_t stream)
+              uint32_t *workspace, hipStream_t stream, int one_grid)
 {
     hipError_t e = lx::launch_zero_counters(workspace, m->n, stream);
+    if (one_grid) {
+        lx::MixedGroupArgs g = {};
+        int q = 0, blocks = 0;
+        for (int k = 0; k < m->n; ++k) {
+            if (!((mask >> k) & 1u)) continue;
+            lx::MixedArgs &a = g.k[q];
+            kind_range(id_base, n_games, m->n, k, &a.j0, &a.count);
+            if (a.count == 0) continue;
+            a.id_base = id_base;
+            a.stride = m->n;
+            a.max_plies = m->games[k]->max_plies;
+            a.key0 = (uint32_t)seed;
+            a.key1 = (uint32_t)(seed >> 32);
+            a.winner = winner;
+            a.plies = plies;
+            a.last = last;
+            a.counter = workspace + k;
+            const int64_t need = (a.count + 63) / 64 * 64;
+            const int lanes = (int)std::min<int64_t>(slots[k], need);
+            g.slot[q] = m->games[k]->ops->mixed_slot;
+            g.first_block[q] = blocks;
+            blocks += lanes / 64;
+            ++q;
+        }
+        for (int k = q; k <= lx::MIXED_MAX; ++k) g.first_block[k] = blocks;
+        g.n = q;
+        if (e == hipSuccess && q > 0) e = lx::launch_mixed_group(g, stream);
+        if (e == hipSuccess && stats != nullptr)
+            e = lx::launch_mixed_stats(winner, plies, n_games, id_base, m->n, stats, stream);
+        return device_error(e);
+    }
     if (e == hipSuccess) e = hipEventRecord(m->fork, stream);
     for (int k = 0; k < m->n && e == hipSuccess; ++k) {
         if (!((mask >> k) & 1u)) continue;
@@ -420,7 +460,7 @@ int mixed_args_ok(const ludax_mixed *m, int64_t id_base, int64_t n_games, int8_t
 // wall time of one batch (ms), measured with events on the stream
 int timed_run(ludax_mixed *m, const int32_t *slots, unsigned mask, uint64_t seed, int64_t id_base,
               int64_t n_games, int8_t *winner, int16_t *plies, int16_t *last, uint32_t *workspace,
-              hipStream_t stream, float *ms)
+              hipStream_t stream, float *ms, int one_grid)
 {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return LUDAX_E_DEVICE;
@@ -430,7 +470,8 @@ int timed_run(ludax_mixed *m, const int32_t *slots, unsigned mask, uint64_t seed
     }
     int rc = device_error(hipEventRecord(a, stream));
     if (rc == LUDAX_OK)
-        rc = mixed_run(m, slots, mask, seed, id_base, n_games, winner, plies, last, nullptr, workspace, stream);
+        rc = mixed_run(m, slots, mask, seed, id_base, n_games, winner, plies, last, nullptr, workspace, stream,
+                       one_grid);
     if (rc == LUDAX_OK) rc = device_error(hipEventRecord(b, stream));
     if (rc == LUDAX_OK) rc = device_error(hipEventSynchronize(b));
     if (rc == LUDAX_OK) rc = device_error(hipEventElapsedTime(ms, a, b));
@@ -469,10 +510,13 @@ int ludax_mixed_create(const ludax_game *const *games, int32_t n_kinds, ludax_mi
     for (int k = 0; k < n_kinds && e == hipSuccess; ++k) {
         m->games[k] = games[k];
         m->slots[k] = 65536;
+        m->one_grid = 0;
         e = hipStreamCreateWithFlags(&m->streams[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&m->join[k], hipEventDisableTiming);
         if (e == hipSuccess) created = k + 1;
     }
+    // one grid when every kind is in the one-grid kernel
+    if (e == hipSuccess) m->one_grid = one_grid_ok(m) ? 1 : 0;
     if (e != hipSuccess) {
         for (int k = 0; k < created; ++k) {
             hipStreamDestroy(m->streams[k]);
@@ -511,6 +555,21 @@ int ludax_mixed_get_slots(const ludax_mixed *m, int32_t *slots)
     return LUDAX_OK;
 }
 
+int ludax_mixed_set_one_grid(ludax_mixed *m, int32_t one_grid)
+{
+    if (m == nullptr || (one_grid != 0 && one_grid != 1)) return LUDAX_E_INVALID;
+    if (one_grid && !one_grid_ok(m)) return LUDAX_E_UNSUPPORTED;
+    m->one_grid = one_grid;
+    return LUDAX_OK;
+}
+
+int ludax_mixed_get_one_grid(const ludax_mixed *m, int32_t *one_grid)
+{
+    if (m == nullptr || one_grid == nullptr) return LUDAX_E_INVALID;
+    *one_grid = m->one_grid;
+    return LUDAX_OK;
+}
+
 int ludax_mixed_playout(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t n_games, int8_t *winner,
                         int16_t *plies, int16_t *last_action, int64_t *stats, uint32_t *workspace,
                         hipStream_t stream)
@@ -519,7 +578,7 @@ int ludax_mixed_playout(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t 
     if (rc) return rc;
     if (n_games == 0) return LUDAX_OK;
     return mixed_run(m, m->slots, 0xFFu, seed, id_base, n_games, winner, plies, last_action, stats, workspace,
-                     stream);
+                     stream, m->one_grid);
 }
 
 // ---------------------------------------------------------------------------
@@ -572,7 +631,7 @@ int ludax_mixed_playout_noalloc(ludax_mixed *m, uint64_t seed, int64_t id_base, 
     rc = scratch_for_current_device(&counters);
     if (rc) return rc;
     return mixed_run(m, m->slots, 0xFFu, seed, id_base, n_games, winner, plies, last_action, stats, counters,
-                     stream);
+                     stream, m->one_grid);
 }
 
 int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t n_games, int32_t total_slots,
@@ -593,7 +652,8 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
     split(ones, n, total_slots, eq);
     for (int k = 0; k < n; ++k) {
         float ms = 0.f;
-        rc = timed_run(m, eq, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream, &ms);
+        rc = timed_run(m, eq, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream, &ms,
+                       m->one_grid);
         if (rc) return rc;
         t_eq[k] = ms;
         w[k] = (double)ms * eq[k];
@@ -607,7 +667,7 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
             if (alt[k] == eq[k]) continue;
             float ms2 = 0.f;
             rc = timed_run(m, alt, 1u << k, seed, id_base, n_games, winner, plies, last_action, workspace, stream,
-                           &ms2);
+                           &ms2, m->one_grid);
             if (rc) return rc;
             if (ms > 0.f && ms2 > 0.f) {
                 slope += -std::log((double)ms2 / ms) / std::log((double)alt[k] / eq[k]);
@@ -662,25 +722,32 @@ int ludax_mixed_autotune(ludax_mixed *m, uint64_t seed, int64_t id_base, int64_t
             add(v);
         }
     }
-    // 3. keep the fastest (a warm-up run first)
+    // 3. keep the fastest (plan, launch) pair, each plan launched as one
+    // grid (when every kind is in the one-grid kernel) and as a kernel per
+    // kind (a warm-up run first)
     float best = 0.f;
-    int best_i = -1;
+    int best_i = -1, best_grid = 0;
+    const int grids = one_grid_ok(m) ? 2 : 1;
     for (size_t i = 0; i < plans.size(); ++i) {
-        float ms = 0.f;
-        if (i == 0) {
+        for (int og = 0; og < grids; ++og) {
+            float ms = 0.f;
+            if (i == 0) {
+                rc = timed_run(m, plans[i].data(), 0xFFu, seed, id_base, n_games, winner, plies, last_action,
+                               workspace, stream, &ms, og);
+                if (rc) return rc;
+            }
             rc = timed_run(m, plans[i].data(), 0xFFu, seed, id_base, n_games, winner, plies, last_action,
-                           workspace, stream, &ms);
+                           workspace, stream, &ms, og);
             if (rc) return rc;
-        }
-        rc = timed_run(m, plans[i].data(), 0xFFu, seed, id_base, n_games, winner, plies, last_action, workspace,
-                       stream, &ms);
-        if (rc) return rc;
-        if (best_i < 0 || ms < best) {
-            best = ms;
-            best_i = (int)i;
+            if (best_i < 0 || ms < best) {
+                best = ms;
+                best_i = (int)i;
+                best_grid = og;
+            }
         }
     }
     for (int k = 0; k < n; ++k) m->slots[k] = plans[best_i][k];
+    m->one_grid = best_grid;
     if (best_ms) *best_ms = best;
     return LUDAX_OK;
 }

@@ -1272,7 +1272,7 @@ __device__ __forceinline__ int64_t next_chunk(unsigned int *counter)
 // refresh is uniform across the wave, and a finished lane idles at most
 // three steps.
 template <class G>
-__global__ __launch_bounds__(BLOCK) void k_persist_ply(MixedArgs a)
+__device__ __forceinline__ void persist_ply_body(const MixedArgs &a)
 {
     const int t = threadIdx.x;
     const uint64_t below = (1ull << t) - 1ull;
@@ -1336,6 +1336,12 @@ __global__ __launch_bounds__(BLOCK) void k_persist_ply(MixedArgs a)
             }
         }
     }
+}
+
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_persist_ply(MixedArgs a)
+{
+    persist_ply_body<G>(a);
 }
 
 // The same schedule for the movement games, over a lane adapter L:
@@ -1409,11 +1415,9 @@ __global__ __launch_bounds__(BLOCK) void k_persist_lane(MixedArgs a)
 // a chunk fills the same number of plies from the start position, so the
 // 64 lanes of a wave play 64 games in lockstep and then take the next chunk.
 template <class G>
-__global__ __launch_bounds__(BLOCK) void k_persist_fill(MixedArgs a)
+__device__ __forceinline__ void persist_fill_body(const MixedArgs &a, MoveT<G> *moves)
 {
     using M = typename G::M;
-    using E = MoveT<G>;
-    __shared__ __align__(16) E moves[BLOCK * G::CELLS];
     const int t = threadIdx.x;
     const M zero = bb_zero<G::NWI>();
     for (;;) {
@@ -1432,6 +1436,86 @@ __global__ __launch_bounds__(BLOCK) void k_persist_fill(MixedArgs a)
         }
         __syncthreads(); // the move list is reused by the next chunk
     }
+}
+
+template <class G>
+__global__ __launch_bounds__(BLOCK) void k_persist_fill(MixedArgs a)
+{
+    __shared__ __align__(16) MoveT<G> moves[BLOCK * G::CELLS];
+    persist_fill_body<G>(a, moves);
+}
+
+// A mixed batch in one grid: the kinds' persistent loops side by side in
+// one launch, block b serving kind k for first_block[k] <= b <
+// first_block[k + 1] with the body of its game (slot[k] in the type list
+// Gs).  No stream per kind: the kinds overlap whatever the queues, as long
+// as the grid is resident at once (the register footprint is the largest
+// body's, the LDS the largest move list).
+template <class... Gs>
+struct PersistGames {
+    template <class G>
+    static constexpr int lds_of()
+    {
+        return (G::KIND == 1 || G::KIND == 2 || G::KIND == 3) ? BLOCK * G::CELLS * (int)sizeof(MoveT<G>) : 0;
+    }
+    static constexpr int LDS = [] {
+        int m = 16;
+        for (int b : {lds_of<Gs>()...}) m = b > m ? b : m;
+        return m;
+    }();
+    template <class G>
+    static constexpr int slot_of()
+    {
+        int i = 0, r = -1;
+        for (bool same : {std::is_same_v<G, Gs>...}) {
+            if (same && r < 0) r = i;
+            ++i;
+        }
+        return r;
+    }
+};
+
+// the small-board kinds that share the one-grid mixed kernel
+using PersistGroup = PersistGames<TicTacToe, ConnectFour, Reversi, Hex<11>, Gomoku<15>>;
+
+template <int I, class G, class... Rest>
+__device__ __forceinline__ void persist_group_body(const MixedArgs &a, int slot, int8_t *lds)
+{
+    if (slot == I) {
+        if constexpr (G::KIND == 1 || G::KIND == 2 || G::KIND == 3)
+            persist_fill_body<G>(a, reinterpret_cast<MoveT<G> *>(lds));
+        else
+            persist_ply_body<G>(a);
+    } else if constexpr (sizeof...(Rest) > 0) {
+        persist_group_body<I + 1, Rest...>(a, slot, lds);
+    }
+}
+
+template <class... Gs>
+__device__ __forceinline__ void persist_group_run(const MixedArgs &a, PersistGames<Gs...>, int slot, int8_t *lds)
+{
+    persist_group_body<0, Gs...>(a, slot, lds);
+}
+
+template <class Group>
+__global__ __launch_bounds__(BLOCK) void k_persist_group(MixedGroupArgs g)
+{
+    __shared__ __align__(16) int8_t lds[Group::LDS];
+    const int b = blockIdx.x;
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < MIXED_MAX; ++j)
+        if (j < g.n && b >= g.first_block[j]) k = j;
+    // the kind's arguments by constant-index selects (scalar registers)
+    MixedArgs a = g.k[0];
+    int slot = g.slot[0];
+#pragma unroll
+    for (int j = 1; j < MIXED_MAX; ++j)
+        if (k == j) {
+            a = g.k[j];
+            slot = g.slot[j];
+        }
+    persist_group_run(a, Group{}, slot, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1550,10 +1634,10 @@ struct Launch {
             return GameOps{G::KIND,     G::H,         G::W,     G::CELLS, G::A,
                            &init,       &mask,        &step,    &random_step,
                            &policy_step, &playout,    &persist, HexAux<G::H>::BYTES,
-                           &aux_sync,   PlayoutGroup::slot_of<G>()};
+                           &aux_sync,   PlayoutGroup::slot_of<G>(), PersistGroup::slot_of<G>()};
         else
             return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step,
-                           &playout, &persist, 0, nullptr, PlayoutGroup::slot_of<G>()};
+                           &playout, &persist, 0, nullptr, PlayoutGroup::slot_of<G>(), PersistGroup::slot_of<G>()};
     }
 };
 

@@ -51,6 +51,20 @@ struct GroupArgs {
 // from_start: the envs are reset to the start position inside the kernel
 hipError_t launch_playout_group(const GroupArgs &a, bool from_start, hipStream_t s);
 
+// A mixed batch in one grid (k_persist_group): kind k of n runs on blocks
+// [first_block[k], first_block[k + 1]) with the one-grid kernel's game
+// slot[k] and its arguments k[k].
+constexpr int MIXED_MAX = 8;
+
+struct MixedGroupArgs {
+    MixedArgs k[MIXED_MAX];
+    int32_t slot[MIXED_MAX];
+    int32_t first_block[MIXED_MAX + 1];
+    int32_t n;
+};
+
+hipError_t launch_mixed_group(const MixedGroupArgs &a, hipStream_t s);
+
 // Kernel entry points of one (game, board size), filled in by the
 // instantiation units.
 struct GameOps {
@@ -69,6 +83,7 @@ struct GameOps {
     int aux_bytes;                                               // per-env cache size (0: no cache)
     hipError_t (*aux_sync)(const DevState &, int64_t, hipStream_t); // NULL when aux_bytes == 0
     int group_slot; // index in the batch-group kernel's game list, -1 if not in it
+    int mixed_slot; // index in the one-grid mixed kernel's game list, -1 if not in it
 };
 
 hipError_t launch_zero_counters(unsigned int *c, int n, hipStream_t s);

@@ -658,7 +658,7 @@ struct MoveLaunch {
     static constexpr GameOps ops()
     {
         return GameOps{G::KIND, G::H, G::W, G::CELLS, G::A, &init, &mask, &step, &random_step, &policy_step,
-                       &playout, &persist, 0, nullptr, -1};
+                       &playout, &persist, 0, nullptr, -1, -1};
     }
 };
 

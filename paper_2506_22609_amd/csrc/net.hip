@@ -1711,7 +1711,11 @@ __global__ __launch_bounds__(256) void k_head_wgrad(const uint16_t *__restrict__
 // boards one at a time: the next board's dZ and X are loaded into registers
 // while the current one is multiplied, then transposed into LDS (cell-major
 // rows per channel); the bias gradient is summed by wave 0 from the A
-// fragments it already holds.
+// fragments it already holds.  With 64 input channels wave w takes the
+// channel tile w of every tap, so a lane's channel row is fixed and each
+// tap is a constant offset: the eight 2-byte reads of a B fragment use
+// eight per-K-step addresses with the tap in the instructions' offset
+// field; X is transposed two cells at a time (32-bit writes).
 // part layout per block: [64 * CR * 9] (param order o, i, t) then [64] db.
 // ---------------------------------------------------------------------------
 template <int N, int CIN>
@@ -1720,7 +1724,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
 {
     constexpr int NP = N + 2, PP = NP * NP, PIX = N * N;
     constexpr int PIXP = (PIX + 31) / 32 * 32, DS = PIXP + 8; // dZ^T row stride
-    constexpr int PPS = PP + 8;                               // X^T row stride
+    // X^T row stride: room for every tap of every cell; with 64 channels
+    // even (cell pairs are 32-bit writes) and an odd number of words (the 16
+    // rows of a fragment read fall in 16 banks)
+    constexpr int PPS = CIN == 64 ? (PP + 1) / 4 * 4 + 2 : PP + 8;
+    static_assert(CIN != 64 || (PPS >= PP && PPS % 2 == 0 && (PPS / 2) % 2 == 1), "X^T stride");
     constexpr int CR = CIN == 4 ? 3 : CIN;                    // real input channels
     constexpr int NCOL = 9 * CIN, NT = (NCOL + 15) / 16;      // column tiles
     constexpr int NTW = (NT + 3) / 4;                         // column tiles per wave
@@ -1731,7 +1739,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     // padding).  X: a (cell, 8 channels) item, 16 bytes (64 channels), or a
     // cell, 8 bytes (4 channels), written as single cells of X^T.
     constexpr int DZ_ITEMS = 32 * (PIXP / 8), DZ_R = (DZ_ITEMS + 255) / 256;
-    constexpr int X_ITEMS = CIN == 4 ? PP : PP * 8, X_R = (X_ITEMS + 255) / 256;
+    // X items: a cell of 4 channels (8 bytes); with 64 channels a pair of
+    // cells and 8 channels (two 16-byte loads)
+    constexpr int X_ITEMS = CIN == 4 ? PP : (PP + 1) / 2 * 8, X_R = (X_ITEMS + 255) / 256;
     __shared__ __align__(16) uint16_t dzt[C * DS];
     __shared__ __align__(16) uint16_t xt[CIN * PPS];
 
@@ -1753,8 +1763,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
         col_off[j] = (t / 3) * NP + (t % 3);
         col_ch[j] = i;
     }
+    static_assert(CIN != 64 || NTW == 9, "64 channels: a wave's tiles are the 9 taps of its channel tile");
     uint32_t dzv[DZ_R][8]; // the next board: 8 cells of a channel pair per item
-    uint4 xv[X_R];
+    uint4 xv[X_R], xv2[CIN == 64 ? X_R : 1];
     auto load_board = [&](int64_t b) {
         const uint16_t *db = dz + b * (int64_t)PP * C;
         const uint16_t *xb = x + b * (int64_t)PP * CIN;
@@ -1778,7 +1789,10 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
                     const uint2 v = *reinterpret_cast<const uint2 *>(xb + (int64_t)j * 4);
                     xv[r] = uint4{v.x, v.y, 0u, 0u};
                 } else {
-                    xv[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)(j >> 3) * C + (j & 7) * 8);
+                    const int q = 2 * (j >> 3), c8 = (j & 7) * 8;
+                    xv[r] = *reinterpret_cast<const uint4 *>(xb + (int64_t)q * C + c8);
+                    xv2[r] = q + 1 < PP ? *reinterpret_cast<const uint4 *>(xb + (int64_t)(q + 1) * C + c8)
+                                        : uint4{0u, 0u, 0u, 0u};
                 }
             }
         }
@@ -1813,12 +1827,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
                     xt[2 * PPS + j] = (uint16_t)(xv[r].y & 0xFFFFu);
                     xt[3 * PPS + j] = (uint16_t)(xv[r].y >> 16);
                 } else {
-                    const int q = j >> 3, c0 = (j & 7) * 8;
-                    const uint32_t wd[4] = {xv[r].x, xv[r].y, xv[r].z, xv[r].w};
+                    // channel c0 + 2h: the low halves of both cells, c0 + 2h + 1: the high halves
+                    const int q = 2 * (j >> 3), c0 = (j & 7) * 8;
+                    const uint32_t a[4] = {xv[r].x, xv[r].y, xv[r].z, xv[r].w};
+                    const uint32_t bq[4] = {xv2[r].x, xv2[r].y, xv2[r].z, xv2[r].w};
 #pragma unroll
                     for (int h = 0; h < 4; ++h) {
-                        xt[(c0 + 2 * h) * PPS + q] = (uint16_t)(wd[h] & 0xFFFFu);
-                        xt[(c0 + 2 * h + 1) * PPS + q] = (uint16_t)(wd[h] >> 16);
+                        *reinterpret_cast<uint32_t *>(xt + (c0 + 2 * h) * PPS + q) =
+                            __builtin_amdgcn_perm(bq[h], a[h], 0x05040100u);
+                        *reinterpret_cast<uint32_t *>(xt + (c0 + 2 * h + 1) * PPS + q) =
+                            __builtin_amdgcn_perm(bq[h], a[h], 0x07060302u);
                     }
                 }
             }
@@ -1849,17 +1867,37 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
                 const int p = p0 + i < PIX ? p0 + i : 0;
                 cq[i] = (p / N) * NP + p % N;
             }
+            if constexpr (CIN == 64) {
+                // this lane's channel row; tap t = j at a constant offset
+                const uint16_t *xl[8];
 #pragma unroll
-            for (int j = 0; j < NTW; ++j) {
-                if (wave * NTW + j >= NT) break;
-                const uint16_t *xrow = xt + col_ch[j] * PPS + col_off[j];
-                uint32_t u[4];
+                for (int i = 0; i < 8; ++i) xl[i] = xt + (wave * 16 + row) * PPS + cq[i];
 #pragma unroll
-                for (int h = 0; h < 4; ++h) u[h] = (uint32_t)xrow[cq[2 * h]] | ((uint32_t)xrow[cq[2 * h + 1]] << 16);
-                const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
+                for (int j = 0; j < NTW; ++j) {
+                    const int off = (j / 3) * NP + (j % 3);
+                    uint32_t u[4];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt)
-                    acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][j], 0, 0, 0);
+                    for (int h = 0; h < 4; ++h)
+                        u[h] = (uint32_t)xl[2 * h][off] | ((uint32_t)xl[2 * h + 1][off] << 16);
+                    const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][j], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NTW; ++j) {
+                    if (wave * NTW + j >= NT) break;
+                    const uint16_t *xrow = xt + col_ch[j] * PPS + col_off[j];
+                    uint32_t u[4];
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        u[h] = (uint32_t)xrow[cq[2 * h]] | ((uint32_t)xrow[cq[2 * h + 1]] << 16);
+                    const bf16x8 bfr = as_bf16x8(uint4{u[0], u[1], u[2], u[3]});
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[mt][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[mt], bfr, acc[mt][j], 0, 0, 0);
+                }
             }
         }
     }
@@ -1868,7 +1906,8 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const uint16_t *__restrict__
     for (int j = 0; j < NTW; ++j) {
         const int col = (wave * NTW + j) * 16 + row;
         if (wave * NTW + j >= NT || col >= NCOL) continue;
-        const int t = col / CIN, i = col % CIN;
+        // 64 channels: tile j of wave w is tap j, channels 16 w + row
+        const int t = CIN == 64 ? j : col / CIN, i = CIN == 64 ? wave * 16 + row : col % CIN;
         if (i >= CR) continue;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt)

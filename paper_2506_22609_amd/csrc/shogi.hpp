@@ -730,7 +730,7 @@ struct ShogiLaunch {
     static constexpr GameOps ops()
     {
         return GameOps{Shogi::KIND, Shogi::H, Shogi::W, Shogi::CELLS, Shogi::A, &init, &mask, &step, &random_step,
-                       &policy_step, &playout, &persist, 0, nullptr, -1};
+                       &policy_step, &playout, &persist, 0, nullptr, -1, -1};
     }
 };
 

@@ -26,7 +26,8 @@ EXPORTS = ("ludax_game_create", "ludax_game_destroy", "ludax_game_info", "ludax_
            "ludax_playout_batches",
            "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
            "ludax_mixed_set_slots",
-           "ludax_mixed_get_slots", "ludax_mixed_playout", "ludax_mixed_playout_noalloc",
+           "ludax_mixed_get_slots", "ludax_mixed_set_one_grid", "ludax_mixed_get_one_grid",
+           "ludax_mixed_playout", "ludax_mixed_playout_noalloc",
            "ludax_mixed_autotune", "ludax_net_create", "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes",
            "ludax_net_max_batch",
            "ludax_net_pack", "ludax_net_forward", "ludax_net_loss_grad", "ludax_net_adam",
@@ -92,6 +93,8 @@ def _load():
             L.ludax_mixed_destroy.argtypes = [vp]
             L.ludax_mixed_set_slots.argtypes = [vp, vp]
             L.ludax_mixed_get_slots.argtypes = [vp, vp]
+            L.ludax_mixed_set_one_grid.argtypes = [vp, i32]
+            L.ludax_mixed_get_one_grid.argtypes = [vp, P(i32)]
             L.ludax_mixed_playout.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp, vp]
             L.ludax_mixed_playout_noalloc.argtypes = [vp, ctypes.c_uint64, i64, i64, vp, vp, vp, vp, vp]
             L.ludax_mixed_autotune.argtypes = [vp, ctypes.c_uint64, i64, i64, i32, vp, vp, vp, vp, vp,
@@ -117,9 +120,10 @@ def _load():
             L.ludax_last_device_error.restype = ctypes.c_char_p
             for name in ("ludax_game_create", "ludax_game_destroy", "ludax_game_info",
                          "ludax_init", "ludax_legal_mask", "ludax_step", "ludax_random_step",
-                         "ludax_policy_step", "ludax_playout",
+                         "ludax_policy_step", "ludax_playout", "ludax_playout_batches",
                          "ludax_state_stats", "ludax_aux_sync", "ludax_mixed_create", "ludax_mixed_destroy",
-                         "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_playout",
+                         "ludax_mixed_set_slots", "ludax_mixed_get_slots", "ludax_mixed_set_one_grid",
+                         "ludax_mixed_get_one_grid", "ludax_mixed_playout",
                          "ludax_mixed_playout_noalloc", "ludax_mixed_autotune", "ludax_net_create",
                          "ludax_net_destroy", "ludax_net_info", "ludax_net_workspace_bytes", "ludax_net_max_batch",
                          "ludax_net_pack",
@@ -479,6 +483,16 @@ class Mixed:
         out = (ctypes.c_int32 * self.n_kinds)()
         _check(_load().ludax_mixed_get_slots(self._h, out), "ludax_mixed_get_slots")
         return list(out)
+
+    @property
+    def one_grid(self) -> bool:
+        v = ctypes.c_int32()
+        _check(_load().ludax_mixed_get_one_grid(self._h, ctypes.byref(v)), "ludax_mixed_get_one_grid")
+        return bool(v.value)
+
+    @one_grid.setter
+    def one_grid(self, value: bool):
+        _check(_load().ludax_mixed_set_one_grid(self._h, 1 if value else 0), "ludax_mixed_set_one_grid")
 
     @slots.setter
     def slots(self, values):

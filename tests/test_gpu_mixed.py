@@ -43,22 +43,26 @@ def oracle_batch(kinds, seed, id_base, n_games, max_plies=0):
     return winner, plies, last, stats
 
 
-def run_mixed(kinds, seed, id_base, n_games, slots, max_plies=0):
+def run_mixed(kinds, seed, id_base, n_games, slots, max_plies=0, one_grid=None):
     games = [ludax.Game(kind, r, c, max_plies) for kind, r, c in kinds]
     m = ludax.Mixed(games)
     m.slots = slots
+    if one_grid is not None:
+        m.one_grid = one_grid
     out, stats = m.playout(seed, id_base, n_games)
     torch.cuda.synchronize()
     return out, stats, (m, games)
 
 
+@pytest.mark.parametrize("one_grid", [True, False], ids=["one_grid", "streams"])
 @pytest.mark.parametrize("id_base,n_games,slots", [
     (0, 4096, [128, 128, 64, 64]),
     (7, 3001, [64, 192, 128, 256]),
     (1 << 40, 777, [4096, 4096, 4096, 4096]),
 ])
-def test_mixed_matches_oracle(id_base, n_games, slots):
-    out, stats, _ = run_mixed(MIX4, 3, id_base, n_games, slots)
+def test_mixed_matches_oracle(id_base, n_games, slots, one_grid):
+    out, stats, (m, _) = run_mixed(MIX4, 3, id_base, n_games, slots, one_grid=one_grid)
+    assert m.one_grid == one_grid
     w, p, l, st = oracle_batch(MIX4, 3, id_base, n_games)
     assert np.array_equal(out.winner.cpu().numpy(), w)
     assert np.array_equal(out.plies.cpu().numpy(), p)
@@ -67,8 +71,13 @@ def test_mixed_matches_oracle(id_base, n_games, slots):
 
 
 def test_mixed_other_kinds_and_truncation():
+    """Kinds outside the one-grid kernel: a kernel per kind, and asking for
+    one grid is refused."""
     kinds = [(ref.TICTACTOE, 3, 3), (ref.HEX, 5, 5), (ref.GOMOKU, 7, 7)]
-    out, stats, _ = run_mixed(kinds, 11, 5, 2000, [64, 128, 64], max_plies=20)
+    out, stats, (m, _) = run_mixed(kinds, 11, 5, 2000, [64, 128, 64], max_plies=20)
+    assert not m.one_grid
+    with pytest.raises(ludax.LudaxError):
+        m.one_grid = True
     w, p, l, st = oracle_batch(kinds, 11, 5, 2000, max_plies=20)
     assert np.array_equal(out.winner.cpu().numpy(), w)
     assert np.array_equal(out.plies.cpu().numpy(), p)
@@ -91,13 +100,15 @@ def test_mixed_single_kind_equals_plain_playout():
     assert torch.equal(stats[0], pst)
 
 
-def test_mixed_graph_replay():
-    """The whole call (counter reset, fork to the kinds' streams, join,
-    counters) captured once and replayed; every replay equals the eager
-    result."""
+@pytest.mark.parametrize("one_grid", [True, False], ids=["one_grid", "streams"])
+def test_mixed_graph_replay(one_grid):
+    """The whole call (counter reset, the kinds' kernels -- one grid, or
+    forked to the kinds' streams and joined -- and the counters) captured
+    once and replayed; every replay equals the eager result."""
     games = [ludax.Game(kind, r, c) for kind, r, c in MIX4]
     m = ludax.Mixed(games)
     m.slots = [256, 256, 128, 128]
+    m.one_grid = one_grid
     n = 2048
     ref_out, ref_stats = m.playout(9, 0, n)
     torch.cuda.synchronize()

@@ -23,10 +23,12 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_noalloc_equals_workspace_playout_twice():
+@pytest.mark.parametrize("one_grid", [True, False], ids=["one_grid", "streams"])
+def test_noalloc_equals_workspace_playout_twice(one_grid):
     games = [ludax.Game(kind, r, c) for kind, r, c in MIX4]
     m = ludax.Mixed(games)
     m.slots = [256, 256, 128, 128]
+    m.one_grid = one_grid
     for seed, id_base, n_games in ((5, 0, 20000), (6, 12345, 3001)):
         print(f"noalloc: seed {seed} id_base {id_base} n_games {n_games}", flush=True)
         ref_out, ref_stats = m.playout(seed, id_base, n_games)
