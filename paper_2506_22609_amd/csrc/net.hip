@@ -53,6 +53,24 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// Two floats to bf16 by the hardware conversion (v_cvt_pk_bf16_f32: round
+// to nearest, ties to even, as f2bf; one instruction for the pair where
+// f2bf takes four per value), lo in the low half.
+typedef __bf16 bf16x2_v __attribute__((ext_vector_type(2)));
+typedef float f32x2_v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_v){lo, hi}, bf16x2_v));
+}
+// y = bf16(relu(a)), bf16(relu(b)) as floats: a layer's output as the next
+// layer reads it
+__device__ __forceinline__ void relu_bf16_pair(float a, float b, float &ya, float &yb)
+{
+    const uint32_t p = pack_bf16(fmaxf(a, 0.f), fmaxf(b, 0.f));
+    ya = __uint_as_float(p << 16);
+    yb = __uint_as_float(p & 0xFFFF0000u);
+}
+
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 // pointers of the memory-to-LDS load builtin
@@ -214,7 +232,7 @@ __device__ __forceinline__ void store_cell(const f32x4 (&acc)[NTW], const uint16
         uint32_t w[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            w[j] = (uint32_t)f2bf(v[8 * q + 2 * j]) | ((uint32_t)f2bf(v[8 * q + 2 * j + 1]) << 16);
+            w[j] = pack_bf16(v[8 * q + 2 * j], v[8 * q + 2 * j + 1]);
         reinterpret_cast<uint4 *>(orow)[q] = uint4{w[0], w[1], w[2], w[3]};
     }
 }
@@ -560,8 +578,8 @@ __device__ __forceinline__ void layer1_half(const FwdArgs &a1, int h, int64_t b0
         }
         if (p < PIX) { // channels co + 4 quad + k, k < 4, of cell p
             const int q = (p / N + 1) * NP + p % N + 1, c = co - 32 * h + 4 * quad;
-            const uint2 o = {(uint32_t)f2bf(fmaxf(acc[0], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[1], 0.f)) << 16),
-                             (uint32_t)f2bf(fmaxf(acc[2], 0.f)) | ((uint32_t)f2bf(fmaxf(acc[3], 0.f)) << 16)};
+            const uint2 o = {pack_bf16(fmaxf(acc[0], 0.f), fmaxf(acc[1], 0.f)),
+                             pack_bf16(fmaxf(acc[2], 0.f), fmaxf(acc[3], 0.f))};
             *reinterpret_cast<uint2 *>(xs + (bb * PP + q) * 32 + (((c >> 3) + (q >> 2)) & 3) * 8 + (c & 7)) = o;
         }
     }
@@ -597,10 +615,13 @@ __device__ __forceinline__ void heads_epilogue(const f32x4 (&acc)[8][NTW], const
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
-                lp += y * wp[4 * nt + k];
-                lv += y * wv[4 * nt + k];
+            for (int k = 0; k < 4; k += 2) {
+                float y0, y1;
+                relu_bf16_pair(acc[mt][nt][k], acc[mt][nt][k + 1], y0, y1);
+                lp += y0 * wp[4 * nt + k];
+                lv += y0 * wv[4 * nt + k];
+                lp += y1 * wp[4 * nt + k + 1];
+                lv += y1 * wv[4 * nt + k + 1];
             }
         // the four quads hold the four 16-channel parts of the same cell
         lp += __shfl_xor(lp, 16);
@@ -643,7 +664,12 @@ __device__ __forceinline__ void heads_to_lds(const f32x4 (&acc)[8][NTW], const i
 #pragma unroll
         for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) lp += bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f))) * wp[4 * nt + k];
+            for (int k = 0; k < 4; k += 2) {
+                float y0, y1;
+                relu_bf16_pair(acc[mt][nt][k], acc[mt][nt][k + 1], y0, y1);
+                lp += y0 * wp[4 * nt + k];
+                lp += y1 * wp[4 * nt + k + 1];
+            }
         lp += __shfl_xor(lp, 16);
         lp += __shfl_xor(lp, 32);
         if (valid && quad == 0) {
@@ -1151,7 +1177,7 @@ __global__ __launch_bounds__(512, 1) void k_fwd11(FusedArgs fa)
                                     const int i0 = 8 * k8 + 2 * j, i1 = i0 + 1;
                                     const float v0 = fmaxf(acc[mt][i0 >> 2][i0 & 3], 0.f);
                                     const float v1 = fmaxf(acc[mt][i1 >> 2][i1 & 3], 0.f);
-                                    wv[j] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+                                    wv[j] = pack_bf16(v0, v1);
                                 }
                                 const int c8 = 2 * (quad & 1) + k8;
                                 *reinterpret_cast<uint4 *>(xo + q * 32 + ((c8 + (q >> 2)) & 3) * 8) =
@@ -1181,10 +1207,13 @@ __global__ __launch_bounds__(512, 1) void k_fwd11(FusedArgs fa)
 #pragma unroll
                     for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
-                            lp += y * wp[4 * nt + k];
-                            lv += y * wv[4 * nt + k];
+                        for (int k = 0; k < 4; k += 2) {
+                            float y0, y1;
+                            relu_bf16_pair(acc[mt][nt][k], acc[mt][nt][k + 1], y0, y1);
+                            lp += y0 * wp[4 * nt + k];
+                            lv += y0 * wv[4 * nt + k];
+                            lp += y1 * wp[4 * nt + k + 1];
+                            lv += y1 * wv[4 * nt + k + 1];
                         }
                     lp += __shfl_xor(lp, 16);
                     lp += __shfl_xor(lp, 32);
@@ -1453,10 +1482,13 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
 #pragma unroll
                 for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float y = bf2f(f2bf(fmaxf(acc[mt][nt][k], 0.f)));
-                        lp += y * hw[c0 + 4 * nt + k];
-                        lv += y * hw[C + c0 + 4 * nt + k];
+                    for (int k = 0; k < 4; k += 2) {
+                        float y0, y1;
+                        relu_bf16_pair(acc[mt][nt][k], acc[mt][nt][k + 1], y0, y1);
+                        lp += y0 * hw[c0 + 4 * nt + k];
+                        lv += y0 * hw[C + c0 + 4 * nt + k];
+                        lp += y1 * hw[c0 + 4 * nt + k + 1];
+                        lv += y1 * hw[C + c0 + 4 * nt + k + 1];
                     }
                 lp += __shfl_xor(lp, 16); // the four quads: the same cell
                 lp += __shfl_xor(lp, 32);
@@ -1649,7 +1681,7 @@ __global__ __launch_bounds__(256) void k_heads_bwd(const uint16_t *__restrict__ 
             const uint16_t y0 = (uint16_t)(wd[h] & 0xFFFFu), y1 = (uint16_t)(wd[h] >> 16);
             const float g0 = (y0 != 0 && (y0 & 0x8000u) == 0) ? d * wp8[2 * h] + dv * wv8[2 * h] : 0.f;
             const float g1 = (y1 != 0 && (y1 & 0x8000u) == 0) ? d * wp8[2 * h + 1] + dv * wv8[2 * h + 1] : 0.f;
-            od[h] = (uint32_t)f2bf(g0) | ((uint32_t)f2bf(g1) << 16);
+            od[h] = pack_bf16(g0, g1);
         }
         *reinterpret_cast<uint4 *>(gb + o) = uint4{od[0], od[1], od[2], od[3]};
     }
