@@ -848,6 +848,35 @@ def _hbm_probe(seed: int):
     print(json.dumps({"hbm_probe": out}), flush=True)
 
 
+def _net_probe(seed: int):
+    """A short fixed sequence of the 11x11 network kernels for counter runs
+    (rocprofv3 --pmc): twice the forward over 65536 mid-game Hex positions
+    (the three-kernel forward, and the one-kernel forward of
+    ludax_net_guided_playout with no plies), then 5 training steps at batch
+    4096 on random-play samples."""
+    import torch
+    from paper_2506_22609_amd import learn, ludax
+    from paper_2506_22609_amd import workloads as W
+    from paper_2506_22609_amd.workloads import init_net_params
+
+    g = ludax.Game(W.HEX, 11, 11)
+    net = ludax.Net(11, 11, params=torch.from_numpy(init_net_params(seed)).cuda())
+    n = 65536
+    s = ludax.State(g, n)
+    ludax.init(g, s)
+    r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
+    t = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for _ in range(30):
+        ludax.random_step(g, s, seed + 2, 0, reward=r, terminal=t)
+    for _ in range(2):
+        net.forward(s.board, s.to_move)
+        net.guided_playout(g, s.clone(), 0, seed + 4, 0)
+    data = learn.collect(g, 2000, seed=seed + 3, id_base=0)
+    learn.train(net, data, 5, batch=4096)
+    torch.cuda.synchronize()
+    print(json.dumps({"net_probe": {"positions": n, "train_steps": 5, "batch": 4096}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -878,6 +907,8 @@ def main():
                          "(a known-size reference for HBM byte counters under a profiler)")
     ap.add_argument("--hbm-probe", action="store_true",
                     help="run only the short fixed sequence for hardware-counter runs and print its env-steps")
+    ap.add_argument("--net-probe", action="store_true",
+                    help="run only a short fixed sequence of the network kernels for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} asked for more): the playouts are independent "
@@ -895,6 +926,9 @@ def main():
     torch.cuda.set_device(0)
     if args.hbm_probe:
         _hbm_probe(args.seed)
+        return
+    if args.net_probe:
+        _net_probe(args.seed)
         return
     batches = W.BENCH_BATCHES
     games = [ludax.Game(b.kind, b.rows, b.cols) for b in batches]
