@@ -56,6 +56,15 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 GROUP_TRAFFIC_BYTES = 12.52e6
 HBM_PEAK_GBS = 8000.0
 EVENT_EVERY = 8
+# What the paper states about its own throughput (Sec. 6, Fig. 2): no
+# absolute rate in the text (the figure is a plot), so vs_baseline is null.
+PAPER_CONTEXT = {
+    "absolute_env_steps_per_s": None,
+    "figure": "Fig. 2: moves per second against batch size for 10 games (plot only)",
+    "hardware": "one NVIDIA RTX 4090 (Ludax, PGX); Intel i9-9980XE, 18 cores / 36 threads (Ludii)",
+    "protocol": "100 warm-up full-game episodes, then 500 measured, per batch size; std over episodes",
+    "speedup_over_ludii": "about 3x (English Draughts) to about 450x (Hex), tensor playout regime",
+}
 # DRAM bytes (read + written) per env-step of the per-ply loop, from the
 # FETCH_SIZE / WRITE_SIZE counters of every ludax_random_step dispatch of one
 # loop, each scaled by what the counter reads for a 1 GiB device copy in the
@@ -1015,6 +1024,7 @@ def main():
                    "envs_per_batch": batches[0].n, "seed": args.seed, "per_game": per},
         "roofline": roofline,
     }
+    out["paper_context"] = PAPER_CONTEXT
     out["protocol"] = _protocol(batches, games, states, rewards, terms)
     out["separate_launches"] = _separate_launches(batches, games, states, rewards, terms, args.seed)
     sec = set(x for x in args.sections.split(",") if x)
