@@ -197,6 +197,9 @@ def test_mixed_argument_checks_need_no_gpu():
     assert L.ludax_mixed_destroy(None) == ludax.E_INVALID
     assert L.ludax_mixed_set_slots(None, None) == ludax.E_INVALID
     assert L.ludax_mixed_get_slots(None, None) == ludax.E_INVALID
+    assert L.ludax_mixed_set_one_grid(None, 1) == ludax.E_INVALID
+    v = ctypes.c_int32()
+    assert L.ludax_mixed_get_one_grid(None, ctypes.byref(v)) == ludax.E_INVALID
     assert L.ludax_mixed_playout(None, 1, 0, 10, 16, 16, 16, None, 16, None) == ludax.E_INVALID
     L.ludax_game_destroy(h)
 
