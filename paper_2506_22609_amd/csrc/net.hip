@@ -1250,13 +1250,15 @@ __global__ __launch_bounds__(512, 1) void k_fwd11(FusedArgs fa)
                     fa.estimate[b] = stt == 1 ? (wn == 1 ? 1.f : (wn == 2 ? -1.f : 0.f))
                                               : (stt == 0 ? (me == 1 ? v : -v) : 0.f);
                 }
-            } else if (live && g == 0) {
-                const uint64_t id = (uint64_t)(fa.gid != nullptr ? fa.gid[b] : fa.gid_base + b);
+            } else if (wave < BPB && b0 + wave < n) {
+                // board `wave`'s ply by wave `wave`: the four plies on four SIMDs
+                const int64_t bp = b0 + wave;
+                const uint64_t id = (uint64_t)(fa.gid != nullptr ? fa.gid[bp] : fa.gid_base + bp);
                 if (fa.kind == 3)
-                    lds_policy_ply<Hex<N>>(scal[slot], id, fa.max_plies, lgs + slot * 128, brow[slot], fa.key0,
+                    lds_policy_ply<Hex<N>>(scal[wave], id, fa.max_plies, lgs + wave * 128, brow[wave], fa.key0,
                                            fa.key1);
                 else
-                    lds_policy_ply<Gomoku<N>>(scal[slot], id, fa.max_plies, lgs + slot * 128, brow[slot], fa.key0,
+                    lds_policy_ply<Gomoku<N>>(scal[wave], id, fa.max_plies, lgs + wave * 128, brow[wave], fa.key0,
                                               fa.key1);
             }
         }

@@ -161,3 +161,36 @@ def test_batch_group_handle_repeats_the_call():
         for k in range(len(kinds)):
             assert_same_state(from_device(a[k]), from_device(b[k]), f"call {call} batch {k}")
             assert torch.equal(ref_out[k][0], grp.outputs[k][0]) and torch.equal(ref_out[k][2], st[k])
+
+
+def test_batch_group_graph_replay():
+    """The whole call (group kernel and counters) captured once and replayed:
+    every replay equals the eager call with the same game ids."""
+    kinds, ns = (C4, HEX), (1000, 777)
+    dg = [pair(k, *SIZES[k])[1] for k in kinds]
+    a = [ludax.State(g, n) for g, n in zip(dg, ns)]
+    ref_out = _run_group(dg, a, [5, 6], 21, True)
+    torch.cuda.synchronize()
+    b = [ludax.State(g, n) for g, n in zip(dg, ns)]
+    st = [torch.zeros(4, dtype=torch.int64, device="cuda") for _ in kinds]
+    grp = ludax.BatchGroup([(g, s, None, None, x) for g, s, x in zip(dg, b, st)])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        grp.run(21, [5, 6], from_start=True, stream=side)  # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        grp.run(21, [5, 6], from_start=True)
+    for rep in range(3):
+        for x in st:
+            x.zero_()
+        for s in b:
+            s.board.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in range(len(kinds)):
+            assert_same_state(from_device(a[k]), from_device(b[k]), f"replay {rep} batch {k}")
+            assert torch.equal(ref_out[k][2], st[k]), rep
