@@ -776,12 +776,16 @@ def _learned_section(seed: int, train_games: int, steps: int):
     out["methods"]["policy20_value_cutoff"] = dict(out["methods"][best], path=best)
     # at a fixed value error: the number of averaged full random playouts
     # that matches the value's squared error, measured
-    vm = out["methods"]["value_only"]
+    # the faster of the two value paths (three kernels through memory, or
+    # the one-kernel forward): the same network, the estimates equal to
+    # float32 rounding order
+    vpath = max(("value_only", "value_only_one_kernel"), key=lambda k: out["methods"][k]["playouts_per_s"])
+    vm = out["methods"][vpath]
     k, mse_k, pps = _averaged_playouts_at_error(g, held, tr, vm["mse_vs_256_playout_mean"], base, seed + 800,
                                                 7 * 10**9)
     out["fixed_value_error"] = {"mse": vm["mse_vs_256_playout_mean"], "plain_playouts_averaged": k,
                                 "plain_average_mse": mse_k, "plain_positions_per_s": pps,
-                                "guided_positions_per_s": vm["playouts_per_s"],
+                                "guided_positions_per_s": vm["playouts_per_s"], "value_path": vpath,
                                 "note": "k measured: the smallest number of averaged full random playouts "
                                         "whose squared error is no larger than the value's"}
     # the value forward alone, as a fraction of the bf16 MFMA peak
