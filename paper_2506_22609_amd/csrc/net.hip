@@ -2467,11 +2467,14 @@ hipError_t net_pack(const float *params, void *packed, hipStream_t s)
     return hipGetLastError();
 }
 
+// 11x11: the one-kernel forward (activations on chip; the same products in
+// the same order as the three-kernel forward, so the same logits and
+// values); 19x19: the three kernels with the weights resident.
 hipError_t net_forward(int N, const float *params, const void *packed, const int8_t *board, const int8_t *to_move,
                        int64_t n, float *logits, float *value, void *ws, hipStream_t s)
 {
     const uint16_t *pk = static_cast<const uint16_t *>(packed);
-    return N == 11 ? net::forward_t<11>(params, pk, board, to_move, n, logits, value, ws, s)
+    return N == 11 ? net::forward_fused11(params, pk, board, to_move, n, logits, value, s)
                    : net::forward_t<19>(params, pk, board, to_move, n, logits, value, ws, s);
 }
 
@@ -2517,6 +2520,9 @@ hipError_t net_guided_playout(const float *params, const void *packed, const Dev
 hipError_t net_estimate(int N, const float *params, const void *packed, const DevState &st, int64_t n,
                         float *estimate, void *ws, hipStream_t s)
 {
+    // 11x11: the guided playout kernel with no plies (value cutoff only,
+    // nothing but the estimates written)
+    if (N == 11) return net_guided_playout(params, packed, st, 3, n, 1, 0, 0, 0, nullptr, estimate, s);
     const int64_t f = N == 11 ? net::Sizes<11>::forward_ws(n) : net::Sizes<19>::forward_ws(n);
     float *logits = reinterpret_cast<float *>(static_cast<char *>(ws) + f);
     float *value = reinterpret_cast<float *>(static_cast<char *>(ws) + f + net::align256(n * N * N * 4));
