@@ -864,9 +864,8 @@ def _hbm_probe(seed: int):
 def _net_probe(seed: int):
     """A short fixed sequence of the 11x11 network kernels for counter runs
     (rocprofv3 --pmc): twice the forward over 65536 mid-game Hex positions
-    (the three-kernel forward, and the one-kernel forward of
-    ludax_net_guided_playout with no plies), then 5 training steps at batch
-    4096 on random-play samples."""
+    (ludax_net_forward, and ludax_net_guided_playout with no plies), then 5
+    training steps at batch 4096 on random-play samples."""
     import torch
     from paper_2506_22609_amd import learn, ludax
     from paper_2506_22609_amd import workloads as W
