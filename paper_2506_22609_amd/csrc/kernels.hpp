@@ -817,19 +817,63 @@ __global__ __launch_bounds__(BLOCK) void k_playout(DevState st, int64_t n, int m
 }
 
 // ---------------------------------------------------------------------------
+// A block's move list in LDS: the internal bit index of window ply j of
+// lane t.  Boards up to 256 bits: one byte per ply, at [j * BLOCK + t].
+// Larger boards (Hex 17 .. 19): the low byte there, and the ninth bit in a
+// word array behind it, word (j / 32) of lane t at [(j / 32) * BLOCK + t]
+// (the lanes of a word row are consecutive: no bank conflicts), cleared per
+// window and set with LDS atomics.  Two bytes per ply would take 46 KB at
+// 19x19, three blocks (waves) per CU; this takes 26 KB, six.
+// ---------------------------------------------------------------------------
+template <class G>
+struct Moves {
+    static constexpr bool WIDE = G::NBITS > 256;
+    static constexpr int HW = (G::CELLS + 31) / 32; // ninth-bit words per lane
+    static constexpr int BYTES = BLOCK * G::CELLS + (WIDE ? BLOCK * HW * 4 : 0);
+    int8_t *base;
+    __device__ __forceinline__ uint8_t *lo() const { return reinterpret_cast<uint8_t *>(base); }
+    __device__ __forceinline__ uint32_t *hi() const
+    {
+        return reinterpret_cast<uint32_t *>(base + BLOCK * G::CELLS);
+    }
+    __device__ __forceinline__ void clear(int t) const
+    {
+        if constexpr (WIDE) {
+#pragma unroll
+            for (int q = 0; q < HW; ++q) hi()[q * BLOCK + t] = 0u;
+        }
+    }
+    __device__ __forceinline__ void put(int j, int t, int b) const
+    {
+        lo()[j * BLOCK + t] = (uint8_t)b;
+        if constexpr (WIDE) {
+            if (b & 256)
+                __hip_atomic_fetch_or(&hi()[(j >> 5) * BLOCK + t], 1u << (j & 31), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __device__ __forceinline__ int get(int j, int t) const
+    {
+        int b = lo()[j * BLOCK + t];
+        if constexpr (WIDE) b |= (int)((hi()[(j >> 5) * BLOCK + t] >> (j & 31)) & 1u) << 8;
+        return b;
+    }
+};
+
+// ---------------------------------------------------------------------------
 // The random sequence of a window of T plies, without any end test: ply j
 // (from ply0) is played by the owner of `cur` for even j and of `oth` for
 // odd j, on a uniformly drawn cell of G::open_cells, and its internal bit is
-// recorded in moves[j * BLOCK + lane].  One Philox block serves the plies
+// recorded in the move list (Moves).  One Philox block serves the plies
 // 4q .. 4q+3; the window is cut into a head (up to the next multiple of
 // four), whole blocks of four plies and a tail, so that no ply tests
 // whether it needs a new block.  On return cur / oth again hold the stones
 // of the player who moved first / second.
 // ---------------------------------------------------------------------------
-template <class G, class E>
+template <class G>
 __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &oth, int T, int ply0,
                                             uint32_t id_lo, uint32_t id_hi, uint32_t key0, uint32_t key1,
-                                            E *moves, int t)
+                                            const Moves<G> &moves, int t)
 {
     using M = typename G::M;
     // The legal set and its size are carried from ply to ply (the chosen
@@ -846,13 +890,14 @@ __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &o
         open = G::open_cells(cur, oth);
         n_open = popcount(open);
     }
+    moves.clear(t);
     auto play = [&](M &mine, const M &theirs, int j, uint32_t w) {
         if constexpr (CARRY) {
             int wi;
             uint32_t bit;
             select_bit_split(open, (int)__umulhi(w, (uint32_t)n_open), wi, bit);
             const int b = 32 * wi + __builtin_ctz(bit);
-            moves[j * BLOCK + t] = (E)b;
+            moves.put(j, t, b);
             static_for<G::NWI>([&](auto I) {
                 constexpr int i = I;
                 const uint32_t x = wi == i ? bit : 0u;
@@ -871,7 +916,7 @@ __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &o
             }
         } else {
             const int b = select_uniform(G::open_cells(mine, theirs), w);
-            moves[j * BLOCK + t] = (E)b;
+            moves.put(j, t, b);
             mine = mine | onehot<G::NWI>(b);
         }
     };
@@ -945,9 +990,6 @@ struct Window {
     int winner, me, ply, last;
 };
 
-// Move-list entry type: internal bit indices of boards up to 256 bits fit a byte.
-template <class G>
-using MoveT = typename std::conditional<(G::NBITS <= 256), uint8_t, uint16_t>::type;
 
 // Play and resolve one window from stones b1 / b2, player me0 to move at
 // ply0.  Only meaningful for run == true (otherwise T = 0 and nothing is
@@ -956,7 +998,7 @@ template <class G>
 __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const typename G::M &b2,
                                                  bool run, int me0, int ply0, int max_plies,
                                                  uint32_t id_lo, uint32_t id_hi, uint32_t key0,
-                                                 uint32_t key1, MoveT<G> *moves, int t)
+                                                 uint32_t key1, const Moves<G> &moves, int t)
 {
     using M = typename G::M;
     constexpr int NW = G::NWI;
@@ -988,7 +1030,7 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 M s = s_lo;
-                for (int k = next; k <= mid; ++k) s = s | onehot<NW>((int)moves[(jw0 + 2 * (k - 1)) * BLOCK + t]);
+                for (int k = next; k <= mid; ++k) s = s | onehot<NW>(moves.get(jw0 + 2 * (k - 1), t));
                 M r = r_lo | G::first_side(s, W);
                 if (G::flood_to_far(r, s, W)) {
                     hi = mid;
@@ -1009,7 +1051,7 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
                 const int mid = (lo + hi) >> 1;
                 M a1 = s1, a2 = s2;
                 for (int j = next; j <= mid; ++j) {
-                    const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+                    const M x = onehot<NW>(moves.get(j, t));
                     const bool p1 = ((j & 1) == 0) == (me0 == 1);
                     a1 = pick(p1, a1 | x, a1);
                     a2 = pick(p1, a2, a2 | x);
@@ -1033,7 +1075,7 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
     w.f1 = end1;
     w.f2 = end2;
     for (int j = played; j < T; ++j) { // take back the plies after the end
-        const M x = onehot<NW>((int)moves[j * BLOCK + t]);
+        const M x = onehot<NW>(moves.get(j, t));
         const bool p1 = ((j & 1) == 0) == (me0 == 1);
         w.f1 = pick(p1, andnot(w.f1, x), w.f1);
         w.f2 = pick(p1, w.f2, andnot(w.f2, x));
@@ -1045,7 +1087,7 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
     if (T == 0) {
         w.status = ILLEGAL; // RUNNING with no legal cell: only a hand-edited board
     } else {
-        w.last = G::action_of((int)moves[(played - 1) * BLOCK + t]);
+        w.last = G::action_of(moves.get(played - 1, t));
         const int mover = ((played - 1) & 1) == 0 ? me0 : 3 - me0; // of the last ply
         if (jstar >= 0) {
             w.status = TERMINAL;
@@ -1069,7 +1111,7 @@ template <class G>
 constexpr int fill_lds_bytes()
 {
     constexpr int STAGE = BLOCK * G::CELLS;
-    constexpr int LIST = BLOCK * G::CELLS * (int)sizeof(MoveT<G>);
+    constexpr int LIST = Moves<G>::BYTES;
     return (STAGE > LIST ? STAGE : LIST) + STAGE_SLACK;
 }
 
@@ -1085,8 +1127,7 @@ __device__ __forceinline__ void playout_fill_block(const DevState &st, int64_t n
                                                    int64_t blk, int8_t *lds)
 {
     using M = typename G::M;
-    using E = MoveT<G>;
-    E *moves = reinterpret_cast<E *>(lds); // moves[j * BLOCK + lane]: internal bit of window ply j
+    const Moves<G> moves{lds}; // the move list over the staging area
 
     const int64_t e0 = blk * BLOCK;
     const int nb = (int)(n - e0 < BLOCK ? n - e0 : BLOCK);
@@ -1415,11 +1456,12 @@ __global__ __launch_bounds__(BLOCK) void k_persist_lane(MixedArgs a)
 // a chunk fills the same number of plies from the start position, so the
 // 64 lanes of a wave play 64 games in lockstep and then take the next chunk.
 template <class G>
-__device__ __forceinline__ void persist_fill_body(const MixedArgs &a, MoveT<G> *moves)
+__device__ __forceinline__ void persist_fill_body(const MixedArgs &a, int8_t *lds)
 {
     using M = typename G::M;
     const int t = threadIdx.x;
     const M zero = bb_zero<G::NWI>();
+    const Moves<G> moves{lds};
     for (;;) {
         const int64_t c = next_chunk(a.counter) * BLOCK;
         if (c >= a.count) break;
@@ -1441,8 +1483,8 @@ __device__ __forceinline__ void persist_fill_body(const MixedArgs &a, MoveT<G> *
 template <class G>
 __global__ __launch_bounds__(BLOCK) void k_persist_fill(MixedArgs a)
 {
-    __shared__ __align__(16) MoveT<G> moves[BLOCK * G::CELLS];
-    persist_fill_body<G>(a, moves);
+    __shared__ __align__(16) int8_t lds[Moves<G>::BYTES];
+    persist_fill_body<G>(a, lds);
 }
 
 // A mixed batch in one grid: the kinds' persistent loops side by side in
@@ -1456,7 +1498,7 @@ struct PersistGames {
     template <class G>
     static constexpr int lds_of()
     {
-        return (G::KIND == 1 || G::KIND == 2 || G::KIND == 3) ? BLOCK * G::CELLS * (int)sizeof(MoveT<G>) : 0;
+        return (G::KIND == 1 || G::KIND == 2 || G::KIND == 3) ? Moves<G>::BYTES : 0;
     }
     static constexpr int LDS = [] {
         int m = 16;
@@ -1483,7 +1525,7 @@ __device__ __forceinline__ void persist_group_body(const MixedArgs &a, int slot,
 {
     if (slot == I) {
         if constexpr (G::KIND == 1 || G::KIND == 2 || G::KIND == 3)
-            persist_fill_body<G>(a, reinterpret_cast<MoveT<G> *>(lds));
+            persist_fill_body<G>(a, lds);
         else
             persist_ply_body<G>(a);
     } else if constexpr (sizeof...(Rest) > 0) {
