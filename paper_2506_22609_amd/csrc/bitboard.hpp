@@ -214,15 +214,28 @@ __device__ __forceinline__ BB<NW> shift(const BB<NW> &x)
     else return shr<-S>(x);
 }
 
+// Word i of a bitboard picked by a per-lane word index q without a compare
+// (whose lane mask in a scalar register costs wait states before the
+// select that reads it): sel = word_sel(q) has bit q set, and
+// word_mask(sel, i) sign-extends bit i of it, all ones in word q and zero
+// elsewhere.  A q outside [0, 31) selects no word of a board of fewer
+// than 31 words.
+__device__ __forceinline__ int word_sel(int q) { return (int)(1u << (q & 31)); }
+__device__ __forceinline__ uint32_t word_mask(int sel, int i)
+{
+    return (uint32_t)__builtin_amdgcn_sbfe(sel, (unsigned)i, 1u);
+}
+
 // Bitboard with only bit b set (b in range).
 template <int NW>
 __device__ __forceinline__ BB<NW> onehot(int b)
 {
+    static_assert(NW < 32, "the word selector is a 32-bit mask");
     BB<NW> r;
     const uint32_t bit = 1u << (b & 31);
-    const int q = b >> 5;
+    const int sel = word_sel(b >> 5);
 #pragma unroll
-    for (int i = 0; i < NW; ++i) r.w[i] = (q == i) ? bit : 0u;
+    for (int i = 0; i < NW; ++i) r.w[i] = bit & word_mask(sel, i);
     return r;
 }
 

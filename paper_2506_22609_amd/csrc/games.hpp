@@ -246,6 +246,15 @@ struct Hex {
     {
         return p == 1 ? any(and_mask<RowL, NBITS, NWI>(x)) : any(and_mask<ColL, NBITS, NWI>(x));
     }
+    // p's first / far side as masks of cells
+    __device__ static M first_mask(int p)
+    {
+        return pick(p == 1, const_mask<Row0, NBITS, NWI>(), const_mask<Col0, NBITS, NWI>());
+    }
+    __device__ static M far_mask(int p)
+    {
+        return pick(p == 1, const_mask<RowL, NBITS, NWI>(), const_mask<ColL, NBITS, NWI>());
+    }
     // do p's stones `x` join p's two sides?
     __device__ static bool joins(const M &x, int p)
     {
@@ -291,6 +300,19 @@ struct Hex {
             const M n2 = dilate(n1) & allowed;
             r = n2;
             if (same(n2, n1) | meets_far_side(n2, p)) return meets_far_side(n2, p);
+        }
+    }
+
+    // flood_to_far with the far side given as a mask (far_mask): the same
+    // rounds without a branch on the player, for lanes of both players
+    __device__ static bool flood_to_far_m(M &r, const M &allowed, const M &far)
+    {
+        for (;;) {
+            const M n1 = dilate(r) & allowed;
+            const M n2 = dilate(n1) & allowed;
+            r = n2;
+            const bool hit = any(n2 & far);
+            if (hit | same(n2, n1)) return hit;
         }
     }
 

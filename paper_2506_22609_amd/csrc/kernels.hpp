@@ -898,9 +898,10 @@ __device__ __forceinline__ void fill_window(typename G::M &cur, typename G::M &o
             select_bit_split(open, (int)__umulhi(w, (uint32_t)n_open), wi, bit);
             const int b = 32 * wi + __builtin_ctz(bit);
             moves.put(j, t, b);
+            const int sel = word_sel(wi);
             static_for<G::NWI>([&](auto I) {
                 constexpr int i = I;
-                const uint32_t x = wi == i ? bit : 0u;
+                const uint32_t x = bit & word_mask(sel, i);
                 mine.w[i] |= x;
                 open.w[i] ^= x;
             });
@@ -1024,15 +1025,26 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
         const int jw0 = W == me0 ? 0 : 1;          // W's first ply in the window
         const int MW = W ? (T - jw0 + 1) >> 1 : 0; // W's moves in the window
         if (MW > 0) {
+            const M first = G::first_mask(W), far = G::far_mask(W);
             M s_lo = pick(W == 1, b1, b2); // W's stones before its lo-th window move
-            M r_lo = G::flood(G::first_side(s_lo, W), s_lo);
+            M r_lo = G::flood(s_lo & first, s_lo);
             int lo = 1, hi = MW, next = 1; // next = first move not yet in s_lo
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 M s = s_lo;
-                for (int k = next; k <= mid; ++k) s = s | onehot<NW>(moves.get(jw0 + 2 * (k - 1), t));
-                M r = r_lo | G::first_side(s, W);
-                if (G::flood_to_far(r, s, W)) {
+                // W's moves next..mid, four list reads in flight at a time
+                // (an index past mid repeats mid's cell)
+                for (int k = next; k <= mid; k += 4) {
+                    int c[4];
+                    static_for<4>([&](auto I) {
+                        constexpr int i = I;
+                        const int kk = k + i < mid ? k + i : mid;
+                        c[i] = moves.get(jw0 + 2 * (kk - 1), t);
+                    });
+                    static_for<4>([&](auto I) { s = s | onehot<NW>(c[I]); });
+                }
+                M r = r_lo | (s & first);
+                if (G::flood_to_far_m(r, s, far)) {
                     hi = mid;
                 } else {
                     lo = mid + 1;
@@ -1050,11 +1062,22 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 M a1 = s1, a2 = s2;
-                for (int j = next; j <= mid; ++j) {
-                    const M x = onehot<NW>(moves.get(j, t));
-                    const bool p1 = ((j & 1) == 0) == (me0 == 1);
-                    a1 = pick(p1, a1 | x, a1);
-                    a2 = pick(p1, a2, a2 | x);
+                // plies next..mid, four list reads in flight at a time (an
+                // index past mid repeats mid's cell, on the same board)
+                for (int j = next; j <= mid; j += 4) {
+                    int c[4], jj[4];
+                    static_for<4>([&](auto I) {
+                        constexpr int i = I;
+                        jj[i] = j + i < mid ? j + i : mid;
+                        c[i] = moves.get(jj[i], t);
+                    });
+                    static_for<4>([&](auto I) {
+                        constexpr int i = I;
+                        const M x = onehot<NW>(c[i]);
+                        const bool p1 = ((jj[i] & 1) == 0) == (me0 == 1);
+                        a1 = pick(p1, a1 | x, a1);
+                        a2 = pick(p1, a2, a2 | x);
+                    });
                 }
                 if (G::line(a1) | G::line(a2)) {
                     hi = mid;
@@ -1072,14 +1095,20 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
     // ---- the final position ----
     Window<G> w;
     const int played = jstar >= 0 ? jstar + 1 : T;
-    w.f1 = end1;
-    w.f2 = end2;
-    for (int j = played; j < T; ++j) { // take back the plies after the end
-        const M x = onehot<NW>(moves.get(j, t));
-        const bool p1 = ((j & 1) == 0) == (me0 == 1);
-        w.f1 = pick(p1, andnot(w.f1, x), w.f1);
-        w.f2 = pick(p1, w.f2, andnot(w.f2, x));
+    // take back the plies after the end: a cell holds one player's stone,
+    // so the cells of those plies leave both boards; four list reads in
+    // flight at a time (an index past the window repeats its last ply)
+    M undo = bb_zero<NW>();
+    for (int j = played; j < T; j += 4) {
+        int c[4];
+        static_for<4>([&](auto I) {
+            constexpr int i = I;
+            c[i] = moves.get(j + i < T - 1 ? j + i : T - 1, t);
+        });
+        static_for<4>([&](auto I) { undo = undo | onehot<NW>(c[I]); });
     }
+    w.f1 = andnot(end1, undo);
+    w.f2 = andnot(end2, undo);
     w.winner = -1;
     w.ply = ply0 + played;
     w.me = me0;
@@ -1286,6 +1315,10 @@ __global__ __launch_bounds__(BLOCK) void k_playout_group(GroupArgs a)
 #pragma unroll
     for (int j = 1; j < GROUP_MAX; ++j)
         if (j < a.nb && b >= a.first_block[j]) k = j;
+    // The batches come longest-running first.  A SIMD runs a wave of the
+    // longest batch next to waves of shorter ones: the longer the batch,
+    // the higher its waves' issue priority, so the long pole runs at close
+    // to its own speed and the short batches fill the cycles it leaves.
     group_run<FROM_START>(a, Group{}, pick(a.slot, k), k, (int64_t)(b - pick(a.first_block, k)), lds);
 }
 
