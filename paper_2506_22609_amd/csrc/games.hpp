@@ -246,14 +246,17 @@ struct Hex {
     {
         return p == 1 ? any(and_mask<RowL, NBITS, NWI>(x)) : any(and_mask<ColL, NBITS, NWI>(x));
     }
-    // p's first / far side as masks of cells
-    __device__ static M first_mask(int p)
+    // first_side / meets_far_side for a per-lane player (p1: player 1)
+    // without a branch on it: both sides' tests, then a select
+    __device__ static M first_side_sel(const M &x, bool p1)
     {
-        return pick(p == 1, const_mask<Row0, NBITS, NWI>(), const_mask<Col0, NBITS, NWI>());
+        return pick(p1, and_mask<Row0, NBITS, NWI>(x), and_mask<Col0, NBITS, NWI>(x));
     }
-    __device__ static M far_mask(int p)
+    __device__ static bool meets_far_side_sel(const M &x, bool p1)
     {
-        return pick(p == 1, const_mask<RowL, NBITS, NWI>(), const_mask<ColL, NBITS, NWI>());
+        const bool row = any(and_mask<RowL, NBITS, NWI>(x));
+        const bool col = any(and_mask<ColL, NBITS, NWI>(x));
+        return (p1 & row) | (!p1 & col);
     }
     // do p's stones `x` join p's two sides?
     __device__ static bool joins(const M &x, int p)
@@ -303,15 +306,15 @@ struct Hex {
         }
     }
 
-    // flood_to_far with the far side given as a mask (far_mask): the same
-    // rounds without a branch on the player, for lanes of both players
-    __device__ static bool flood_to_far_m(M &r, const M &allowed, const M &far)
+    // flood_to_far for a per-lane player (p1: player 1): the same rounds
+    // without a branch on the player
+    __device__ static bool flood_to_far_sel(M &r, const M &allowed, bool p1)
     {
         for (;;) {
             const M n1 = dilate(r) & allowed;
             const M n2 = dilate(n1) & allowed;
             r = n2;
-            const bool hit = any(n2 & far);
+            const bool hit = meets_far_side_sel(n2, p1);
             if (hit | same(n2, n1)) return hit;
         }
     }

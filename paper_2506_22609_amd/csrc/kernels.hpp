@@ -1025,9 +1025,9 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
         const int jw0 = W == me0 ? 0 : 1;          // W's first ply in the window
         const int MW = W ? (T - jw0 + 1) >> 1 : 0; // W's moves in the window
         if (MW > 0) {
-            const M first = G::first_mask(W), far = G::far_mask(W);
-            M s_lo = pick(W == 1, b1, b2); // W's stones before its lo-th window move
-            M r_lo = G::flood(s_lo & first, s_lo);
+            const bool w1 = W == 1;
+            M s_lo = pick(w1, b1, b2); // W's stones before its lo-th window move
+            M r_lo = G::flood(G::first_side_sel(s_lo, w1), s_lo);
             int lo = 1, hi = MW, next = 1; // next = first move not yet in s_lo
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -1043,8 +1043,8 @@ __device__ __forceinline__ Window<G> play_window(const typename G::M &b1, const 
                     });
                     static_for<4>([&](auto I) { s = s | onehot<NW>(c[I]); });
                 }
-                M r = r_lo | (s & first);
-                if (G::flood_to_far_m(r, s, far)) {
+                M r = r_lo | G::first_side_sel(s, w1);
+                if (G::flood_to_far_sel(r, s, w1)) {
                     hi = mid;
                 } else {
                     lo = mid + 1;
