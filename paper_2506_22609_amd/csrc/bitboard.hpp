@@ -251,21 +251,32 @@ __device__ __forceinline__ uint32_t test_bit(const BB<NW> &x, int b)
     return (w >> (b & 31)) & 1u;
 }
 
+// All ones when x < 0, else zero, as a byte permute in which every byte
+// takes the sign of x's top byte: a select on it is a bit-field insert,
+// where a compare would write a scalar lane mask that the select reading it
+// waits a few cycles for.
+__device__ __forceinline__ int sign_mask(int x)
+{
+    return (int)__builtin_amdgcn_perm(0u, (uint32_t)x, 0x09090909u);
+}
+
 // Position of the k-th (from 0) set bit of a 32-bit word; k < popcount(w).
+// Binary search over halves with the position as a bit offset into the
+// unshifted word: the lower half of the current window [off, off + 2s)
+// holds c set bits; when k >= c the bit is in the upper half.  The
+// "k >= c" choice is taken from the sign of k - c (sign_mask).
 __device__ __forceinline__ int select_in_word(uint32_t w, int k)
 {
-    int pos = 0;
-    int c = __popc(w & 0xFFFFu);
-    if (k >= c) { k -= c; w >>= 16; pos += 16; }
-    c = __popc(w & 0xFFu);
-    if (k >= c) { k -= c; w >>= 8; pos += 8; }
-    c = __popc(w & 0xFu);
-    if (k >= c) { k -= c; w >>= 4; pos += 4; }
-    c = __popc(w & 0x3u);
-    if (k >= c) { k -= c; w >>= 2; pos += 2; }
-    c = (int)(w & 1u);
-    if (k >= c) pos += 1;
-    return pos;
+    int off = 0;
+#pragma unroll
+    for (int s = 16; s >= 1; s >>= 1) {
+        const int c = __popc(__builtin_amdgcn_ubfe(w, (unsigned)off, (unsigned)s));
+        const int d = k - c;
+        const int lower = sign_mask(d);
+        k = (lower & k) | (~lower & d);
+        off |= ~lower & s;
+    }
+    return off;
 }
 
 // Index of the k-th (from 0) set bit in increasing bit order; k < popcount(m).
