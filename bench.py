@@ -46,14 +46,14 @@ sys.path.insert(0, ROOT)
 # batches (env-steps of both).  Peak: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz = 39.3 T lane-ops/s (the fp64 vector rate 78.6 TFLOP/s counts an
 # FMA as two operations).
-VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 264, "hex11x11_n65536": 171, "group": 183}
+VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 239, "hex11x11_n65536": 158, "group": 170}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # HBM bytes of one launch of the dominant kernel: FETCH_SIZE and WRITE_SIZE
 # scaled by a 1 GiB device copy in the same profiled run
-# (profiles/playout_c4_hex11_n65536_hbm_bytes.txt): 0.42 MB read (no state:
+# (profiles/playout_c4_hex11_n65536_hbm_bytes.txt): 0.41 MB read (no state:
 # the kernel resets the envs itself) and 12.12 MB written (the final
 # states, exactly their algorithmic bytes).
-GROUP_TRAFFIC_BYTES = 12.55e6
+GROUP_TRAFFIC_BYTES = 12.53e6
 HBM_PEAK_GBS = 8000.0
 EVENT_EVERY = 8
 # What the paper states about its own throughput (Sec. 6, Fig. 2): no
