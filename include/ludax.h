@@ -391,8 +391,10 @@ int ludax_mixed_playout_noalloc(ludax_mixed *mixed, uint64_t seed, int64_t id_ba
  * every kind's fitted time to a common value with the lanes adding up to
  * total_slots (and that plan with the flattest-scaling kind's share moved
  * by +-25 %), each split launched as one grid (where supported) and as a
- * kernel per kind, each timed twice (the better run counts); keeps the
- * fastest split and launch as the handle's plan
+ * kernel per kind, each timed twice (the better run counts); then refines
+ * the fastest split in its launch mode, moving each kind's share by -30 %
+ * and +40 %, then by -15 % and +18 % (a move kept when the batch gets
+ * faster); keeps the result as the handle's plan
  * (ludax_mixed_get_slots and ludax_mixed_get_one_grid read it).  Runs real
  * batches with the given
  * arguments (outputs are overwritten) and SYNCHRONISES the stream.
