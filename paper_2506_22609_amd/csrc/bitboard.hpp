@@ -279,22 +279,63 @@ __device__ __forceinline__ int select_in_word(uint32_t w, int k)
     return off;
 }
 
+// The word holding the k-th (from 0) set bit: its value, index and the
+// count of set bits in the words before it; k < popcount(m).  Up to four
+// words, the last word whose prefix count is <= k, by a chain of selects.
+// Longer boards first pick a group of four words the same way, then the
+// word within the group: about half the selects of one chain over all
+// the words.
+template <int NW>
+__device__ __forceinline__ void select_word(const BB<NW> &m, int k, uint32_t &wsel, int &wi, int &off)
+{
+    if constexpr (NW <= 4) {
+        wsel = m.w[0];
+        wi = 0;
+        off = 0;
+        int pre = __popc(m.w[0]);
+#pragma unroll
+        for (int i = 1; i < NW; ++i) {
+            const bool ge = k >= pre;
+            wsel = ge ? m.w[i] : wsel;
+            wi = ge ? i : wi;
+            off = ge ? pre : off;
+            pre += __popc(m.w[i]);
+        }
+    } else {
+        constexpr int NG = (NW + 3) / 4;
+        BB<4> q;
+        q.w[0] = m.w[0], q.w[1] = m.w[1], q.w[2] = m.w[2], q.w[3] = m.w[3];
+        int g = 0, goff = 0;
+        int gpre = __popc(m.w[0]) + __popc(m.w[1]) + __popc(m.w[2]) + __popc(m.w[3]);
+        static_for<NG - 1>([&](auto I) {
+            constexpr int G = I + 1;
+            const int start = gpre; // set bits before group G
+            const bool ge = k >= start;
+            static_for<4>([&](auto J) {
+                constexpr int j = J;
+                constexpr int i = 4 * G + j;
+                const uint32_t x = i < NW ? m.w[i < NW ? i : 0] : 0u;
+                q.w[j] = ge ? x : q.w[j];
+                if constexpr (G + 1 < NG) gpre += __popc(x);
+            });
+            g = ge ? G : g;
+            goff = ge ? start : goff;
+        });
+        int j;
+        select_word<4>(q, k - goff, wsel, j, off);
+        wi = 4 * g + j;
+        off += goff;
+    }
+}
+
 // Index of the k-th (from 0) set bit in increasing bit order; k < popcount(m).
 template <int NW>
 __device__ __forceinline__ int select_bit(const BB<NW> &m, int k)
 {
-    // prefix popcounts; the last word whose prefix is <= k holds the bit
-    uint32_t wsel = m.w[0];
-    int base = 0, off = 0, pre = __popc(m.w[0]);
-#pragma unroll
-    for (int i = 1; i < NW; ++i) {
-        const bool ge = k >= pre;
-        wsel = ge ? m.w[i] : wsel;
-        base = ge ? 32 * i : base;
-        off = ge ? pre : off;
-        pre += __popc(m.w[i]);
-    }
-    return base + select_in_word(wsel, k - off);
+    uint32_t wsel;
+    int wi, off;
+    select_word(m, k, wsel, wi, off);
+    return 32 * wi + select_in_word(wsel, k - off);
 }
 
 // The same search returning the word index of the k-th set bit and that bit
@@ -302,17 +343,9 @@ __device__ __forceinline__ int select_bit(const BB<NW> &m, int k)
 template <int NW>
 __device__ __forceinline__ void select_bit_split(const BB<NW> &m, int k, int &word, uint32_t &bit)
 {
-    uint32_t wsel = m.w[0];
-    int wi = 0, off = 0, pre = __popc(m.w[0]);
-#pragma unroll
-    for (int i = 1; i < NW; ++i) {
-        const bool ge = k >= pre;
-        wsel = ge ? m.w[i] : wsel;
-        wi = ge ? i : wi;
-        off = ge ? pre : off;
-        pre += __popc(m.w[i]);
-    }
-    word = wi;
+    uint32_t wsel;
+    int off;
+    select_word(m, k, wsel, word, off);
     bit = 1u << select_in_word(wsel, k - off);
 }
 

@@ -500,15 +500,30 @@ struct Gomoku {
         return exact_five<1>(x, h) | exact_five<S>(x, v) | exact_five<S - 1>(x, d1) | exact_five<S + 1>(x, d2);
     }
 
+    // place player me's stone on cell b: me's win, else a draw when `full`
+    // (the board is full after this stone), else -1.  The stone's word is
+    // picked by word masks, per player (no select between whole boards).
+    __device__ int place_full(int b, int me, bool full)
+    {
+        const uint32_t bit = 1u << (b & 31);
+        const int sel = word_sel(b >> 5);
+        const int s1 = me == 1 ? sel : 0, s2 = sel ^ s1;
+#pragma unroll
+        for (int i = 0; i < NWI; ++i) {
+            p1.w[i] |= bit & word_mask(s1, i);
+            p2.w[i] |= bit & word_mask(s2, i);
+        }
+        if (any_exact_five(pick(me == 1, p1, p2))) return me;
+        return full ? 0 : -1;
+    }
     __device__ int place(int b, int me, int &extra)
     {
-        M own = pick(me == 1, p1, p2) | onehot<NWI>(b);
-        p1 = pick(me == 1, own, p1);
-        p2 = pick(me == 1, p2, own);
-        if (any_exact_five(own)) return me;
-        if (popcount(p1 | p2) == CELLS) return 0;
-        return -1;
+        const int r = place_full(b, me, false);
+        if (r >= 0) return r;
+        return popcount(p1 | p2) == CELLS ? 0 : -1;
     }
+    // a random ply knows the number of empty cells before its stone
+    __device__ int place_drawn(int b, int me, int &extra, int n_legal) { return place_full(b, me, n_legal == 1); }
     __device__ int place_step(int b, int me, int &extra) { return place(b, me, extra); }
     __device__ int pass(int &) { return -1; }
 };

@@ -698,7 +698,8 @@ __device__ __forceinline__ bool random_ply(G &g, int &me, int &passes, int &ply,
     } else {
         const int b = select_bit(m, k);
         a = G::action_of(b);
-        outcome = g.place(b, me, passes);
+        if constexpr (G::KIND == 5) outcome = g.place_drawn(b, me, passes, np); // Gomoku: np empty cells
+        else outcome = g.place(b, me, passes);
     }
     ply += 1;
     last = a;
