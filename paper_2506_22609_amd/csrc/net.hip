@@ -1499,6 +1499,10 @@ __global__ __launch_bounds__(LdsR<N>::THREADS, 1) void k_conv_res(const uint16_t
                 if ((vmask >> mt) & 1u) {
                     sv += lv;
                     if (quad == 0) {
+                        // at most two partials per cell onto a zeroed slot: the
+                        // first lands exactly and float addition commutes, so
+                        // the sum does not depend on which wave adds first
+                        static_assert(L::NSPLIT <= 2, "order-independent policy sums");
                         const int r = cell_off[mt] / NP, c = cell_off[mt] % NP;
                         atomicAdd(&hl[slot * L::PIX + r * N + c], lp);
                     }

@@ -97,6 +97,24 @@ def test_forward_bench_scale_sampled(N, n):
     close(value.cpu().numpy()[idx], f["value"])
 
 
+@pytest.mark.parametrize("N,n", [(11, 1030), (19, 700)])
+def test_forward_is_reproducible(N, n):
+    """The forward is bit-identical run after run, and a board's outputs do
+    not depend on where it sits in the batch or on the other boards of its
+    block (at 19x19 two waves add a cell's policy partials with LDS atomics,
+    and a board's value partials come from six waves)."""
+    rng = np.random.default_rng(7 + N)
+    board = torch.from_numpy(rng.integers(0, 3, size=(n, N * N), dtype=np.int8)).cuda()
+    to_move = torch.from_numpy(rng.integers(1, 3, size=n, dtype=np.int8)).cuda()
+    net, _ = _net(N, 13)
+    l1, v1 = net.forward(board, to_move)
+    l2, v2 = net.forward(board, to_move)
+    assert torch.equal(l1, l2) and torch.equal(v1, v2)
+    perm = torch.from_numpy(rng.permutation(n)[: n - 7]).cuda()
+    l3, v3 = net.forward(board[perm].contiguous(), to_move[perm].contiguous())
+    assert torch.equal(l3, l1[perm]) and torch.equal(v3, v1[perm])
+
+
 def _running_batch(kind, N, n, seed):
     """n RUNNING positions (reachable mid-game states), a legal move of each
     and an outcome for its mover."""
