@@ -383,14 +383,40 @@ struct Reversi {
         else return andnot_mask<Col7, 64, 2>(shr<9>(x));
     }
 
-    // cells from which a disc of `own` flanks a run of `opp` along D
-    template <int D>
-    __device__ static M moves_along(const M &own, const M &opp, const M &empty)
+    template <int D, int K>
+    __device__ static M shift_k(const M &x)
     {
-        M x = step<D>(own) & opp;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) x = x | (step<D>(x) & opp);
-        return step<D>(x) & empty;
+        // K steps along D at once: the shift amount times K
+        if constexpr (D == 0) return shl<K>(x);
+        else if constexpr (D == 1) return shr<K>(x);
+        else if constexpr (D == 2) return shl<8 * K>(x);
+        else if constexpr (D == 3) return shr<8 * K>(x);
+        else if constexpr (D == 4) return shl<9 * K>(x);
+        else if constexpr (D == 5) return shl<7 * K>(x);
+        else if constexpr (D == 6) return shr<7 * K>(x);
+        else return shr<9 * K>(x);
+    }
+    // the cells where a step along D may land (a step that wraps around a
+    // row edge lands in the first or the last column)
+    template <int D>
+    __device__ static M landing(const M &x)
+    {
+        if constexpr (D == 0 || D == 4 || D == 6) return andnot_mask<Col0, 64, 2>(x);
+        else if constexpr (D == 1 || D == 5 || D == 7) return andnot_mask<Col7, 64, 2>(x);
+        else return x;
+    }
+
+    // `gen` extended along D over the cells of `pro` (already restricted to
+    // landing cells) by doubling steps: runs of up to seven cells, three
+    // shifts of the growing set and two of the propagator
+    template <int D>
+    __device__ static M fill(M gen, M pro)
+    {
+        gen = gen | (pro & shift_k<D, 1>(gen));
+        pro = pro & shift_k<D, 1>(pro);
+        gen = gen | (pro & shift_k<D, 2>(gen));
+        pro = pro & shift_k<D, 2>(pro);
+        return gen | (pro & shift_k<D, 4>(gen));
     }
 
     __device__ M placements(int me) const
@@ -404,19 +430,10 @@ struct Reversi {
         M m = bb_zero<2>();
         static_for<8>([&](auto Dc) {
             constexpr int D = Dc;
-            m = m | moves_along<D>(own, opp, empty);
+            const M run = andnot(fill<D>(own, landing<D>(opp)), own); // opponent's discs reached
+            m = m | (shift_k<D, 1>(run) & landing<D>(empty));
         });
         return m;
-    }
-
-    // opponent discs flipped along D by a disc placed at s
-    template <int D>
-    __device__ static M flips_along(const M &s, const M &own, const M &opp)
-    {
-        M run = step<D>(s) & opp;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) run = run | (step<D>(run) & opp);
-        return any(step<D>(run) & own) ? run : bb_zero<2>();
     }
 
     __device__ int place(int b, int me, int &extra)
@@ -424,10 +441,14 @@ struct Reversi {
         const M s = onehot<2>(b);
         M own = pick(me == 1, p1, p2);
         M opp = pick(me == 1, p2, p1);
+        // opponent discs flipped along D: the run of them from s, when a
+        // disc of the mover closes it
         M f = bb_zero<2>();
         static_for<8>([&](auto Dc) {
             constexpr int D = Dc;
-            f = f | flips_along<D>(s, own, opp);
+            const M run = fill<D>(s, landing<D>(opp)); // s and the run after it
+            const bool closed = any(shift_k<D, 1>(run) & landing<D>(own));
+            f = f | (closed ? andnot(run, s) : bb_zero<2>());
         });
         own = own | f | s;
         opp = andnot(opp, f);
