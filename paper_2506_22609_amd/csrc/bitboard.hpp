@@ -214,6 +214,102 @@ __device__ __forceinline__ BB<NW> shift(const BB<NW> &x)
     else return shr<-S>(x);
 }
 
+// All ones when x < 0, else zero, as a byte permute in which every byte
+// takes the sign of x's top byte: a select on it is a bit-field insert,
+// where a compare would write a scalar lane mask that the select reading it
+// waits a few cycles for.
+__device__ __forceinline__ int sign_mask(int x)
+{
+    return (int)__builtin_amdgcn_perm(0u, (uint32_t)x, 0x09090909u);
+}
+
+// A 128-bit view of a bitboard around a per-lane cell b: v bit (64 + o) is
+// x bit (b + o) for every offset o in [-64, 64), zero off the board.  The
+// five words q - 2 .. q + 2 (q = b / 32) are picked by a barrel shift over
+// q's bits (a few selects per stage instead of a select chain per word),
+// then funnel-shifted by b mod 32.  Tests at constant offsets from b then
+// read constant bit positions of the view.
+template <int NW>
+__device__ __forceinline__ void view128(const BB<NW> &x, int b, uint32_t (&v)[4])
+{
+    static_assert(NW <= 16, "q fits four selector bits");
+    const int q = b >> 5, off = b & 31;
+    // y[i] = x word i - 2, zero outside the board
+    uint32_t y[20];
+    static_for<20>([&](auto I) {
+        constexpr int i = I;
+        y[i] = (i >= 2 && i - 2 < NW) ? x.w[(i >= 2 && i - 2 < NW) ? i - 2 : 0] : 0u;
+    });
+    // y[j] <- y[j + step] where q has the step's bit, for the entries the
+    // later stages read.  The choice is a bit-field insert under an opaque
+    // all-ones mask: as selects on q the stages are recognised as an
+    // indexed read and the words go to private memory.
+    auto stage = [&](auto STEP, auto KEEP) {
+        constexpr int step = STEP, keep = KEEP;
+        const uint32_t on = (uint32_t)sign_mask(q << (31 - __builtin_ctz(step)));
+        static_for<keep>([&](auto J) {
+            constexpr int j = J;
+            y[j] = (on & y[j + step]) | (~on & y[j]);
+        });
+    };
+    if constexpr (NW > 8) stage(std::integral_constant<int, 8>{}, std::integral_constant<int, 12>{});
+    if constexpr (NW > 4) stage(std::integral_constant<int, 4>{}, std::integral_constant<int, 8>{});
+    if constexpr (NW > 2) stage(std::integral_constant<int, 2>{}, std::integral_constant<int, 6>{});
+    if constexpr (NW > 1) stage(std::integral_constant<int, 1>{}, std::integral_constant<int, 5>{});
+    static_for<4>([&](auto J) {
+        constexpr int j = J;
+        v[j] = __builtin_amdgcn_alignbit(y[j + 1], y[j], (unsigned)off);
+    });
+}
+
+// bit 64 + O of a view: x bit (b + O)
+template <int O>
+__device__ __forceinline__ uint32_t view_bit(const uint32_t (&v)[4])
+{
+    static_assert(O >= -64 && O < 64, "offset inside the view");
+    constexpr int p = 64 + O;
+    return (v[p >> 5] >> (p & 31)) & 1u;
+}
+
+// The inverse of view128: the board whose bit b + o is view bit 64 + o
+// (offsets that fall off the board are dropped).
+template <int NW>
+__device__ __forceinline__ BB<NW> unview128(const uint32_t (&c)[4], int b)
+{
+    const int q = b >> 5, off = b & 31;
+    // the view shifted up by b mod 32: window words 0..4 (window word j is
+    // board word q - 2 + j); funnel shifts, b mod 32 = 0 taking the words
+    // as they are
+    uint32_t t[20];
+    static_for<20>([&](auto I) { t[(int)I] = 0u; });
+    const unsigned back = (unsigned)(32 - off) & 31u;
+    t[0] = c[0] << off;
+    static_for<3>([&](auto J) {
+        constexpr int j = J + 1;
+        t[j] = off == 0 ? c[j] : __builtin_amdgcn_alignbit(c[j], c[j - 1], back);
+    });
+    t[4] = off == 0 ? 0u : __builtin_amdgcn_alignbit(0u, c[3], back);
+    // window word j to board word q - 2 + j: t[k] <- t[k - step] where q has
+    // the step's bit (t index k is board word k - 2)
+    auto stage = [&](auto STEP, auto TOP) {
+        constexpr int step = STEP, top = TOP;
+        const uint32_t on = (uint32_t)sign_mask(q << (31 - __builtin_ctz(step)));
+        static_for<top>([&](auto K) {
+            constexpr int k = top - 1 - K; // from the top down: reads the unshifted entries
+            const uint32_t below = k >= step ? t[k >= step ? k - step : 0] : 0u;
+            t[k] = (on & below) | (~on & t[k]);
+        });
+    };
+    constexpr int TOPN = NW + 2 < 20 ? NW + 2 : 20;
+    if constexpr (NW > 1) stage(std::integral_constant<int, 1>{}, std::integral_constant<int, (6 < TOPN ? 6 : TOPN)>{});
+    if constexpr (NW > 2) stage(std::integral_constant<int, 2>{}, std::integral_constant<int, (8 < TOPN ? 8 : TOPN)>{});
+    if constexpr (NW > 4) stage(std::integral_constant<int, 4>{}, std::integral_constant<int, (12 < TOPN ? 12 : TOPN)>{});
+    if constexpr (NW > 8) stage(std::integral_constant<int, 8>{}, std::integral_constant<int, TOPN>{});
+    BB<NW> r;
+    static_for<NW>([&](auto I) { r.w[(int)I] = t[(int)I + 2]; });
+    return r;
+}
+
 // Word i of a bitboard picked by a per-lane word index q without a compare
 // (whose lane mask in a scalar register costs wait states before the
 // select that reads it): sel = word_sel(q) has bit q set, and
@@ -249,15 +345,6 @@ __device__ __forceinline__ uint32_t test_bit(const BB<NW> &x, int b)
 #pragma unroll
     for (int i = 0; i < NW; ++i) w |= x.w[i] & (0u - (uint32_t)(q == i));
     return (w >> (b & 31)) & 1u;
-}
-
-// All ones when x < 0, else zero, as a byte permute in which every byte
-// takes the sign of x's top byte: a select on it is a bit-field insert,
-// where a compare would write a scalar lane mask that the select reading it
-// waits a few cycles for.
-__device__ __forceinline__ int sign_mask(int x)
-{
-    return (int)__builtin_amdgcn_perm(0u, (uint32_t)x, 0x09090909u);
 }
 
 // Position of the k-th (from 0) set bit of a 32-bit word; k < popcount(w).

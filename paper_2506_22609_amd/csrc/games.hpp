@@ -689,13 +689,22 @@ struct Pente {
         return pick(any(occ), and_mask<Valid, NBITS, NWI>(~occ), onehot<NWI>(CENTRE));
     }
 
-    // the new stone s brackets two opponent stones along step D
+    // the new stone at b brackets two opponent stones along step D: read
+    // from the views of the mover's and the opponent's stones around b; a
+    // capture marks the two cells in the view of captured stones
     template <int D>
-    __device__ static bool brackets(const M &s, const M &own, const M &opp, M &cap)
+    __device__ __forceinline__ static uint32_t brackets(const uint32_t (&vo)[4], const uint32_t (&vp)[4],
+                                                        uint32_t &c0, uint32_t &c1, uint32_t &c2, uint32_t &c3)
     {
-        const M a = shift<D>(s) & opp, b = shift<2 * D>(s) & opp;
-        const bool hit = any(a) & any(b) & any(shift<3 * D>(s) & own);
-        cap = pick(hit, cap | a | b, cap);
+        const uint32_t hit = view_bit<D>(vp) & view_bit<2 * D>(vp) & view_bit<3 * D>(vo);
+        constexpr int p1 = 64 + D, p2 = 64 + 2 * D;
+        static_assert(p1 >= 0 && p2 >= 0 && p1 < 128 && p2 < 128, "inside the view");
+        const uint32_t m1 = hit << (p1 & 31), m2 = hit << (p2 & 31);
+        // the capture view's words as separate scalars (no indexed array)
+        if constexpr ((p1 >> 5) == 0) c0 |= m1; else if constexpr ((p1 >> 5) == 1) c1 |= m1;
+        else if constexpr ((p1 >> 5) == 2) c2 |= m1; else c3 |= m1;
+        if constexpr ((p2 >> 5) == 0) c0 |= m2; else if constexpr ((p2 >> 5) == 1) c1 |= m2;
+        else if constexpr ((p2 >> 5) == 2) c2 |= m2; else c3 |= m2;
         return hit;
     }
     // starts of runs of five or more along step K
@@ -712,17 +721,27 @@ struct Pente {
         const M s = onehot<NWI>(b);
         const M own = pick(me == 1, p1, p2) | s;
         M opp = pick(me == 1, p2, p1);
-        M cap = bb_zero<NWI>();
+        // the captures: the cells within three steps of b in the eight
+        // directions, read from 128-bit views of both players' stones
+        // around b (three steps span at most 3 (S + 1) <= 63 bits)
+        static_assert(3 * (S + 1) < 64, "captures inside the view");
+        uint32_t vo[4], vp[4];
+        view128(own, b, vo);
+        view128(opp, b, vp);
+        uint32_t c0 = 0u, c1 = 0u, c2 = 0u, c3 = 0u;
         int pairs = 0;
-        pairs += brackets<1>(s, own, opp, cap);
-        pairs += brackets<-1>(s, own, opp, cap);
-        pairs += brackets<S>(s, own, opp, cap);
-        pairs += brackets<-S>(s, own, opp, cap);
-        pairs += brackets<S + 1>(s, own, opp, cap);
-        pairs += brackets<-(S + 1)>(s, own, opp, cap);
-        pairs += brackets<S - 1>(s, own, opp, cap);
-        pairs += brackets<-(S - 1)>(s, own, opp, cap);
-        opp = andnot(opp, cap);
+        pairs += brackets<1>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<-1>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<S>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<-S>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<S + 1>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<-(S + 1)>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<S - 1>(vo, vp, c0, c1, c2, c3);
+        pairs += brackets<-(S - 1)>(vo, vp, c0, c1, c2, c3);
+        if (__any(pairs != 0)) {
+            const uint32_t cv[4] = {c0, c1, c2, c3};
+            opp = andnot(opp, unview128<NWI>(cv, b));
+        }
         p1 = pick(me == 1, own, opp);
         p2 = pick(me == 1, opp, own);
         int lo = extra & 15, hi = (extra >> 4) & 15;
