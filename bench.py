@@ -1042,7 +1042,7 @@ def main():
     if "mixed" in sec:
         out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
     if "plain_step" in sec:
-        cases = [(b, False) for b in batches]
+        cases = [(b, False) for b in batches] + [(W.HEX11_65536, True)]
         if "large" in sec:
             cases += [(b, False) for b in W.LARGE_BATCHES] + [(W.HEX19_524288, True), (W.HEX19_1M, False),
                                                             (W.HEX19_1M, True)]
