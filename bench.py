@@ -572,6 +572,51 @@ def _large_mixed_section(seed: int, reps: int, train_steps: int, budget_gb: floa
     return res
 
 
+def _sweep_section(seed: int, reps: int):
+    """Throughput against batch size (Sec. 6, Fig. 2): for each of the
+    ten games of the paper's figure and batch sizes 2^10 .. 2^20, full-game
+    episodes from the start position (ludax_init + ludax_playout, the
+    movement games capped at 200 plies), two warm-up batches, then `reps`
+    timed batches with fresh game ids, each bracketed by events; the median
+    time and the mean env-steps of the timed batches (counted outside the
+    timed region) give env-steps/s."""
+    import torch
+    from paper_2506_22609_amd import ludax
+    from paper_2506_22609_amd import workloads as W
+
+    out = {}
+    for b in W.SWEEP_GAMES:
+        g = ludax.Game(b.kind, b.rows, b.cols)
+        row = {}
+        for n in W.SWEEP_SIZES:
+            s = ludax.State(g, n)
+            r = torch.empty((n, 2), dtype=torch.int8, device="cuda")
+            t = torch.empty(n, dtype=torch.uint8, device="cuda")
+            st = torch.zeros(4, dtype=torch.int64, device="cuda")
+            for k in range(2):
+                ludax.init(g, s)
+                ludax.playout(g, s, seed, k * n, reward=r, terminal=t, stats=None)
+            torch.cuda.synchronize()
+            ms = []
+            for k in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ludax.init(g, s)
+                ludax.playout(g, s, seed, (k + 2) * n, reward=r, terminal=t, stats=None)
+                e1.record()
+                ludax.state_stats(g, s, +1, st)
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            steps = int(st[0].item()) / reps  # env-steps of one batch (the mean over the timed ones)
+            ms.sort()
+            med = ms[len(ms) // 2]
+            row[str(n)] = {"ms_per_batch": med, "min_ms": ms[0], "max_ms": ms[-1],
+                           "env_steps_per_s": steps / (med / 1e3), "mean_plies": steps / n}
+            del s, r, t
+        out[b.name] = row
+    return out
+
+
 def _more_games_section(seed: int, reps: int):
     """Plain fused playouts of the paper's other games, 65536 envs each:
     Yavalath on the diameter-9 hexagon, Pente 19x19, and the movement games
@@ -898,7 +943,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-time budget of the CPU oracle baseline (0 = skip)")
     ap.add_argument("--sections", default="mixed,plain_step,large,more_games,learned,large_mixed",
-                    help="comma-separated extra sections to run after the headline steps")
+                    help="comma-separated extra sections to run after the headline steps "
+                         "(also: sweep, throughput against batch size for the paper's ten games)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the mixed persistent batch section")
     ap.add_argument("--mixed-steps", type=int, default=5)
@@ -1041,6 +1087,8 @@ def main():
         sec -= {"learned", "large_mixed"}
     if "mixed" in sec:
         out["mixed"] = _mixed_section(args.seed, args.mixed_steps, 1)
+    if "sweep" in sec:
+        out["sweep"] = _sweep_section(args.seed, args.section_reps)
     if "plain_step" in sec:
         cases = [(b, False) for b in batches] + [(W.HEX11_65536, True)]
         if "large" in sec:

@@ -42,6 +42,16 @@ DRAUGHTS_65536 = Batch("draughts8x8_n65536", DRAUGHTS, 8, 8, 65536)
 HASAMI_SHOGI_65536 = Batch("hasami_shogi9x9_n65536", HASAMI_SHOGI, 9, 9, 65536)
 MORE_GAMES = (YAVALATH9_65536, PENTE19_65536, WOLF_SHEEP_65536, DRAUGHTS_65536, HASAMI_SHOGI_65536)
 
+# the batch-size sweep of the paper's throughput figure (Sec. 6, Fig. 2:
+# moves per second against batch size under uniform-random play): its ten
+# games at batch sizes 2^10 .. 2^20
+SWEEP_GAMES = (Batch("tictactoe3x3", TICTACTOE, 3, 3, 0), Batch("connect4_6x7", CONNECT_FOUR, 6, 7, 0),
+               Batch("hex11x11", HEX, 11, 11, 0), Batch("reversi8x8", REVERSI, 8, 8, 0),
+               Batch("gomoku15x15", GOMOKU, 15, 15, 0), Batch("yavalath9", YAVALATH, 9, 9, 0),
+               Batch("pente19x19", PENTE, 19, 19, 0), Batch("wolf_sheep8x8", WOLF_SHEEP, 8, 8, 0),
+               Batch("draughts8x8", DRAUGHTS, 8, 8, 0), Batch("hasami_shogi9x9", HASAMI_SHOGI, 9, 9, 0))
+SWEEP_SIZES = (1024, 4096, 16384, 65536, 262144, 1048576)
+
 # large boards: Hex 19x19 and Gomoku 19x19, 524288 envs each (1,048,576
 # envs, 378.5 MB of int8 boards)
 HEX19_524288 = Batch("hex19x19_n524288", HEX, 19, 19, 524288)
