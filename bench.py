@@ -48,6 +48,9 @@ sys.path.insert(0, ROOT)
 # FMA as two operations).
 VALU_OPS_PER_STEP = {"connect4_6x7_n65536": 239, "hex11x11_n65536": 158, "group": 170}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# the same count for the mixed persistent batch's one-grid kernel
+# (k_persist_group over 4 x 262144 games, same profile)
+MIXED_VALU_OPS_PER_STEP = 320
 # HBM bytes of one launch of the dominant kernel: FETCH_SIZE and WRITE_SIZE
 # scaled by a 1 GiB device copy in the same profiled run
 # (profiles/playout_c4_hex11_n65536_hbm_bytes.txt): 0.41 MB read (no state:
@@ -301,6 +304,9 @@ def _mixed_section(seed: int, steps: int, warmup: int):
         "slots_per_kind": m.slots, "one_grid": m.one_grid, "autotuned_ms": tune_ms, "equal_split_ms": equal_ms,
         "mixed_graph_env_steps_per_s": g_steps / g_el,
         "mixed_graph_ms_per_batch": g_el / steps * 1e3,
+        # VALU lane-ops per env-step (measured, one grid) x env-steps / time
+        "valu_frac_graph": (MIXED_VALU_OPS_PER_STEP * g_steps / g_el / 1e12 / VALU_PEAK_TOPS
+                            if m.one_grid else None),
         "mixed_eager_env_steps_per_s": e_steps / e_el,
         "plain_env_steps_per_s": p_steps / p_el,
         "plain_ms_per_batch": p_el / steps * 1e3,
@@ -859,7 +865,8 @@ def _hbm_probe(seed: int):
     """A short fixed sequence for hardware-counter runs (rocprofv3 --pmc):
     one plain device copy of 1 GiB (the known-size reference of the byte
     counters), one headline step (Connect Four and Hex 11x11 playouts of
-    65536 envs), and the per-ply loop over 1,048,576 Hex 19x19 envs (361
+    65536 envs), one mixed persistent batch (4 x 262144 game ids, equal
+    split, one grid), and the per-ply loop over 1,048,576 Hex 19x19 envs (361
     ludax_random_step launches) without and then with the component cache.
     Prints the env-steps of each part, which the counters are divided by."""
     import torch
@@ -887,6 +894,19 @@ def _hbm_probe(seed: int):
                                  for g, s in zip(games, states)], seed, from_start=True)
     out["group"] = {"env_steps": int(sum(r[2][0].item() for r in res))}
     del states, res
+    # the mixed persistent batch (4 x 262144 game ids, equal slot split, one
+    # grid): its kernel's instructions per env-step
+    mb = W.MIXED4
+    mgames = [ludax.Game(k.kind, k.rows, k.cols) for k in mb.kinds]
+    mx = ludax.Mixed(mgames)
+    mx.slots = [mb.slots // len(mgames) // 64 * 64] * len(mgames)
+    mx.one_grid = True
+    mres = ludax.MixedResult(mb.n_games, len(mgames))
+    mst = torch.zeros((len(mgames), 4), dtype=torch.int64, device="cuda")
+    mx.playout(seed, 0, mb.n_games, out=mres, stats=mst)
+    torch.cuda.synchronize()
+    out["mixed4"] = {"env_steps": int(mst[:, 0].sum().item()), "slots": mx.slots}
+    del mx, mres
     b = W.HEX19_1M
     g = ludax.Game(b.kind, b.rows, b.cols)
     for aux in (False, True):
