@@ -430,7 +430,8 @@ def _plain_step_section(cases, seed: int, reps: int):
 
 def _large_section(batches, seed: int, reps: int):
     """Plain fused playouts (ludax_init + ludax_playout) of the large
-    single-game batches, the playout kernel timed with events."""
+    single-game batches, the playout kernel timed with events; and the
+    same games through a one-kind persistent batch (refill)."""
     import torch
     from paper_2506_22609_amd import ludax
 
@@ -465,6 +466,31 @@ def _large_section(batches, seed: int, reps: int):
                        "mean_plies": v[0] / reps / b.n,
                        "p1_wins": v[1], "p2_wins": v[2], "draws": v[3]}
         del s
+        torch.cuda.synchronize()
+        # the same games through the persistent batch of this one kind
+        # (ludax_mixed_*): 262144 lanes, a lane refilled as soon as its game
+        # ends instead of waiting for the longest game of its wave; per-game
+        # outputs (winner, plies, last action) instead of the final states
+        m = ludax.Mixed([g])
+        m.slots = [262144]
+        res = ludax.MixedResult(b.n, 1)
+        mst = torch.zeros((1, 4), dtype=torch.int64, device="cuda")
+        m.playout(seed, 0, b.n, out=res, stats=None)
+        torch.cuda.synchronize()
+        ms = []
+        for k in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            m.playout(seed, (k + 1) * b.n, b.n, out=res, stats=mst)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        ms.sort()
+        med = ms[len(ms) // 2]
+        psteps = int(mst[0, 0].item()) / reps
+        out[b.name]["persistent"] = {"slots": 262144, "one_grid": m.one_grid, "ms_per_batch": med,
+                                     "env_steps_per_s": psteps / (med / 1e3), "playouts_per_s": b.n / (med / 1e3)}
+        del m, res
         torch.cuda.synchronize()
     return out
 
