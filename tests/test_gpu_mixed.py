@@ -100,6 +100,25 @@ def test_mixed_single_kind_equals_plain_playout():
     assert torch.equal(stats[0], pst)
 
 
+@pytest.mark.parametrize("kind", [ref.HEX, ref.GOMOKU], ids=["hex19", "gomoku19"])
+def test_mixed_single_kind_large_equals_plain_playout(kind):
+    """The one-kind persistent batch as the large-board benchmark launches it
+    (524288 games of a 19x19 game through 262144 refilled slots) gives every
+    game the outcome, length and last action of the plain fused playout."""
+    g = ludax.Game(kind, 19, 19)
+    n = 524288
+    m = ludax.Mixed([g])
+    m.slots = [262144]
+    out, stats = m.playout(5, 7 * n, n)
+    d = ludax.State(g, n)
+    ludax.init(g, d)
+    _, _, pst = ludax.playout(g, d, 5, 7 * n)
+    w = torch.where(d.status == ref.TERMINAL, d.winner, torch.full_like(d.winner, -1))
+    assert torch.equal(out.winner, w) and torch.equal(out.plies, d.ply)
+    assert torch.equal(out.last_action, d.last_action)
+    assert torch.equal(stats[0], pst)
+
+
 @pytest.mark.parametrize("one_grid", [True, False], ids=["one_grid", "streams"])
 def test_mixed_graph_replay(one_grid):
     """The whole call (counter reset, the kinds' kernels -- one grid, or
